@@ -1,0 +1,413 @@
+"""FP64 CPU oracle for ViPer NL-COMM vector-perturbation precoding.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call,
+link or execute anything in this directory; only the test-suite, the smoke
+check and the CPU-baseline leg of the benchmark do.  It shares no code,
+tables or constants with the HIP path.
+
+Every function is a plain, slow, obviously-correct restatement of the paper
+(Thomas, Katsaros, Jayawardena, Nikitopoulos, "ViPer NL-COMM: Making Vector
+Perturbation Precoding Practical", arXiv 2602.12098), in complex128 / float64.
+Citations name the section, equation label or algorithm.
+
+Notation (search order = level order of the tree; level 0 is the root):
+  A       = H H^H + alpha I                        (RZF Gram matrix, Sec. II-A / III-A-1)
+  pi      : level -> user permutation              (the sorting P-bar of Alg. 1)
+  Lbar    : lower-triangular, A[pi][:,pi] = Lbar Lbar^H   (Rbar of Alg. 1)
+  W       = Lbar^{-1} (lower-triangular)           (R-tilde = Rbar^{-1}, Sec. III-A-2)
+  w_i     = |W_ii|^2                               (MoP weights, eq_mop)
+  u       = s + tau * l    (l = -t: the paper writes v - tau t, Sec. II-B)
+  cost(l) = || W u_pi ||^2 = u^H A^{-1} u          (eq:se after the unitary step, eq_qrse)
+
+Readings of the paper that this file fixes (each is also listed in the
+design notes):
+  * Alg. 1 is read as sorted modified Gram-Schmidt on the rows of
+    [H, lambda I]: the argmin runs over the rows not yet processed, each new
+    basis row is normalised by Rbar_ii, and the projection uses q_j (the
+    printed listing drops the index).  This equals a Cholesky factorisation
+    of A with the smallest remaining Schur-complement diagonal as pivot.
+  * With sorting, the implicit inverse of eq:invr becomes
+    Rbar^{-1} = Q2[:, pi] / lambda (columns permuted).
+  * The child order at each level is the exact order of the nine points of
+    the B=1 box by squared distance to the level centre (Sec. III-A-2,
+    "position vector ... ordered according to increasing PEDs"); equal
+    distances are ordered by the canonical box index j = 3(bx+1) + (by+1).
+  * Ties elsewhere: pivots -> smaller user index; MoP -> lexicographic
+    position vector (level 0 most significant); path costs -> smaller path
+    index k (the zero perturbation, when included, has index K).
+"""
+from __future__ import annotations
+
+import itertools
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+# The B = 1 perturbation box (Sec. III-A-2: |Re t|, |Im t| <= 1, |B| = 9),
+# in canonical index order j = 3 (bx + 1) + (by + 1).
+BOX = np.array([complex(bx, by) for bx in (-1, 0, 1) for by in (-1, 0, 1)], dtype=np.complex128)
+NBOX = 9
+
+STATUS_OK = 0
+STATUS_NOT_PD = 1
+STATUS_NONFINITE = 2
+
+
+# ---------------------------------------------------------------------------
+# Preprocessing (Sec. III-A-1, Alg. 1, eq:invr)
+# ---------------------------------------------------------------------------
+
+def gram(H: np.ndarray, alpha: float) -> np.ndarray:
+    """A = H H^H + alpha I (the regularised Gram matrix of Sec. II-A and Sec. III-A-1)."""
+    H = np.asarray(H, dtype=np.complex128)
+    return H @ H.conj().T + alpha * np.eye(H.shape[0])
+
+
+@dataclass
+class Prep:
+    L: np.ndarray        # Lbar, lower, search order
+    W: np.ndarray        # Lbar^{-1}
+    perm: np.ndarray     # level -> user
+    w2: np.ndarray       # |W_ii|^2
+    G: Optional[np.ndarray]   # H^H A^{-1}   [M][N]
+    status: int
+    pivots: np.ndarray   # Schur-complement diagonal chosen at each step
+    pivot_margin: np.ndarray  # gap to the runner-up pivot at each step (inf if none)
+
+
+def cholesky_minpivot(A: np.ndarray):
+    """Pivoted Cholesky A[pi][:,pi] = L L^H choosing, at each step, the remaining
+    user whose Schur-complement diagonal is smallest (ties -> smaller user index).
+
+    This is the factorisation that Alg. 1 (ISRQD) produces: its squared row norms
+    after each Gram-Schmidt sweep are exactly these Schur-complement diagonals.
+    Returns (L, perm, pivots, margins, status)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    C = np.zeros((n, n), dtype=np.complex128)   # C[u, k]: user u's entry in column k
+    remaining = list(range(n))
+    perm = []
+    pivots = np.zeros(n)
+    margins = np.full(n, np.inf)
+    status = STATUS_OK
+    # A pivot at or below n * eps * max_u A_uu is treated as zero: A is then not
+    # numerically positive definite (e.g. alpha = 0 with more users than antennas).
+    floor = n * np.finfo(np.float64).eps * float(np.max(np.real(np.diag(A))))
+    for i in range(n):
+        schur = np.array([A[u, u].real - np.sum(np.abs(C[u, :i]) ** 2) for u in remaining])
+        order = np.argsort(schur, kind="stable")       # stable: ties keep ascending user index
+        p_pos = int(order[0])
+        p = remaining[p_pos]
+        if len(remaining) > 1:
+            margins[i] = schur[order[1]] - schur[order[0]]
+        piv = schur[p_pos]
+        pivots[i] = piv
+        if not np.isfinite(piv) or piv <= floor:
+            status = STATUS_NOT_PD
+            piv = max(piv, 0.0) if np.isfinite(piv) else 0.0
+        lii = math.sqrt(piv)
+        C[p, i] = lii
+        for u in remaining:
+            if u == p:
+                continue
+            num = A[u, p] - np.sum(C[u, :i] * np.conj(C[p, :i]))
+            C[u, i] = num / lii if lii > 0 else 0.0
+        perm.append(p)
+        remaining.pop(p_pos)
+    perm = np.array(perm, dtype=np.int64)
+    L = C[perm, :]
+    return L, perm, pivots, margins, status
+
+
+def forward_inverse(L: np.ndarray) -> np.ndarray:
+    """W = L^{-1} for lower-triangular L by forward substitution, column by column."""
+    n = L.shape[0]
+    W = np.zeros_like(L, dtype=np.complex128)
+    for j in range(n):
+        e = np.zeros(n, dtype=np.complex128)
+        e[j] = 1.0
+        x = np.zeros(n, dtype=np.complex128)
+        for i in range(n):
+            x[i] = (e[i] - np.dot(L[i, :i], x[:i])) / L[i, i]
+        W[:, j] = x
+    return W
+
+
+def preprocess(H: np.ndarray, alpha: float, want_G: bool = True) -> Prep:
+    """Per-subcarrier preprocessing of Alg. 2's "regularise and factorise" step:
+    A = H H^H + alpha I, sorted factorisation (Alg. 1 via its Cholesky form),
+    W = Rbar^{-1}, MoP weights w_i = |W_ii|^2 (eq_mop) and the RZF matrix
+    G = H^H A^{-1} (Sec. II-A; equal to the Tikhonov pseudo-inverse of
+    Sec. III-A-1)."""
+    H = np.asarray(H, dtype=np.complex128)
+    if not np.all(np.isfinite(H.view(np.float64))) or not math.isfinite(alpha):
+        n = H.shape[0]
+        return Prep(np.zeros((n, n), complex), np.zeros((n, n), complex), np.arange(n),
+                    np.zeros(n), None, STATUS_NONFINITE, np.zeros(n), np.full(n, np.inf))
+    A = gram(H, alpha)
+    L, perm, pivots, margins, status = cholesky_minpivot(A)
+    if status != STATUS_OK:
+        n = H.shape[0]
+        return Prep(L, np.zeros((n, n), complex), perm, np.zeros(n), None, status, pivots, margins)
+    W = forward_inverse(L)
+    w2 = np.abs(np.diag(W)) ** 2
+    G = np.linalg.solve(A, H).conj().T if want_G else None   # H^H A^{-1} = (A^{-1} H)^H
+    return Prep(L, W, perm, w2, G, status, pivots, margins)
+
+
+def isrqd(H: np.ndarray, lam: float):
+    """Alg. 1 (improved sorted RQ decomposition) of Hbar = [H, lambda I].
+
+    Sorted modified Gram-Schmidt on the rows: the remaining row of smallest
+    squared norm is processed next (ties -> smaller user index), it becomes
+    q_i = row / Rbar_ii, and every later row j loses its projection
+    Rbar_ji = <row_j, q_i>, with its squared norm downdated by |Rbar_ji|^2.
+    Returns (Rbar lower-triangular, Qbar with orthonormal rows, perm) such that
+    Hbar[perm] = Rbar Qbar."""
+    H = np.asarray(H, dtype=np.complex128)
+    n, m = H.shape
+    Qb = np.concatenate([H, lam * np.eye(n)], axis=1)
+    norms = np.sum(np.abs(Qb) ** 2, axis=1)
+    perm = np.arange(n)
+    R = np.zeros((n, n), dtype=np.complex128)
+    for i in range(n):
+        rest = np.arange(i, n)
+        best = min(rest, key=lambda j: (norms[j], perm[j]))
+        for arr in (Qb, norms, perm):
+            arr[[i, best]] = arr[[best, i]]
+        R[[i, best], :i] = R[[best, i], :i]
+        R[i, i] = math.sqrt(norms[i])
+        Qb[i] = Qb[i] / R[i, i]
+        for j in range(i + 1, n):
+            R[j, i] = np.dot(Qb[j], np.conj(Qb[i]))
+            Qb[j] = Qb[j] - R[j, i] * Qb[i]
+            norms[j] = norms[j] - abs(R[j, i]) ** 2
+    return R, Qb, perm
+
+
+# ---------------------------------------------------------------------------
+# Metric of Promise and the path set (Sec. III-A-2, eq_mop)
+# ---------------------------------------------------------------------------
+
+def mop_value(w2: np.ndarray, r) -> float:
+    """M(p) = sum_l |Rtilde_ll|^2 (p_l - 1) with r = p - 1, summed in level order."""
+    acc = 0.0
+    for wi, ri in zip(np.asarray(w2, dtype=np.float64), r):
+        acc = acc + float(wi) * float(ri)
+    return acc
+
+
+def mop_paths_bruteforce(w2: np.ndarray, K: int) -> np.ndarray:
+    """The K position vectors of smallest MoP over all 9^N candidates, ordered by
+    (MoP, lexicographic r with level 0 most significant).  Tiny N only."""
+    n = len(w2)
+    cands = list(itertools.product(range(NBOX), repeat=n))
+    cands.sort(key=lambda r: (mop_value(w2, r), r))
+    return np.array(cands[:K], dtype=np.int64).reshape(K, n)
+
+
+def mop_paths_kbest(w2: np.ndarray, K: int) -> np.ndarray:
+    """Breadth-first K-best over the MoP tree (Sec. III-A-2): from level 0, expand
+    every survivor to its 9 children, keep the K smallest partial MoPs
+    (ties -> lexicographic prefix), repeat to depth N.  Partial sums are
+    accumulated in level order, as in mop_value."""
+    w2 = np.asarray(w2, dtype=np.float64)
+    n = len(w2)
+    surv_m = np.zeros(1)
+    surv_r = np.zeros((1, 0), dtype=np.int64)
+    for lvl in range(n):
+        cm = (surv_m[:, None] + w2[lvl] * np.arange(NBOX)[None, :]).reshape(-1)
+        cr = np.concatenate([np.repeat(surv_r, NBOX, axis=0),
+                             np.tile(np.arange(NBOX), len(surv_r))[:, None]], axis=1)
+        keys = [cr[:, c] for c in range(lvl, -1, -1)] + [cm]   # lexsort: last key primary
+        order = np.lexsort(keys)[:K]
+        surv_m, surv_r = cm[order], cr[order]
+    return surv_r
+
+
+# ---------------------------------------------------------------------------
+# Same-path-set search (Sec. II-B PED recursion, Sec. III-A-2 centres and DEMAP,
+# Alg. 2 parallel evaluation + argmin)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class SearchResult:
+    l: np.ndarray          # complex [n_vec][N], user order, exact Gaussian integers
+    cost: np.ndarray       # [n_vec] selected cost (gamma of Alg. 2)
+    kidx: np.ndarray       # [n_vec] selected path (K = the zero perturbation)
+    path_cost: np.ndarray  # [n_vec][K(+1)] every candidate's cost
+    path_l: np.ndarray     # [n_vec][K][N] every candidate's l, level order
+    margin: np.ndarray     # [n_vec][K] smallest order margin met along each path
+
+
+def demap_walk(W, st, tau, ranks):
+    """Walk the tree along position vectors for many (vector, path) pairs at once.
+
+    st: complex [V][N] = W s_pi (s-tilde of the PED recursion); ranks: int
+    [P][N].  Returns (l [V][P][N], cost [V][P], margin [V][P]).  At level i the
+    centre is c_i = -r_i / (tau W_ii) where r_i is the running residual
+    s-tilde_i + tau sum_{j<i} W_ij l_j (the s-hat of Sec. III-A-2 with l = -t);
+    the child of rank p_i is the p_i-th box point in the (distance, j) order;
+    the PED grows by tau^2 |W_ii|^2 |c_i - l_i|^2 (Sec. II-B)."""
+    V, n = st.shape
+    P = ranks.shape[0]
+    resid = np.broadcast_to(st[:, None, :], (V, P, n)).copy()
+    l = np.zeros((V, P, n), dtype=np.complex128)
+    cost = np.zeros((V, P))
+    margin = np.full((V, P), np.inf)
+    for i in range(n):
+        wii = W[i, i]
+        c = -resid[:, :, i] / (tau * wii)
+        d = np.abs(c[:, :, None] - BOX[None, None, :]) ** 2             # [V][P][9]
+        order = np.argsort(d, axis=2, kind="stable")                      # (d, j) order
+        dsorted = np.take_along_axis(d, order, axis=2)
+        r = np.broadcast_to(ranks[None, :, i], (V, P))[:, :, None]
+        j = np.take_along_axis(order, r, axis=2)[:, :, 0]
+        dch = np.take_along_axis(dsorted, r, axis=2)[:, :, 0]
+        dlo = np.take_along_axis(dsorted, np.maximum(r - 1, 0), axis=2)[:, :, 0]
+        dhi = np.take_along_axis(dsorted, np.minimum(r + 1, NBOX - 1), axis=2)[:, :, 0]
+        lo = np.where(r[:, :, 0] > 0, dch - dlo, np.inf)
+        hi = np.where(r[:, :, 0] < NBOX - 1, dhi - dch, np.inf)
+        margin = np.minimum(margin, np.minimum(lo, hi))
+        li = BOX[j]
+        l[:, :, i] = li
+        cost += (tau ** 2) * (abs(wii) ** 2) * dch
+        if i + 1 < n:
+            resid[:, :, i + 1:] += tau * W[None, None, i + 1:, i] * li[:, :, None]
+    return l, cost, margin
+
+
+def search_paths(W, perm, s, tau, paths, include_zero: bool = True) -> SearchResult:
+    """Alg. 2's data-dependent part for one subcarrier: for every vector (columns
+    of s, user order) evaluate every path of the set, then take the argmin.
+
+    W: complex [N][N] lower (search order); perm: level -> user; s: complex
+    [N][V] (user order); paths: int [K][N] ranks 0..8.  With include_zero, the
+    zero perturbation (plain RZF) is candidate index K."""
+    W = np.asarray(W, dtype=np.complex128)
+    perm = np.asarray(perm, dtype=np.int64)
+    s = np.asarray(s, dtype=np.complex128)
+    if s.ndim == 1:
+        s = s[:, None]
+    paths = np.asarray(paths, dtype=np.int64)
+    K, n = paths.shape
+    s_pi = s[perm, :].T                     # [V][N] level order
+    st = s_pi @ W.T                         # s-tilde = W s_pi, per vector
+    l, cost, margin = demap_walk(W, st, tau, paths)
+    if include_zero:
+        c0 = np.sum(np.abs(st) ** 2, axis=1)
+        cost_all = np.concatenate([cost, c0[:, None]], axis=1)
+    else:
+        cost_all = cost
+    k = np.argmin(cost_all, axis=1)         # first minimum -> smaller k on ties
+    V = st.shape[0]
+    l_sel = np.zeros((V, n), dtype=np.complex128)
+    for v in range(V):
+        if k[v] < K:
+            l_sel[v, perm] = l[v, k[v]]
+    return SearchResult(l_sel, cost_all[np.arange(V), k], k, cost_all, l, margin)
+
+
+def cost_closed_form(A: np.ndarray, s: np.ndarray, l: np.ndarray, tau: float) -> float:
+    """u^H A^{-1} u with u = s + tau l (user order): the quantity eq:se minimises,
+    written with the RZF inverse (Sec. III-A-1)."""
+    u = np.asarray(s, np.complex128) + tau * np.asarray(l, np.complex128)
+    return float(np.real(np.vdot(u, np.linalg.solve(A, u))))
+
+
+def cost_tri(W, perm, s, l, tau) -> float:
+    """|| W (s + tau l)_pi ||^2 (eq_qrse with l = -t)."""
+    u = np.asarray(s, np.complex128) + tau * np.asarray(l, np.complex128)
+    return float(np.sum(np.abs(np.asarray(W, np.complex128) @ u[np.asarray(perm)]) ** 2))
+
+
+# ---------------------------------------------------------------------------
+# Exact VP over the box: brute force and a depth-first sphere encoder
+# ---------------------------------------------------------------------------
+
+def brute_force(W, perm, s, tau):
+    """Exact minimiser of eq:se over the whole box B^N (9^N candidates): the
+    smallest || W (s_pi + tau l) ||^2; ties -> lexicographically smallest box
+    index vector in level order.  Returns (l user order, cost)."""
+    W = np.asarray(W, np.complex128)
+    n = W.shape[0]
+    s_pi = np.asarray(s, np.complex128)[np.asarray(perm)]
+    J = np.array(list(itertools.product(range(NBOX), repeat=n)), dtype=np.int64)   # lexicographic
+    U = s_pi[None, :] + tau * BOX[J]
+    costs = np.sum(np.abs(U @ W.T) ** 2, axis=1)
+    b = int(np.argmin(costs))
+    l = np.zeros(n, dtype=np.complex128)
+    l[np.asarray(perm)] = BOX[J[b]]
+    return l, float(costs[b])
+
+
+def sphere_encode(W, perm, s, tau, radius: float = math.inf):
+    """Depth-first Schnorr-Euchner sphere encoder over the box (the exact VP of
+    eq:se restricted to |Re|,|Im| <= 1).  Children of a node are visited in
+    (distance, j) order; a subtree is pruned when its PED is not below the best
+    cost found so far.  Returns (l user order, cost, nodes visited)."""
+    W = np.asarray(W, np.complex128)
+    n = W.shape[0]
+    s_pi = np.asarray(s, np.complex128)[np.asarray(perm)]
+    st = W @ s_pi
+    best = [radius, None]
+    nodes = [0]
+    lvl_l = np.zeros(n, dtype=np.complex128)
+
+    def rec(i, resid, ped):
+        wii = W[i, i]
+        c = -resid[i] / (tau * wii)
+        d = np.abs(c - BOX) ** 2
+        for j in np.argsort(d, kind="stable"):
+            nped = ped + tau * tau * abs(wii) ** 2 * d[j]
+            if nped >= best[0]:
+                break
+            nodes[0] += 1
+            lvl_l[i] = BOX[j]
+            if i + 1 == n:
+                best[0] = nped
+                best[1] = lvl_l.copy()
+            else:
+                rec(i + 1, resid + tau * W[:, i] * BOX[j] * (np.arange(n) > i), nped)
+
+    rec(0, st.copy(), 0.0)
+    if best[1] is None:
+        return None, math.inf, nodes[0]
+    l = np.zeros(n, dtype=np.complex128)
+    l[np.asarray(perm)] = best[1]
+    return l, float(best[0]), nodes[0]
+
+
+# ---------------------------------------------------------------------------
+# Precoding, receiver modulo, power gap (Alg. 2 output, eq:postproc)
+# ---------------------------------------------------------------------------
+
+def precode(G, s, l, tau, gamma=None, P_T: float = 0.0):
+    """x = G (s + tau l) (Alg. 2 / Sec. IV-B: the precoded vector before and,
+    with P_T > 0, after the sqrt(P_T / gamma) normalisation)."""
+    u = np.asarray(s, np.complex128) + tau * np.asarray(l, np.complex128)
+    x = np.asarray(G, np.complex128) @ u
+    if P_T > 0.0:
+        x = x * math.sqrt(P_T / gamma)
+    return x
+
+
+def mod_tau(a, tau):
+    """Receiver modulo of eq:postproc, applied to both rails:
+    mod(a) = a - tau * floor((a + tau/2) / tau)."""
+    a = np.asarray(a, np.complex128)
+    f = lambda v: v - tau * np.floor((v + tau / 2.0) / tau)
+    return f(a.real) + 1j * f(a.imag)
+
+
+def gap_db(gamma_method, gamma_exact) -> float:
+    """Transmit-power gap 10 log10(sum gamma_method / sum gamma_exact)."""
+    return 10.0 * math.log10(float(np.sum(gamma_method)) / float(np.sum(gamma_exact)))
+
+
+def complexity_cm(n_r: int, n_t: int, K: int) -> int:
+    """Per-vector complex multiplications of ViPer (Sec. III-B complexity paragraph):
+    N_r N_t + N_t^2 + K N_t (1 + (N_t + 1) / 2)."""
+    return n_r * n_t + n_t * n_t + (K * n_t * (2 + n_t + 1)) // 2
