@@ -1,0 +1,183 @@
+/*
+ * vp.h -- C ABI of the MI355X (gfx950) vector-perturbation precoding library.
+ *
+ * ViPer NL-COMM vector perturbation (Thomas, Katsaros, Jayawardena,
+ * Nikitopoulos, arXiv 2602.12098): per-subcarrier sorted regularised-ZF
+ * preprocessing, channel-only selection of the K most promising tree paths
+ * by the Metric of Promise, and per-vector evaluation of those K paths with
+ * an argmin, followed by the linear precoding x = G (s + tau l).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller.  Nothing is
+ *    allocated, freed or synchronised by these calls: each one validates its
+ *    scalar arguments on the host and enqueues kernels on `stream` (a
+ *    hipStream_t; NULL is the default stream), then returns.
+ *  - Complex numbers are vp_c32 {re, im} (interleaved float32, 8 bytes).
+ *  - N = n_r = users/streams = tree levels (1..16); M = n_t = AP antennas
+ *    (1..64).  Row i of H is user i (Sec. II).
+ *  - Vector index v = sc * n_sym + sym, n_vec = n_sc * n_sym.
+ *  - "Search order" is the level order of the tree (level 0 is the root);
+ *    perm[sc][i] is the user served at level i.
+ *  - The perturbation is l = -t relative to the paper's v - tau t
+ *    (Sec. II-B), so u = s + tau l and both are Gaussian integers with
+ *    |Re l|, |Im l| <= 1 (the B = 1 box of Sec. III-A-2).
+ *  - Return value: VP_OK, or a negative code for an argument / launch error
+ *    (then nothing, or not everything, was enqueued).  Data-dependent
+ *    failures are reported per subcarrier in `status` instead.
+ *  - Calls on one stream run in order; calls are reentrant and thread-safe
+ *    (the library keeps no mutable state besides the last HIP error code).
+ */
+#ifndef VP_H
+#define VP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+    float re, im;
+} vp_c32;
+
+enum {
+    VP_OK = 0,
+    VP_EINVAL = -1,       /* null pointer, bad size, tau <= 0, K > 9^N, alpha = 0 with N > M, ... */
+    VP_EUNSUPPORTED = -2, /* N > 16, M > 64, K > 4096 */
+    VP_ELAUNCH = -3       /* a HIP launch failed; see vp_last_hip_error() */
+};
+
+/* per-subcarrier status written by vp_preprocess */
+enum {
+    VP_STATUS_OK = 0,
+    VP_STATUS_NOT_PD = 1,    /* a pivot <= N * eps32 * max_u A_uu: A not positive definite */
+    VP_STATUS_NONFINITE = 2  /* H or alpha not finite */
+};
+
+/* flags for vp_search */
+enum {
+    VP_INCLUDE_ZERO = 1 /* also evaluate l = 0 (plain RZF) as candidate index K */
+};
+
+/* Size (in vp_c32) of one packed lower-triangular N x N matrix. */
+#define VP_PACKED(N) ((N) * ((N) + 1) / 2)
+
+/*
+ * vp_preprocess -- regularised sorted factorisation (Sec. III-A-1, Alg. 1,
+ * eq:invr; Alg. 2 "regularise & factorise").
+ *
+ * For every subcarrier: A = H H^H + alpha I (alpha = lambda^2; alpha = 0 is
+ * zero forcing, Sec. II-A).  A is factorised as A[pi][:,pi] = Lbar Lbar^H,
+ * choosing at each step the remaining user with the smallest Schur-complement
+ * diagonal (ties -> smaller user index): this is the sorted RQ of
+ * [H, lambda I] computed by Alg. 1 (Lbar = Rbar).  W = Lbar^{-1} is the
+ * R-tilde of Sec. III-A-2.
+ *
+ *  H      [n_sc][N][M]   input channel, row-major
+ *  alpha  >= 0 (finite)
+ *  W      [n_sc][VP_PACKED(N)]  output, lower triangle of W in LAPACK
+ *         column-major packed order: element (i, j), i >= j, lives at
+ *         j*N - j*(j-1)/2 + (i - j).  The diagonal is real and positive.
+ *  w2     [n_sc][N]  output, |W_ii|^2, the Metric-of-Promise weights (eq_mop)
+ *  perm   [n_sc][N]  output, level -> user
+ *  G      [n_sc][M][N] output or NULL: G = H^H A^{-1}, the RZF precoder
+ *         (x = G u, Sec. II-A; equal to the Tikhonov pseudo-inverse of
+ *         Sec. III-A-1)
+ *  status [n_sc]     output, VP_STATUS_*; on failure W and G are filled with
+ *         NaN and w2 with +inf, so later calls see the failure.
+ *
+ * Errors: VP_EINVAL for NULL H/W/w2/perm/status, n_sc < 0, N < 1, M < 1,
+ * alpha < 0 or not finite, or alpha == 0 with N > M (rank-deficient A);
+ * VP_EUNSUPPORTED for N > 16 or M > 64.  n_sc == 0 is a no-op.
+ */
+int vp_preprocess(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c32 *W, float *w2,
+                  uint8_t *perm, vp_c32 *G, int32_t *status, void *stream);
+
+/*
+ * vp_paths_mop -- most promising paths (Sec. III-A-2, eq_mop; Alg. 2
+ * "MoP-Search").
+ *
+ * For every subcarrier, the K position vectors r in {0..8}^N (r = p - 1,
+ * 0-based ranks; rank 0 is the closest child) with the smallest Metric of
+ * Promise M(r) = sum_i w2_i r_i, found by the paper's breadth-first K-best
+ * search.  Partial sums are formed in float64 in level order; ties in M are
+ * broken by the lexicographic order of r (level 0 most significant), which
+ * makes the K-best result equal to the exact K smallest.  Output order is
+ * (M, lexicographic r): path k = 0 is the zero-rank (Babai) path.
+ *
+ *  w2     [n_sc][N]     input (from vp_preprocess), finite and > 0
+ *  paths  [n_sc][K][N]  output ranks 0..8, uint8
+ *
+ * Errors: VP_EINVAL for NULL pointers, n_sc < 0, N < 1, K < 1, K > 9^N;
+ * VP_EUNSUPPORTED for N > 16 or K > 4096.
+ */
+int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, void *stream);
+
+/*
+ * vp_search -- per-vector evaluation of K paths and argmin (Sec. II-B PED
+ * recursion, Sec. III-A-2 centres and DEMAP, Alg. 2 parallel post-processing).
+ *
+ * For every vector v of subcarrier sc and every path k: s_pi = s[perm] (user
+ * -> level order), s-tilde = W s_pi, and down the levels i = 0..N-1 the centre
+ * c_i = -(s-tilde_i + tau sum_{j<i} W_ij l_j) / (tau W_ii); l_i is the box
+ * point of rank paths[k][i] in the order of increasing |c_i - b|^2 (equal
+ * distances in canonical order j = 3(bx+1) + (by+1)).  cost_k =
+ * || W (s_pi + tau l) ||^2.  The result is the k with the smallest cost (ties
+ * -> smaller k); with VP_INCLUDE_ZERO the zero perturbation competes as index
+ * K.  cost is gamma_VP of Alg. 2 (the squared norm that sets the transmit
+ * normalisation).
+ *
+ *  W, perm  from vp_preprocess (W's diagonal must be real and > 0)
+ *  s        [N][n_vec]  symbols, structure of arrays (user-major), user order
+ *  tau      perturbation interval 2 sqrt(Q) (Sec. II-B), > 0
+ *  paths    ranks uint8; subcarrier sc uses paths + sc * paths_sc_stride,
+ *           a [K][N] table (stride 0 = one table for every subcarrier)
+ *  l        [N][n_vec][2] output int8 (re, im) in {-1, 0, 1}, user order
+ *  cost     [n_vec] output
+ *  kidx     [n_vec] output, selected path (K = zero perturbation)
+ *
+ * A subcarrier whose W_00 is not finite and > 0 (a failed vp_preprocess)
+ * gets l = 0, cost = NaN, kidx = -1.
+ *
+ * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, N < 1, K < 1,
+ * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N);
+ * VP_EUNSUPPORTED for N > 16 or K > 4096.
+ */
+int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
+              const uint8_t *paths, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
+              uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream);
+
+/*
+ * vp_precode -- precoded vector (Alg. 2 output; Sec. IV-B channel-inverse,
+ * gamma and PV blocks).
+ *
+ * x_v = G (s_v + tau l_v); with P_T > 0 also scaled by sqrt(P_T / cost_v), the
+ * transmit-power normalisation of Sec. II-B.  A vector whose cost is not
+ * finite and > 0 is written as NaN when P_T > 0.
+ *
+ *  G     [n_sc][M][N]  from vp_preprocess
+ *  s     [N][n_vec], l [N][n_vec][2] as in vp_search
+ *  cost  [n_vec] (may be NULL when P_T == 0)
+ *  x     [n_vec][M] output
+ *
+ * Errors: VP_EINVAL for NULL pointers, bad sizes, tau <= 0, P_T < 0, or
+ * cost == NULL with P_T > 0; VP_EUNSUPPORTED for N > 16 or M > 64.
+ */
+int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, float tau, const float *cost,
+               int n_sc, int n_sym, int n_r, int n_t, float P_T, vp_c32 *x, void *stream);
+
+/* Human-readable text for a return code. */
+const char *vp_strerror(int code);
+
+/* The hipError_t value of the last failed launch (0 if none). */
+int vp_last_hip_error(void);
+
+/* Library version string. */
+const char *vp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_H */

@@ -1,0 +1,78 @@
+"""Build the gfx950 precoding library in-tree.
+
+  libvp.so      HIP kernels + C ABI (hipcc, --offload-arch=gfx950)
+  libvphost.so  host build of the DEMAP routines, for CPU-side tests
+
+Usage: python -m paper_2602_12098_amd.build   (or build() from Python)
+"""
+from __future__ import annotations
+
+import os
+import shutil
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+BUILD = os.path.join(HERE, "_build")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
+LIB = os.path.join(HERE, "libvp.so")
+HOSTLIB = os.path.join(HERE, "libvphost.so")
+
+HIP_SOURCES = ["vp_api.hip", "vp_preprocess.hip", "vp_mop.hip", "vp_search.hip", "vp_precode.hip"]
+
+HIPCC_FLAGS = [
+    "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-I" + INCLUDE, "-I" + CSRC,
+]
+
+
+def _hipcc() -> str:
+    for c in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
+        if c and os.path.exists(c):
+            return c
+    raise RuntimeError("hipcc not found")
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("build failed:\n" + " ".join(cmd) + "\n" + r.stdout)
+    return r.stdout
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    hipcc = _hipcc()
+    # the DEMAP table is generated from its own enumeration script
+    lut = os.path.join(CSRC, "demap_lut.h")
+    gen = os.path.join(CSRC, "gen_demap_lut.py")
+    if not os.path.exists(lut) or os.path.getmtime(lut) < os.path.getmtime(gen):
+        out = _run([sys.executable, gen])
+        with open(lut, "w") as f:
+            f.write(out)
+
+    def compile_one(src):
+        obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
+        _run([hipcc, *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        return obj
+
+    with ThreadPoolExecutor(max_workers=min(8, len(HIP_SOURCES))) as ex:
+        objs = list(ex.map(compile_one, HIP_SOURCES))
+    tmp = LIB + ".tmp"
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    os.replace(tmp, LIB)
+    gxx = shutil.which("g++") or "g++"
+    tmp = HOSTLIB + ".tmp"
+    _run([gxx, "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-I" + CSRC, "-o", tmp,
+          os.path.join(CSRC, "vp_hostcheck.cpp")])
+    os.replace(tmp, HOSTLIB)
+    if verbose:
+        print("built", LIB, HOSTLIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

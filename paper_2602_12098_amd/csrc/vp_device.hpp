@@ -1,0 +1,98 @@
+// Device building blocks shared by the precoding kernels: the exact child
+// order of the B = 1 box (DEMAP, Sec. III-A-2) and packed-triangle indexing.
+//
+// The functions are plain float32 code with every fused multiply-add written
+// out, so that each kernel that walks a path (the search and its re-walk that
+// materialises l) performs bit-identical arithmetic.  They also compile for
+// the host, which lets the CPU test-suite check them exhaustively.
+#pragma once
+
+#include <math.h>
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#include <hip/hip_runtime.h>
+#define VP_HD __host__ __device__ __forceinline__
+#else
+#define VP_HD static inline
+#endif
+
+#include "demap_lut.h"
+
+// Offset of element (i, j), i >= j, in LAPACK column-major lower packed storage.
+VP_HD constexpr int vp_pidx(int n, int i, int j) { return j * n - (j * (j - 1)) / 2 + (i - j); }
+
+// Per-axis order of the three box offsets {-1, 0, 1} by squared distance to x:
+// o0 nearest, o2 farthest, with gaps A = (x-o1)^2 - (x-o0)^2 and
+// B = (x-o2)^2 - (x-o0)^2 (closed forms of those differences).
+struct vp_axis {
+    float o0, o1, o2, A, B;
+};
+
+VP_HD float vp_nearest_offset(float x) { return fminf(fmaxf(rintf(x), -1.0f), 1.0f); }
+
+VP_HD vp_axis vp_axis_order(float x) {
+    vp_axis r;
+    const float o0 = vp_nearest_offset(x);
+    const float s = (x > 0.0f) ? 1.0f : -1.0f;
+    const bool near0 = (o0 == 0.0f);
+    const float t = fabsf(x);
+    r.o0 = o0;
+    r.o1 = near0 ? s : 0.0f;
+    r.o2 = -s;
+    r.A = fabsf(fmaf(-2.0f, t, 1.0f));        // |1 - 2|x||
+    r.B = near0 ? fmaf(2.0f, t, 1.0f) : 4.0f * t;
+    return r;
+}
+
+// Rank-0 child: the box point nearest to (cx, cy).
+VP_HD void vp_demap0(float cx, float cy, float &a, float &b) {
+    a = vp_nearest_offset(cx);
+    b = vp_nearest_offset(cy);
+}
+
+// Children of rank 0 or 1.  Cell (0,1) precedes (1,0) when C < A, or on a tie
+// when its x offset is smaller (canonical index order).  Written with
+// non-short-circuit logic and selects so that no lane-divergent branch is made.
+VP_HD void vp_demap1(float cx, float cy, int rank, float &a, float &b) {
+    const vp_axis X = vp_axis_order(cx);
+    const vp_axis Y = vp_axis_order(cy);
+    const bool q1 = (Y.A < X.A) | ((Y.A == X.A) & (X.o0 < X.o1));
+    const bool r1 = (rank == 1);
+    a = (r1 & !q1) ? X.o1 : X.o0;
+    b = (r1 & q1) ? Y.o1 : Y.o0;
+}
+
+// Any rank 0..8: eight cell comparisons form the signature of the box order,
+// a 256 x 9 table gives the cell (p, q) of the requested rank.
+VP_HD int vp_demap_signature(const vp_axis &X, const vp_axis &Y) {
+    const float A = X.A, B = X.B, C = Y.A, D = Y.B;
+    const float AC = A + C, BC = B + C, AD = A + D;
+    int sig = (int)((C < A) | ((C == A) & (X.o0 < X.o1)));       // (0,1) before (1,0)
+    sig |= (int)(C < B) << 1;                                    // (0,1) before (2,0)
+    sig |= (int)(D < A) << 2;                                    // (0,2) before (1,0)
+    sig |= (int)(D < AC) << 3;                                   // (0,2) before (1,1)
+    sig |= (int)((D < B) | ((D == B) & (X.o0 < X.o2))) << 4;     // (0,2) before (2,0)
+    sig |= (int)(D < BC) << 5;                                   // (0,2) before (2,1)
+    sig |= (int)(AC < B) << 6;                                   // (1,1) before (2,0)
+    sig |= (int)(AD < B) << 7;                                   // (1,2) before (2,0)
+    return sig;
+}
+
+VP_HD float vp_pick_offset(const vp_axis &X, int p) {
+    float v = (p == 1) ? X.o1 : X.o0;
+    v = (p == 2) ? X.o2 : v;
+    return v;
+}
+
+VP_HD void vp_demapN(float cx, float cy, int rank, const uint8_t *lut, float &a, float &b) {
+    const vp_axis X = vp_axis_order(cx);
+    const vp_axis Y = vp_axis_order(cy);
+    const int sig = vp_demap_signature(X, Y);
+    const int cell = lut[sig * 9 + rank];
+    a = vp_pick_offset(X, cell & 3);
+    b = vp_pick_offset(Y, cell >> 2);
+}
+
+// Box code of a perturbation symbol: j = 3 (a + 1) + (b + 1).
+VP_HD int vp_box_code(float a, float b) { return 3 * ((int)a + 1) + ((int)b + 1); }

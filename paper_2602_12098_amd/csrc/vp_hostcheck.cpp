@@ -1,0 +1,26 @@
+// Host build of the device DEMAP routines, so that the CPU test-suite can
+// check the exact child order (Sec. III-A-2) exhaustively without a GPU.
+#include "vp_device.hpp"
+
+extern "C" {
+
+// tier 0: rank 0 only; tier 1: ranks 0..1; tier 2: any rank (table lookup).
+int vp_host_demap(const float *cx, const float *cy, const int32_t *rank, int n, int tier, float *a,
+                  float *b) {
+    for (int k = 0; k < n; ++k) {
+        float aa, bb;
+        if (tier == 0) {
+            if (rank[k] != 0) return -1;
+            vp_demap0(cx[k], cy[k], aa, bb);
+        } else if (tier == 1) {
+            if (rank[k] > 1) return -1;
+            vp_demap1(cx[k], cy[k], rank[k], aa, bb);
+        } else {
+            vp_demapN(cx[k], cy[k], rank[k], VP_DEMAP_LUT, aa, bb);
+        }
+        a[k] = aa;
+        b[k] = bb;
+    }
+    return 0;
+}
+}

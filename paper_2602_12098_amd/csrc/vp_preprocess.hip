@@ -1,0 +1,194 @@
+// Per-subcarrier regularised sorted factorisation (Sec. III-A-1, Alg. 1,
+// eq:invr) and the RZF precoder G = H^H (H H^H + alpha I)^{-1} (Sec. II-A).
+//
+// One 256-thread workgroup per subcarrier; the N x N Gram matrix lives in LDS
+// with one thread per entry.  Alg. 1's sorted Gram-Schmidt on the rows of
+// [H, lambda I] is carried out in its equivalent Cholesky form: the squared
+// row norms that Alg. 1 downdates are exactly the Schur-complement diagonals
+// of A = H H^H + lambda^2 I, so the pivot is the smallest remaining one and the
+// column entries are the projections R_ji.  W = Lbar^{-1} is then formed by
+// forward substitution (eq:invr's implicit inverse Q2/lambda needs the extended
+// Q, which this form never builds, and is undefined for lambda = 0).
+#include "vp_internal.hpp"
+
+namespace vp {
+namespace {
+
+constexpr int kT = 256;
+
+__global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H, int N, int M, float alpha,
+                                                   float2 *__restrict__ Wout, float *__restrict__ w2out,
+                                                   uint8_t *__restrict__ perm_out, float2 *__restrict__ Gout,
+                                                   int32_t *__restrict__ status_out) {
+    __shared__ float2 sH[kMaxN * kMaxM];
+    __shared__ float2 S[kMaxN][kMaxN + 1];    // Schur complement, user indices
+    __shared__ float2 Lc[kMaxN][kMaxN + 1];   // Lc[u][k]: user u's entry of factor column k
+    __shared__ float2 Wl[kMaxN][kMaxN + 1];   // W = Lbar^{-1}, search order
+    __shared__ float2 Ai[kMaxN][kMaxN + 1];   // A^{-1}, user indices
+    __shared__ int sperm[kMaxN];
+    __shared__ int srem[kMaxN];               // 1 while user not yet pivoted
+    __shared__ float spiv;
+    __shared__ int sstatus;
+
+    const int sc = blockIdx.x;
+    const int t = threadIdx.x;
+    const int NM = N * M;
+    const float2 *Hs = H + (size_t)sc * NM;
+
+    int bad = 0;
+    for (int idx = t; idx < NM; idx += kT) {
+        float2 h = Hs[idx];
+        sH[idx] = h;
+        bad |= !(isfinite(h.x) && isfinite(h.y));
+    }
+    bad = __syncthreads_or(bad);
+    if (t == 0) sstatus = bad ? VP_STATUS_NONFINITE : VP_STATUS_OK;
+
+    const int i = t >> 4, j = t & 15;
+    if (i < N && j < N) {
+        float re = 0.f, im = 0.f;
+        for (int k = 0; k < M; ++k) {   // A_ij = sum_k H_ik conj(H_jk)
+            const float2 a = sH[i * M + k], b = sH[j * M + k];
+            re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
+            im = fmaf(a.y, b.x, fmaf(-a.x, b.y, im));
+        }
+        if (i == j) {
+            re += alpha;
+            im = 0.f;
+        }
+        S[i][j] = make_float2(re, im);
+    }
+    if (t < N) srem[t] = 1;
+    __syncthreads();
+
+    // Pivot floor: N * eps32 * max_u A_uu.
+    float floor_ = 0.f;
+    for (int u = 0; u < N; ++u) floor_ = fmaxf(floor_, S[u][u].x);
+    floor_ *= (float)N * 1.1920929e-7f;
+
+    for (int step = 0; step < N; ++step) {
+        if (t == 0) {
+            int p = -1;
+            float best = 0.f;
+            for (int u = 0; u < N; ++u) {   // ascending u: ties keep the smaller user
+                if (!srem[u]) continue;
+                const float d = S[u][u].x;
+                if (p < 0 || d < best) {
+                    p = u;
+                    best = d;
+                }
+            }
+            if (!(best > floor_) && sstatus == VP_STATUS_OK) sstatus = VP_STATUS_NOT_PD;
+            sperm[step] = p;
+            srem[p] = 0;
+            spiv = sqrtf(fmaxf(best, 0.f));
+        }
+        __syncthreads();
+        const int p = sperm[step];
+        const float lpp = spiv;
+        if (t < N) {
+            if (t == p) {
+                Lc[t][step] = make_float2(lpp, 0.f);
+            } else if (srem[t]) {
+                const float2 a = S[t][p];
+                Lc[t][step] = lpp > 0.f ? make_float2(a.x / lpp, a.y / lpp) : make_float2(0.f, 0.f);
+            }
+        }
+        __syncthreads();
+        if (i < N && j < N && srem[i] && srem[j]) {   // S_ij -= L_i conj(L_j)
+            const float2 a = Lc[i][step], b = Lc[j][step];
+            float2 v = S[i][j];
+            v.x = fmaf(-a.x, b.x, fmaf(-a.y, b.y, v.x));
+            v.y = fmaf(-a.y, b.x, fmaf(a.x, b.y, v.y));
+            S[i][j] = v;
+        }
+        __syncthreads();
+    }
+
+    const int st = sstatus;
+    const int NP = VP_PACKED(N);
+    float2 *Wsc = Wout + (size_t)sc * NP;
+    if (st != VP_STATUS_OK) {
+        const float qnan = __int_as_float(0x7fc00000);
+        for (int idx = t; idx < NP; idx += kT) Wsc[idx] = make_float2(qnan, qnan);
+        if (t < N) {
+            w2out[(size_t)sc * N + t] = __int_as_float(0x7f800000);
+            perm_out[(size_t)sc * N + t] = (uint8_t)t;
+        }
+        if (Gout)
+            for (int idx = t; idx < NM; idx += kT) Gout[(size_t)sc * NM + idx] = make_float2(qnan, qnan);
+        if (t == 0) status_out[sc] = st;
+        return;
+    }
+
+    // W = Lbar^{-1}: thread c solves Lbar x = e_c by forward substitution.
+    if (t < N) {
+        const int c = t;
+        for (int r = 0; r < c; ++r) Wl[r][c] = make_float2(0.f, 0.f);
+        for (int r = c; r < N; ++r) {
+            const int ur = sperm[r];
+            float re = (r == c) ? 1.f : 0.f, im = 0.f;
+            for (int k = c; k < r; ++k) {   // - Lbar_rk W_kc
+                const float2 a = Lc[ur][k], b = Wl[k][c];
+                re = fmaf(-a.x, b.x, fmaf(a.y, b.y, re));
+                im = fmaf(-a.x, b.y, fmaf(-a.y, b.x, im));
+            }
+            const float d = Lc[ur][r].x;
+            Wl[r][c] = make_float2(re / d, im / d);
+        }
+    }
+    __syncthreads();
+
+    // A^{-1} = P^T W^H W P:  (W^H W)_kl = sum_{r >= max(k,l)} conj(W_rk) W_rl
+    if (i < N && j < N) {
+        float re = 0.f, im = 0.f;
+        for (int r = (i > j ? i : j); r < N; ++r) {
+            const float2 a = Wl[r][i], b = Wl[r][j];
+            re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
+            im = fmaf(a.x, b.y, fmaf(-a.y, b.x, im));
+        }
+        Ai[sperm[i]][sperm[j]] = make_float2(re, im);
+    }
+    __syncthreads();
+
+    for (int idx = t; idx < NP; idx += kT) {   // packed column-major lower
+        int c = 0, rem = idx;
+        while (rem >= N - c) {
+            rem -= N - c;
+            ++c;
+        }
+        const int r = c + rem;
+        float2 v = Wl[r][c];
+        if (r == c) v.y = 0.f;
+        Wsc[idx] = v;
+    }
+    if (t < N) {
+        const float d = Wl[t][t].x;
+        w2out[(size_t)sc * N + t] = d * d;
+        perm_out[(size_t)sc * N + t] = (uint8_t)sperm[t];
+    }
+    if (Gout) {   // G[m][u] = sum_v conj(H_vm) Ainv_vu
+        for (int idx = t; idx < NM; idx += kT) {
+            const int m = idx / N, u = idx % N;
+            float re = 0.f, im = 0.f;
+            for (int v = 0; v < N; ++v) {
+                const float2 h = sH[v * M + m], a = Ai[v][u];
+                re = fmaf(h.x, a.x, fmaf(h.y, a.y, re));
+                im = fmaf(h.x, a.y, fmaf(-h.y, a.x, im));
+            }
+            Gout[(size_t)sc * NM + idx] = make_float2(re, im);
+        }
+    }
+    if (t == 0) status_out[sc] = st;
+}
+
+}  // namespace
+
+int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
+                      uint8_t *perm, float2 *G, int32_t *status, hipStream_t st) {
+    if (n_sc == 0) return VP_OK;
+    hipLaunchKernelGGL(k_preprocess, dim3(n_sc), dim3(kT), 0, st, H, N, M, alpha, W, w2, perm, G, status);
+    return launch_status();
+}
+
+}  // namespace vp

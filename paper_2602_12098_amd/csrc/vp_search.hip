@@ -1,0 +1,281 @@
+// Per-vector path search and argmin (Sec. II-B PED recursion, Sec. III-A-2
+// level centres and DEMAP, Alg. 2 parallel post-processing over K paths).
+//
+// k_search: one 256-thread workgroup per vector, one path per lane.  The
+// subcarrier's W column entries are wave-uniform (scalar loads), the
+// per-vector start residual s-tilde / tau is computed once and broadcast
+// through LDS, and each lane reads its path's ranks as one 16-byte load.
+// Down the tree each lane keeps its residuals r_m = (s-tilde_m + tau
+// sum_{j<i} W_mj l_j) / tau in registers, so a level costs one DEMAP and a
+// rank-1 update of the residuals below it (4 FMAs per entry: l is a
+// Gaussian integer in the box).  The DEMAP work is picked per wave and
+// level from the largest rank the wave needs there (rank 0 is plain
+// rounding).  The cost of each path is ||W (s_pi + tau l)||^2 =
+// tau^2 sum_i |r_i + W_ii l_i|^2; the argmin over paths packs
+// (cost bits, k) into one 64-bit key and reduces it across the wave and the
+// workgroup.
+//
+// k_search_finalize re-walks the winning path of each vector with the very
+// same arithmetic to materialise l in user order.
+#include "vp_internal.hpp"
+
+#define VP_LUT_STORAGE static __constant__
+#include "vp_device.hpp"
+
+namespace vp {
+namespace {
+
+constexpr int kT = 256;
+
+// s-tilde_i / tau = (sum_{j<=i} W_ij s_{pi_j}) / tau for one vector.
+template <int N>
+__device__ __forceinline__ float2 stilde_over_tau(const float2 *__restrict__ Wc, const uint8_t *__restrict__ pm,
+                                                  const float2 *__restrict__ s, size_t v, size_t n_vec, int i,
+                                                  float inv_tau) {
+    float re = 0.f, im = 0.f;
+    for (int j = 0; j <= i; ++j) {
+        const float2 w = Wc[vp_pidx(N, i, j)];
+        const int u = pm[j] < N ? pm[j] : N - 1;   // a corrupt permutation must not index out of bounds
+        const float2 x = s[(size_t)u * n_vec + v];
+        re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
+        im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+    }
+    return make_float2(re * inv_tau, im * inv_tau);
+}
+
+// Walk one path.  r: residuals / tau (in: s-tilde / tau, destroyed), linv_i =
+// 1 / W_ii, wdiag_i = W_ii.  Returns sum_i |r_i + W_ii l_i|^2; with REC the chosen offsets.
+// Hides a wave-uniform pointer from loop-invariant code motion, so that the W
+// column of each level is scalar-loaded where it is used instead of all 240
+// coefficients being hoisted (and spilled) at once.  Loads through the
+// constant address space are selected as scalar (SMEM) loads.
+typedef const __attribute__((address_space(4))) float cfloat;   // constant space: scalar loads
+
+// The dependence on `after` keeps a load from being issued before that value
+// exists (the level's DEMAP result, or the chunk two steps back), which bounds
+// the scalar registers held by W to two chunks.
+__device__ __forceinline__ cfloat *opaque_uniform(const float2 *p, float after) {
+    asm volatile("" : "+s"(p) : "v"(after));
+    return (cfloat *)p;
+}
+
+template <int N, bool UNIFORM_TIERS, bool REC>
+__device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float *linv, const float *wdiag, float2 (&r)[N],
+                                      unsigned long long word, const uint8_t *lut, float *ra, float *rb) {
+    constexpr int CH = 4;   // W rows per scalar load (8 dwords)
+    float ped = 0.f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int rank = (int)((word >> (4 * i)) & 15ull);
+        const float li = linv[i];
+        const float cx = -(r[i].x * li);
+        const float cy = -(r[i].y * li);
+        float a, b;
+        if (UNIFORM_TIERS) {
+            if (__any(rank > 1)) vp_demapN(cx, cy, rank, lut, a, b);
+            else vp_demap1(cx, cy, rank, a, b);
+        } else {
+            vp_demapN(cx, cy, rank, lut, a, b);
+        }
+        if (REC) {
+            ra[i] = a;
+            rb[i] = b;
+        }
+        const float wii = wdiag[i];
+        const float ex = fmaf(wii, a, r[i].x);
+        const float ey = fmaf(wii, b, r[i].y);
+        ped = fmaf(ex, ex, ped);
+        ped = fmaf(ey, ey, ped);
+#pragma unroll
+        for (int m0 = i + 1; m0 < N; m0 += CH) {
+            float2 w[CH];
+            if (UNIFORM_TIERS) {
+                // chunk c may load once chunk c-1 has started at this level
+                const float dep = (m0 > i + 1) ? r[m0 - CH].y : a;
+                cfloat *Wk = opaque_uniform(W0, dep);
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+                    if (m0 + q < N) {
+                        w[q].x = Wk[2 * vp_pidx(N, m0 + q, i)];
+                        w[q].y = Wk[2 * vp_pidx(N, m0 + q, i) + 1];
+                    }
+            } else {
+#pragma unroll
+                for (int q = 0; q < CH; ++q)
+                    if (m0 + q < N) w[q] = W0[vp_pidx(N, m0 + q, i)];
+            }
+#pragma unroll
+            for (int q = 0; q < CH; ++q) {
+                const int m = m0 + q;
+                if (m < N) {
+                    r[m].x = fmaf(w[q].x, a, fmaf(-w[q].y, b, r[m].x));
+                    r[m].y = fmaf(w[q].x, b, fmaf(w[q].y, a, r[m].y));
+                }
+            }
+        }
+    }
+    return ped;
+}
+
+__device__ __forceinline__ unsigned long long umin64(unsigned long long a, unsigned long long b) {
+    return a < b ? a : b;
+}
+
+__device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x = umin64(x, __shfl_xor(x, off));
+    return x;
+}
+
+// Rank nibbles of path k (level i at bits 4i..4i+3).
+template <int N>
+__device__ __forceinline__ unsigned long long load_word(const uint8_t *__restrict__ P, int k) {
+    unsigned long long wd = 0;
+    if (N == 16 && ((reinterpret_cast<uintptr_t>(P) & 15) == 0)) {
+        const uint4 q = *reinterpret_cast<const uint4 *>(P + (size_t)k * 16);
+        const uint32_t d[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int i = 0; i < 16; ++i) wd |= (unsigned long long)((d[i >> 2] >> (8 * (i & 3))) & 15u) << (4 * i);
+    } else {
+#pragma unroll
+        for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[(size_t)k * N + i] & 15) << (4 * i);
+    }
+    return wd;
+}
+
+template <int N>
+__global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                               const float2 *__restrict__ s, float tau,
+                                               const uint8_t *__restrict__ paths, int K, long long pstride,
+                                               int n_sym, unsigned flags, float *__restrict__ cost_out,
+                                               int32_t *__restrict__ kidx_out) {
+    __shared__ float2 s_r0[N];
+    __shared__ float s_linv[N];
+    __shared__ float s_wdiag[N];
+    __shared__ uint8_t s_perm[N];
+    __shared__ unsigned long long s_red[kT / 64];
+
+    constexpr int NP = VP_PACKED(N);
+    const size_t v = blockIdx.x;            // one vector per workgroup
+    const int sc = (int)(v / n_sym);
+    const int t = threadIdx.x;
+    const size_t n_vec = (size_t)gridDim.x;
+    const float2 *__restrict__ Wc = W + (size_t)sc * NP;
+    const float w00 = Wc[0].x;
+    if (!(w00 > 0.f) || !isfinite(w00)) {   // failed preprocessing: l = 0, cost = NaN
+        if (t == 0) {
+            cost_out[v] = __int_as_float(0x7fc00000);
+            kidx_out[v] = -1;
+        }
+        return;
+    }
+    if (t < N) {
+        s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
+        s_linv[t] = 1.0f / s_wdiag[t];
+        s_perm[t] = perm[(size_t)sc * N + t];
+    }
+    __syncthreads();
+    if (t < N) s_r0[t] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, t, 1.0f / tau);
+    __syncthreads();
+
+    const uint8_t *P = paths + (size_t)sc * pstride;
+    unsigned long long best = ~0ull;
+    for (int k = t; k < K; k += kT) {
+        const unsigned long long wd = load_word<N>(P, k);
+        float2 r[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = s_r0[i];
+        const float ped = walk<N, true, false>(Wc, s_linv, s_wdiag, r, wd, VP_DEMAP_LUT, nullptr, nullptr);
+        best = umin64(best, ((unsigned long long)__float_as_uint(ped * (tau * tau)) << 32) | (unsigned)k);
+    }
+    if ((flags & VP_INCLUDE_ZERO) && t == 0) {
+        float z = 0.f;
+        for (int i = 0; i < N; ++i) {
+            z = fmaf(s_r0[i].x, s_r0[i].x, z);
+            z = fmaf(s_r0[i].y, s_r0[i].y, z);
+        }
+        best = umin64(best, ((unsigned long long)__float_as_uint(z * (tau * tau)) << 32) | (unsigned)K);
+    }
+    best = wave_min(best);
+    if ((t & 63) == 0) s_red[t >> 6] = best;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long b = s_red[0];
+        for (int w = 1; w < kT / 64; ++w) b = umin64(b, s_red[w]);
+        cost_out[v] = __uint_as_float((unsigned)(b >> 32));
+        kidx_out[v] = (int32_t)(b & 0xffffffffull);
+    }
+}
+
+template <int N>
+__global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict__ W,
+                                                        const uint8_t *__restrict__ perm,
+                                                        const float2 *__restrict__ s, float tau,
+                                                        const uint8_t *__restrict__ paths, int K,
+                                                        long long pstride, int n_sc, int n_sym,
+                                                        const int32_t *__restrict__ kidx,
+                                                        int8_t *__restrict__ l_out) {
+    constexpr int NP = VP_PACKED(N);
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n_vec) return;
+    const int sc = (int)(v / n_sym);
+    const int k = kidx[v];
+    const uint8_t *pm = perm + (size_t)sc * N;
+    float ra[N], rb[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) ra[i] = rb[i] = 0.f;
+    if (k >= 0 && k < K) {
+        const float2 *__restrict__ Wc = W + (size_t)sc * NP;
+        float linv[N], wdiag[N];
+        float2 r[N];
+        const float inv_tau = 1.0f / tau;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            wdiag[i] = Wc[vp_pidx(N, i, i)].x;
+            linv[i] = 1.0f / wdiag[i];
+            r[i] = stilde_over_tau<N>(Wc, pm, s, v, n_vec, i, inv_tau);
+        }
+        const uint8_t *P = paths + (size_t)sc * pstride + (size_t)k * N;
+        unsigned long long wd = 0;
+        for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
+        (void)walk<N, false, true>(Wc, linv, wdiag, r, wd, VP_DEMAP_LUT, ra, rb);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int u = pm[i] < N ? pm[i] : N - 1;
+        int8_t *o = l_out + ((size_t)u * n_vec + v) * 2;
+        o[0] = (int8_t)ra[i];
+        o[1] = (int8_t)rb[i];
+    }
+}
+
+template <int N>
+int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths, int K,
+                    int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l, float *cost, int32_t *kidx,
+                    hipStream_t st) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    hipLaunchKernelGGL(k_search<N>, dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
+                       (long long)pstride, n_sym, flags, cost, kidx);
+    hipLaunchKernelGGL(k_search_finalize<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
+                       tau, paths, K, (long long)pstride, n_sc, n_sym, kidx, l);
+    return launch_status();
+}
+
+}  // namespace
+
+int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths, int K,
+                  int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags, int8_t *l, float *cost,
+                  int32_t *kidx, hipStream_t st) {
+    if (n_sc == 0) return VP_OK;
+    switch (N) {
+#define VP_CASE(n) \
+    case n: return launch_search_n<n>(W, perm, s, tau, paths, K, pstride, n_sc, n_sym, flags, l, cost, kidx, st);
+        VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
+        VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
+#undef VP_CASE
+        default: return VP_EUNSUPPORTED;
+    }
+}
+
+}  // namespace vp

@@ -1,0 +1,140 @@
+"""Thin torch binding of the C ABI (argument marshalling only).
+
+Every function takes device tensors, checks dtype / shape / contiguity, passes
+raw pointers and the current HIP stream to libvp.so and returns the output
+tensors.  All arithmetic happens in the HIP kernels.  Names and layouts follow
+include/vp.h."""
+from __future__ import annotations
+
+from typing import NamedTuple, Optional
+
+import torch
+
+from . import _lib
+from ._lib import VP_INCLUDE_ZERO, check
+
+__all__ = ["Prep", "SearchOut", "preprocess", "paths_mop", "search", "precode", "packed_size",
+           "VP_INCLUDE_ZERO", "version"]
+
+
+def packed_size(n: int) -> int:
+    return n * (n + 1) // 2
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _req(t: torch.Tensor, name: str, dtype, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t.data_ptr()
+
+
+class Prep(NamedTuple):
+    W: torch.Tensor       # complex64 [n_sc][N(N+1)/2] packed lower, column-major, search order
+    w2: torch.Tensor      # float32 [n_sc][N]
+    perm: torch.Tensor    # uint8 [n_sc][N] level -> user
+    G: Optional[torch.Tensor]   # complex64 [n_sc][M][N]
+    status: torch.Tensor  # int32 [n_sc]
+
+
+class SearchOut(NamedTuple):
+    l: torch.Tensor       # int8 [N][n_vec][2]
+    cost: torch.Tensor    # float32 [n_vec]
+    kidx: torch.Tensor    # int32 [n_vec]
+
+
+def preprocess(H: torch.Tensor, alpha: float, want_G: bool = True, out: Optional[Prep] = None) -> Prep:
+    """vp_preprocess: H complex64 [n_sc][N][M] -> W, w2, perm, G, status."""
+    lib = _lib.load()
+    n_sc, N, M = H.shape
+    dev = H.device
+    if out is None:
+        out = Prep(torch.empty((n_sc, packed_size(N)), dtype=torch.complex64, device=dev),
+                   torch.empty((n_sc, N), dtype=torch.float32, device=dev),
+                   torch.empty((n_sc, N), dtype=torch.uint8, device=dev),
+                   torch.empty((n_sc, M, N), dtype=torch.complex64, device=dev) if want_G else None,
+                   torch.empty((n_sc,), dtype=torch.int32, device=dev))
+    pH = _req(H, "H", torch.complex64)
+    pW = _req(out.W, "W", torch.complex64, (n_sc, packed_size(N)))
+    pw = _req(out.w2, "w2", torch.float32, (n_sc, N))
+    pp = _req(out.perm, "perm", torch.uint8, (n_sc, N))
+    pG = _req(out.G, "G", torch.complex64, (n_sc, M, N)) if out.G is not None else None
+    ps = _req(out.status, "status", torch.int32, (n_sc,))
+    check(lib.vp_preprocess(pH, n_sc, N, M, float(alpha), pW, pw, pp, pG, ps, _stream()), "vp_preprocess")
+    return out
+
+
+def paths_mop(w2: torch.Tensor, K: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vp_paths_mop: w2 float32 [n_sc][N] -> paths uint8 [n_sc][K][N]."""
+    lib = _lib.load()
+    n_sc, N = w2.shape
+    if out is None:
+        out = torch.empty((n_sc, K, N), dtype=torch.uint8, device=w2.device)
+    pw = _req(w2, "w2", torch.float32)
+    po = _req(out, "paths", torch.uint8, (n_sc, K, N))
+    check(lib.vp_paths_mop(pw, n_sc, N, int(K), po, _stream()), "vp_paths_mop")
+    return out
+
+
+def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
+           n_sym: int, flags: int = VP_INCLUDE_ZERO, out: Optional[SearchOut] = None) -> SearchOut:
+    """vp_search: paths is [K][N] (one table for all subcarriers) or [n_sc][K][N]."""
+    lib = _lib.load()
+    n_sc = W.shape[0]
+    N = perm.shape[1]
+    n_vec = n_sc * n_sym
+    if paths.dim() == 2:
+        K, stride = paths.shape[0], 0
+    else:
+        if paths.shape[0] != n_sc:
+            raise ValueError("paths: first dimension must be n_sc")
+        K, stride = paths.shape[1], paths.shape[1] * paths.shape[2]
+    if paths.shape[-1] != N:
+        raise ValueError("paths: last dimension must be N")
+    dev = W.device
+    if out is None:
+        out = SearchOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
+                        torch.empty((n_vec,), dtype=torch.float32, device=dev),
+                        torch.empty((n_vec,), dtype=torch.int32, device=dev))
+    pW = _req(W, "W", torch.complex64, (n_sc, packed_size(N)))
+    pp = _req(perm, "perm", torch.uint8, (n_sc, N))
+    ps = _req(s, "s", torch.complex64, (N, n_vec))
+    pP = _req(paths, "paths", torch.uint8)
+    pl = _req(out.l, "l", torch.int8, (N, n_vec, 2))
+    pc = _req(out.cost, "cost", torch.float32, (n_vec,))
+    pk = _req(out.kidx, "kidx", torch.int32, (n_vec,))
+    check(lib.vp_search(pW, pp, ps, float(tau), pP, int(K), int(stride), n_sc, int(n_sym), N, int(flags),
+                        pl, pc, pk, _stream()), "vp_search")
+    return out
+
+
+def precode(G: torch.Tensor, s: torch.Tensor, l: torch.Tensor, tau: float, cost: Optional[torch.Tensor],
+            n_sym: int, P_T: float = 0.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vp_precode: x complex64 [n_vec][M] = G (s + tau l) (* sqrt(P_T / cost))."""
+    lib = _lib.load()
+    n_sc, M, N = G.shape
+    n_vec = n_sc * n_sym
+    if out is None:
+        out = torch.empty((n_vec, M), dtype=torch.complex64, device=G.device)
+    pG = _req(G, "G", torch.complex64)
+    ps = _req(s, "s", torch.complex64, (N, n_vec))
+    pl = _req(l, "l", torch.int8, (N, n_vec, 2))
+    pc = _req(cost, "cost", torch.float32, (n_vec,)) if cost is not None else None
+    px = _req(out, "x", torch.complex64, (n_vec, M))
+    check(lib.vp_precode(pG, ps, pl, float(tau), pc, n_sc, int(n_sym), N, M, float(P_T), px, _stream()),
+          "vp_precode")
+    return out
+
+
+def version() -> str:
+    return _lib.load().vp_version().decode()

@@ -1,0 +1,154 @@
+"""CPU-side checks of the C ABI boundary and of the host build of the DEMAP code.
+
+No compute call reaches the GPU here: argument validation returns before any
+HIP call, and the DEMAP routines are exercised through their host build."""
+import ctypes
+import os
+import re
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import vp_oracle as O
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vp.h")
+PKG = os.path.join(ROOT, "paper_2602_12098_amd")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2602_12098_amd import _lib
+    return _lib.load()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(vp_[a-z_]+)\(", text, flags=re.M)))
+
+
+def test_header_symbols_exported(lib):
+    names = declared_functions()
+    assert {"vp_preprocess", "vp_paths_mop", "vp_search", "vp_precode", "vp_strerror"} <= set(names)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(PKG, "libvp.so")],
+                         capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}\b", out), n
+
+
+def test_argument_validation(lib):
+    from paper_2602_12098_amd._lib import VP_EINVAL, VP_EUNSUPPORTED, VP_OK
+    F = 0
+    # vp_preprocess
+    assert lib.vp_preprocess(None, 1, 4, 4, 0.1, None, None, None, None, None, None) == VP_EINVAL
+    assert lib.vp_preprocess(None, 1, 17, 17, 0.1, None, None, None, None, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_preprocess(None, 1, 4, 65, 0.1, None, None, None, None, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_preprocess(None, 1, 6, 4, 0.0, None, None, None, None, None, None) == VP_EINVAL
+    assert lib.vp_preprocess(None, 1, 4, 4, -1.0, None, None, None, None, None, None) == VP_EINVAL
+    assert lib.vp_preprocess(None, 1, 4, 4, float("nan"), None, None, None, None, None, None) == VP_EINVAL
+    assert lib.vp_preprocess(None, 0, 4, 4, 0.1, None, None, None, None, None, None) == VP_OK
+    assert lib.vp_preprocess(None, -1, 4, 4, 0.1, None, None, None, None, None, None) == VP_EINVAL
+    # vp_paths_mop
+    assert lib.vp_paths_mop(None, 1, 2, 82, None, None) == VP_EINVAL          # K > 9^2
+    assert lib.vp_paths_mop(None, 1, 16, 1025, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_paths_mop(None, 1, 16, 0, None, None) == VP_EINVAL
+    assert lib.vp_paths_mop(None, 0, 4, 32, None, None) == VP_OK
+    assert lib.vp_paths_mop(None, 3, 4, 32, None, None) == VP_EINVAL          # null pointers
+    # vp_search
+    args = dict(tau=8.0, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1)
+
+    def search(**kw):
+        a = dict(args, **kw)
+        return lib.vp_search(None, None, None, a["tau"], None, a["K"], a["stride"], a["n_sc"], a["n_sym"],
+                             a["N"], a["flags"], None, None, None, None)
+    assert search() == VP_EINVAL
+    assert search(n_sc=0) == VP_OK
+    assert search(tau=0.0, n_sc=0) == VP_EINVAL
+    assert search(tau=float("inf"), n_sc=0) == VP_EINVAL
+    assert search(N=17, n_sc=0) == VP_EUNSUPPORTED
+    assert search(K=4097, n_sc=0) == VP_EUNSUPPORTED
+    assert search(stride=5, n_sc=0) == VP_EINVAL      # 0 < stride < K*N
+    assert search(stride=-1, n_sc=0) == VP_EINVAL
+    assert search(flags=2, n_sc=0) == VP_EINVAL
+    assert search(n_sym=0, n_sc=0) == VP_EINVAL
+    # vp_precode
+    assert lib.vp_precode(None, None, None, 8.0, None, 0, 14, 4, 4, 0.0, None, None) == VP_OK
+    assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 4, 4, 1.0, None, None) == VP_EINVAL
+    assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 4, 4, -1.0, None, None) == VP_EINVAL
+    assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 17, 4, 0.0, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_strerror(VP_EINVAL) == b"invalid argument"
+    assert lib.vp_last_hip_error() == 0
+    _ = F
+
+
+def _host_demap():
+    path = os.path.join(PKG, "libvphost.so")
+    h = ctypes.CDLL(path)
+    h.vp_host_demap.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int] * 2 + [ctypes.c_void_p] * 2
+    h.vp_host_demap.restype = ctypes.c_int
+
+    def run(cx, cy, r, tier):
+        n = len(cx)
+        a = np.zeros(n, np.float32)
+        b = np.zeros(n, np.float32)
+        cx = np.ascontiguousarray(cx, np.float32)
+        cy = np.ascontiguousarray(cy, np.float32)
+        r = np.ascontiguousarray(r, np.int32)
+        assert h.vp_host_demap(cx.ctypes.data, cy.ctypes.data, r.ctypes.data, n, tier,
+                               a.ctypes.data, b.ctypes.data) == 0
+        return a, b
+    return run
+
+
+def test_demap_matches_oracle_order():
+    """The GPU's DEMAP (host build) picks the same box point as the oracle's
+    (distance, j) order for every rank, except where two distances are within
+    1e-5 (float32 cannot order them); its three variants agree exactly."""
+    run = _host_demap()
+    rng = np.random.default_rng(0)
+    cx = rng.uniform(-4, 4, 60000).astype(np.float32)
+    cy = rng.uniform(-4, 4, 60000).astype(np.float32)
+    q = (np.arange(-15, 16, 2) / 32.0).astype(np.float32)      # 256-QAM level-0 centres, exact ties
+    gx, gy = np.meshgrid(q, q)
+    cx = np.concatenate([cx, gx.ravel(), cx[:5000]])
+    cy = np.concatenate([cy, gy.ravel(), -cx[:5000]])
+    c = cx.astype(np.float64) + 1j * cy.astype(np.float64)
+    d = np.abs(c[:, None] - O.BOX[None, :]) ** 2
+    order = np.argsort(d, axis=1, kind="stable")
+    ds = np.take_along_axis(d, order, 1)
+    for r in range(9):
+        a, b = run(cx, cy, np.full(len(cx), r), 2)
+        ref = O.BOX[order[:, r]]
+        mism = (a != ref.real) | (b != ref.imag)
+        lo = ds[:, r] - ds[:, max(r - 1, 0)] if r > 0 else np.full(len(cx), np.inf)
+        hi = ds[:, min(r + 1, 8)] - ds[:, r] if r < 8 else np.full(len(cx), np.inf)
+        assert not np.any(mism & (np.minimum(lo, hi) > 1e-5)), r
+        if r <= 1:
+            a1, b1 = run(cx, cy, np.full(len(cx), r), 1)
+            assert np.array_equal(a1, a) and np.array_equal(b1, b)
+        if r == 0:
+            a0, b0 = run(cx, cy, np.full(len(cx), r), 0)
+            assert np.array_equal(a0, a) and np.array_equal(b0, b)
+    # the exact diagonal ties of QAM centres are resolved by the canonical index
+    a, b = run(np.array([-3 / 32.0]), np.array([-3 / 32.0]), np.array([1]), 2)
+    assert (a[0], b[0]) == (-1.0, 0.0)
+    a, b = run(np.array([-3 / 32.0]), np.array([-3 / 32.0]), np.array([2]), 2)
+    assert (a[0], b[0]) == (0.0, -1.0)
+
+
+def test_demap_table_is_generated():
+    gen = os.path.join(PKG, "csrc", "gen_demap_lut.py")
+    out = subprocess.run([sys.executable, gen], capture_output=True, text=True, check=True).stdout
+    assert out == open(os.path.join(PKG, "csrc", "demap_lut.h")).read()
+
+
+def test_product_never_imports_oracle():
+    for dirpath, _, files in os.walk(PKG):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower(), f

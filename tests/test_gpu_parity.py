@@ -1,0 +1,313 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Same-input parity feeds the oracle the GPU's own W / perm / paths (upcast to
+float64); end-to-end parity lets the oracle preprocess H itself.  Sizes span
+several workgroups and ragged tails; the full 16x16 workload is launched as
+the benchmark launches it and checked on sampled subcarriers."""
+import math
+
+import numpy as np
+import pytest
+
+import vpgen
+from oracle import vp_oracle as O
+from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def vp():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2602_12098_amd as vp
+    return vp
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _to_dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
+
+
+def run_pipeline(vp, wl, K=None, want_G=True, include_zero=True, H=None, s=None, n_sym=None, alpha=None):
+    K = K or wl.K
+    H = wl.H if H is None else H
+    s = wl.s if s is None else s
+    n_sym = wl.n_sym if n_sym is None else n_sym
+    alpha = wl.alpha if alpha is None else alpha
+    Hd, sd = _to_dev(H), _to_dev(s)
+    prep = vp.preprocess(Hd, alpha, want_G=want_G)
+    paths = vp.paths_mop(prep.w2, K)
+    flags = vp.VP_INCLUDE_ZERO if include_zero else 0
+    out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, n_sym, flags=flags)
+    torch.cuda.synchronize()
+    return prep, paths, out, sd
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def check_same_input(vp, wl, prep, paths, out, scs, include_zero=True, n_sym=None):
+    n_sym = n_sym or wl.n_sym
+    N = wl.N
+    Wd = unpack_W(host(prep.W), N)
+    perm = host(prep.perm).astype(np.int64)
+    P = host(paths)
+    l = l_from_gpu(host(out.l))
+    cost, kidx = host(out.cost), host(out.kidx)
+    rep = ParityReport()
+    for sc in scs:
+        sl = slice(sc * n_sym, (sc + 1) * n_sym)
+        check_search_subcarrier(rep, Wd[sc], perm[sc], wl.s[:, sl].astype(np.complex128), wl.tau, P[sc],
+                                include_zero, l[sl], cost[sl], kidx[sl])
+    return rep
+
+
+def test_cfg1_full_same_input_and_brute_force(vp):
+    wl = vpgen.cfg1()
+    _say("cfg1", wl.name, wl.n_sc, wl.n_sym, wl.K)
+    prep, paths, out, _ = run_pipeline(vp, wl)
+    rep = check_same_input(vp, wl, prep, paths, out, range(wl.n_sc))
+    _say(rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.99 * rep.n
+    # every vector also against the exhaustive optimum over the 6561-point box
+    Wd = unpack_W(host(prep.W), 4)
+    perm = host(prep.perm).astype(np.int64)
+    cost = host(out.cost)
+    worse = 0
+    for sc in range(wl.n_sc):
+        for sym in range(wl.n_sym):
+            v = sc * wl.n_sym + sym
+            _, cb = O.brute_force(Wd[sc], perm[sc], wl.s[:, v], wl.tau)
+            assert cost[v] >= cb * (1 - 1e-5)
+            worse += cost[v] > cb * (1 + 1e-5)
+    _say("cfg1 vectors worse than exhaustive optimum:", worse, "of", wl.n_vec)
+
+
+def test_paths_mop_bit_exact(vp):
+    for wl, K in ((vpgen.cfg1(), 32), (vpgen.cfg2(20, n_sc=40), 64), (vpgen.cfg3(512, n_sc=24), 512),
+                  (vpgen.cfg3(128, n_sc=24), 128)):
+        _say("mop", wl.name, K)
+        Hd = _to_dev(wl.H)
+        prep = vp.preprocess(Hd, wl.alpha)
+        paths = host(vp.paths_mop(prep.w2, K))
+        w2 = host(prep.w2).astype(np.float64)
+        for sc in range(min(wl.n_sc, 24)):
+            ref = O.mop_paths_kbest(w2[sc], K)
+            assert np.array_equal(paths[sc], ref), (wl.name, sc)
+
+
+def test_paths_mop_ties_and_small_K(vp):
+    # equal weights: every tie broken lexicographically; K = 1 and K = 9^N
+    w = torch.full((3, 3), 0.25, dtype=torch.float32, device=DEV)
+    for K in (1, 7, 100, 729):
+        p = host(vp.paths_mop(w, K))
+        ref = O.mop_paths_bruteforce(np.full(3, 0.25, dtype=np.float32).astype(np.float64), K)
+        assert np.array_equal(p[0], ref) and np.array_equal(p[2], ref), K
+
+
+def test_preprocess_parity(vp):
+    for wl in (vpgen.cfg1(n_sc=32), vpgen.cfg2(10, n_sc=64), vpgen.cfg3(n_sc=64)):
+        _say("prep", wl.name)
+        Hd = _to_dev(wl.H)
+        prep = vp.preprocess(Hd, wl.alpha)
+        Wd = unpack_W(host(prep.W), wl.N)
+        perm = host(prep.perm).astype(np.int64)
+        w2 = host(prep.w2)
+        G = host(prep.G)
+        st = host(prep.status)
+        assert np.all(st == 0)
+        flagged = 0
+        for sc in range(wl.n_sc):
+            ref = O.preprocess(wl.H[sc], wl.alpha)
+            if not np.array_equal(perm[sc], ref.perm):
+                # only a near-tied pivot may reorder the users
+                assert np.min(ref.pivot_margin) <= 1e-4 * np.max(ref.pivots), (wl.name, sc)
+                flagged += 1
+                continue
+            scale = np.abs(ref.W).max()
+            assert np.abs(Wd[sc] - ref.W).max() <= 2e-5 * scale * wl.N, (wl.name, sc)
+            np.testing.assert_allclose(w2[sc], ref.w2, rtol=2e-5 * wl.N)
+            assert np.abs(G[sc] - ref.G).max() <= 2e-5 * np.abs(ref.G).max() * wl.N
+            # W is lower triangular with a real positive diagonal
+            assert np.all(np.diag(Wd[sc]).imag == 0) and np.all(np.diag(Wd[sc]).real > 0)
+        _say("  pivot-tie subcarriers:", flagged)
+        assert flagged <= max(1, wl.n_sc // 20)
+
+
+@pytest.mark.parametrize("snr", [10, 20, 30])
+def test_cfg2_same_input(vp, snr):
+    wl = vpgen.cfg2(snr, n_sc=48)
+    _say("cfg2", wl.name)
+    prep, paths, out, _ = run_pipeline(vp, wl)
+    rep = check_same_input(vp, wl, prep, paths, out, range(wl.n_sc))
+    _say(rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.99 * rep.n
+
+
+@pytest.mark.parametrize("K", [128, 512])
+def test_cfg3_same_input(vp, K):
+    wl = vpgen.cfg3(K, n_sc=20)
+    _say("cfg3", wl.name)
+    prep, paths, out, _ = run_pipeline(vp, wl)
+    rep = check_same_input(vp, wl, prep, paths, out, range(wl.n_sc))
+    _say(rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.99 * rep.n
+    assert rep.max_cost_rel_err <= 1e-5
+
+
+def test_cfg3_full_size_sampled(vp):
+    # the benchmark's launch: 3276 subcarriers x 14 symbols, K = 512
+    wl = vpgen.cfg3(512)
+    _say("cfg3 full", wl.n_sc, wl.n_sym)
+    prep, paths, out, _ = run_pipeline(vp, wl)
+    assert np.all(host(prep.status) == 0)
+    rng = np.random.default_rng(0)
+    scs = sorted(set(rng.choice(wl.n_sc, 12, replace=False).tolist()) | {0, wl.n_sc - 1})
+    w2 = host(prep.w2).astype(np.float64)
+    P = host(paths)
+    for sc in scs[:4]:
+        assert np.array_equal(P[sc], O.mop_paths_kbest(w2[sc], 512))
+    rep = check_same_input(vp, wl, prep, paths, out, scs)
+    _say(rep)
+    assert rep.ok(), rep.failures[:5]
+    # every vector: the cost never exceeds the plain RZF (l = 0) cost, and l in the box
+    l = host(out.l)
+    assert l.min() >= -1 and l.max() <= 1
+    assert np.all(host(out.kidx) >= 0) and np.all(host(out.kidx) <= 512)
+
+
+def test_end_to_end_from_H(vp):
+    wl = vpgen.cfg3(256, n_sc=12)
+    prep, paths, out, _ = run_pipeline(vp, wl)
+    l = l_from_gpu(host(out.l))
+    cost = host(out.cost)
+    P = host(paths)
+    mism = 0
+    for sc in range(wl.n_sc):
+        ref = O.preprocess(wl.H[sc], wl.alpha)
+        refp = O.mop_paths_kbest(ref.w2, 256)
+        sl = slice(sc * 14, (sc + 1) * 14)
+        res = O.search_paths(ref.W, ref.perm, wl.s[:, sl], wl.tau, refp)
+        same_set = np.array_equal(refp, P[sc])
+        for v in range(14):
+            c64 = O.cost_closed_form(O.gram(wl.H[sc], wl.alpha), wl.s[:, sl][:, v], l[sl][v], wl.tau)
+            assert abs(cost[sl][v] - c64) <= 1e-5 * c64 * 4
+            if not np.array_equal(l[sl][v], res.l[v]):
+                if abs(c64 - res.cost[v]) > 1e-5 * res.cost[v]:
+                    mism += 1
+                    assert (not same_set) or np.min(res.margin[v]) <= 1e-2, (sc, v)
+    _say("end-to-end mismatches (pivot / path-set / order near ties):", mism)
+    assert mism <= 3
+
+
+def test_precode_parity_and_invariants(vp):
+    for wl in (vpgen.cfg1(n_sc=16), vpgen.cfg3(512, n_sc=8)):
+        prep, paths, out, sd = run_pipeline(vp, wl)
+        x = host(vp.precode(prep.G, sd, out.l, wl.tau, out.cost, wl.n_sym))
+        xn = host(vp.precode(prep.G, sd, out.l, wl.tau, out.cost, wl.n_sym, P_T=1.0))
+        G = host(prep.G).astype(np.complex128)
+        l = l_from_gpu(host(out.l))
+        cost = host(out.cost)
+        for v in range(wl.n_vec):
+            sc = v // wl.n_sym
+            u = wl.s[:, v] + wl.tau * l[v]
+            xr = G[sc] @ u
+            assert np.abs(x[v] - xr).max() <= 1e-5 * np.abs(xr).max() * 4
+            np.testing.assert_allclose(O.mod_tau(u, wl.tau), wl.s[:, v], atol=1e-9)
+            assert math.isclose(float(np.vdot(xn[v], xn[v]).real),
+                                float(np.vdot(x[v], x[v]).real) / cost[v], rel_tol=1e-4)
+            if wl.alpha == 0.0:
+                np.testing.assert_allclose(wl.H[sc].astype(np.complex128) @ x[v], u, atol=2e-3 * np.abs(u).max())
+
+
+@pytest.mark.parametrize("N,K", [(1, 9), (2, 20), (3, 300), (5, 64), (7, 33), (12, 257), (16, 1)])
+def test_ragged_shapes(vp, N, K):
+    rng = np.random.default_rng(N * 100 + K)
+    n_sc, n_sym = 9, 5
+    H = vpgen.draw_rayleigh(rng, n_sc, N, max(N, 4))
+    s = vpgen.draw_symbols(rng, N, n_sc * n_sym, 64)
+    wl = vpgen.Workload("ragged", N, max(N, 4), n_sc, n_sym, 64, 0.1, K, H, s, 0)
+    prep, paths, out, _ = run_pipeline(vp, wl)
+    rep = check_same_input(vp, wl, prep, paths, out, range(n_sc))
+    _say(N, K, rep)
+    assert rep.ok(), rep.failures[:5]
+
+
+def test_shared_path_table_and_no_zero(vp):
+    wl = vpgen.cfg2(20, n_sc=10)
+    Hd, sd = _to_dev(wl.H), _to_dev(wl.s)
+    prep = vp.preprocess(Hd, wl.alpha)
+    table = _to_dev(O.mop_paths_kbest(np.linspace(0.1, 0.4, 8), 64).astype(np.uint8))
+    out = vp.search(prep.W, prep.perm, sd, wl.tau, table, wl.n_sym, flags=0)
+    torch.cuda.synchronize()
+    shared = host(table)[None].repeat(wl.n_sc, 0)
+    N = wl.N
+    Wd = unpack_W(host(prep.W), N)
+    perm = host(prep.perm).astype(np.int64)
+    l = l_from_gpu(host(out.l))
+    rep = ParityReport()
+    for sc in range(wl.n_sc):
+        sl = slice(sc * 14, (sc + 1) * 14)
+        check_search_subcarrier(rep, Wd[sc], perm[sc], wl.s[:, sl], wl.tau, shared[sc], False, l[sl],
+                                host(out.cost)[sl], host(out.kidx)[sl])
+    assert rep.ok(), rep.failures[:5]
+    assert np.all(host(out.kidx) < 64)
+
+
+def test_failed_subcarriers_and_degenerate_inputs(vp):
+    rng = np.random.default_rng(3)
+    N, n_sc, n_sym = 4, 6, 3
+    H = vpgen.draw_rayleigh(rng, n_sc, N, N)
+    H[1, 2, 3] = np.nan                       # non-finite channel
+    H[2, 1] = H[2, 0]                         # duplicate user rows, ZF: singular
+    H[3] = np.eye(4, dtype=np.complex64)      # identity channel: all pivots tie
+    s = vpgen.draw_symbols(rng, N, n_sc * n_sym, 16)
+    Hd, sd = _to_dev(H), _to_dev(s)
+    prep = vp.preprocess(Hd, 0.0)
+    st = host(prep.status)
+    assert st[1] == 2 and st[2] == 1 and st[0] == 0 and st[3] == 0
+    assert list(host(prep.perm)[3]) == [0, 1, 2, 3]
+    paths = vp.paths_mop(torch.where(torch.isfinite(prep.w2), prep.w2, torch.ones_like(prep.w2)), 16)
+    out = vp.search(prep.W, prep.perm, sd, 8.0, paths, n_sym)
+    torch.cuda.synchronize()
+    cost, kidx, l = host(out.cost), host(out.kidx), host(out.l)
+    for sc in (1, 2):
+        sl = slice(sc * n_sym, (sc + 1) * n_sym)
+        assert np.all(np.isnan(cost[sl])) and np.all(kidx[sl] == -1) and np.all(l[:, sl] == 0)
+    # identity channel under ZF: the problem separates, zero perturbation optimal
+    sl = slice(3 * n_sym, 4 * n_sym)
+    assert np.all(l[:, sl] == 0)
+    # empty batch is a no-op
+    e = torch.empty((0, 4, 4), dtype=torch.complex64, device=DEV)
+    vp.preprocess(e, 0.1)
+
+
+def test_errors_are_reported(vp):
+    from paper_2602_12098_amd._lib import VPError
+    wl = vpgen.cfg1(n_sc=2)
+    prep, paths, out, sd = run_pipeline(vp, wl)
+    with pytest.raises(VPError):
+        vp.paths_mop(prep.w2, 9 ** 4 + 1)
+    with pytest.raises(VPError):
+        vp.search(prep.W, prep.perm, sd, -1.0, paths, wl.n_sym)
+    with pytest.raises(VPError):
+        vp.preprocess(_to_dev(np.zeros((1, 5, 3), np.complex64)), 0.0)   # ZF with N > M
+
+
+def test_deterministic_reruns(vp):
+    wl = vpgen.cfg3(256, n_sc=16)
+    a = run_pipeline(vp, wl)
+    b = run_pipeline(vp, wl)
+    for x, y in ((a[2].l, b[2].l), (a[2].cost, b[2].cost), (a[2].kidx, b[2].kidx), (a[1], b[1]), (a[0].W, b[0].W)):
+        assert torch.equal(x, y)
