@@ -63,6 +63,7 @@ def cpu_baseline(K, budget_s=12.0):
     nv, dt = _cpu_worker(([0], 3, K))
     per_sc = dt
     n_sc = int(max(cores, min(3276, budget_s * cores / per_sc)))
+    n_sc = min(n_sc, 3275)
     scs = list(range(1, 1 + n_sc))
     chunks = [scs[i::cores] for i in range(cores)]
     t0 = time.perf_counter()
