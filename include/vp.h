@@ -100,19 +100,25 @@ int vp_preprocess(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c
  *
  * For every subcarrier, the K position vectors r in {0..8}^N (r = p - 1,
  * 0-based ranks; rank 0 is the closest child) with the smallest Metric of
- * Promise M(r) = sum_i w2_i r_i, found by the paper's breadth-first K-best
- * search.  Partial sums are formed in float64 in level order; ties in M are
- * broken by the lexicographic order of r (level 0 most significant), which
- * makes the K-best result equal to the exact K smallest.  Output order is
- * (M, lexicographic r): path k = 0 is the zero-rank (Babai) path.
+ * Promise M(r) = sum_i w2_i r_i -- the result of the paper's breadth-first
+ * K-best search over the partial metrics.  Partial sums are formed in
+ * float64 in level order; ties in M are broken by the lexicographic order of
+ * r (level 0 most significant), which makes the K-best result equal to the
+ * exact K smallest.  Output order is (M, lexicographic r): path k = 0 is the
+ * zero-rank (Babai) path.  (The kernel finds the same set by enumerating
+ * all r below a counted threshold; see the design notes.)
  *
- *  w2     [n_sc][N]     input (from vp_preprocess), finite and > 0
- *  paths  [n_sc][K][N]  output ranks 0..8, uint8
+ *  w2       [n_sc][N]     input (from vp_preprocess), finite and > 0; a
+ *                         subcarrier with any other weight gets all-zero ranks
+ *  paths    [n_sc][K][N]  output ranks 0..8, uint8
+ *  lexorder [n_sc][K]     output or NULL: lexorder[j] is the path index k of
+ *                         the j-th path in lexicographic order.  vp_search
+ *                         uses it to share the work of common path prefixes.
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, N < 1, K < 1, K > 9^N;
- * VP_EUNSUPPORTED for N > 16 or K > 4096.
+ * VP_EUNSUPPORTED for N > 16 or K > 1024.
  */
-int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, void *stream);
+int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint16_t *lexorder, void *stream);
 
 /*
  * vp_search -- per-vector evaluation of K paths and argmin (Sec. II-B PED
@@ -133,6 +139,10 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, void
  *  tau      perturbation interval 2 sqrt(Q) (Sec. II-B), > 0
  *  paths    ranks uint8; subcarrier sc uses paths + sc * paths_sc_stride,
  *           a [K][N] table (stride 0 = one table for every subcarrier)
+ *  lexorder [n_sc][K] or NULL: the tables' lexicographic order as written by
+ *           vp_paths_mop (requires paths_sc_stride == K*N).  With it, the
+ *           work of each distinct prefix of the first N/4 levels is done once
+ *           per vector instead of once per path; results are identical.
  *  l        [N][n_vec][2] output int8 (re, im) in {-1, 0, 1}, user order
  *  cost     [n_vec] output
  *  kidx     [n_vec] output, selected path (K = zero perturbation)
@@ -141,12 +151,12 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, void
  * gets l = 0, cost = NaN, kidx = -1.
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, N < 1, K < 1,
- * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N);
- * VP_EUNSUPPORTED for N > 16 or K > 4096.
+ * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N), lexorder
+ * given with paths_sc_stride != K*N; VP_EUNSUPPORTED for N > 16 or K > 4096.
  */
 int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
-              const uint8_t *paths, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
-              uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream);
+              const uint8_t *paths, const uint16_t *lexorder, int K, int64_t paths_sc_stride, int n_sc,
+              int n_sym, int n_r, uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream);
 
 /*
  * vp_precode -- precoded vector (Alg. 2 output; Sec. IV-B channel-inverse,
@@ -166,6 +176,31 @@ int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
  */
 int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, float tau, const float *cost,
                int n_sc, int n_sym, int n_r, int n_t, float P_T, vp_c32 *x, void *stream);
+
+/*
+ * vp_sphere_encode -- exact vector perturbation over the B = 1 box (eq:se,
+ * solved as the tree search of eq_qrse with the PED recursion of Sec. II-B).
+ *
+ * For every vector, the l in {-1,0,1}^2N minimising || W (s_pi + tau l) ||^2,
+ * found by a depth-first Schnorr-Euchner search (children in increasing
+ * distance to the level centre, equal distances in canonical box order).
+ * This is the reference the power gap of the K-path method is measured
+ * against, and the label generator of the learned path proposal.
+ *
+ *  W, perm, s, tau, n_sc, n_sym, n_r  as in vp_search
+ *  radius    [n_vec] initial squared radius, or NULL for none; a radius at or
+ *            slightly above a known solution's cost (e.g. vp_search's cost)
+ *            only prunes
+ *  max_nodes per-vector node budget (> 0); a vector that exhausts it, or has
+ *            no point inside its radius, gets l = 0 and cost = NaN
+ *  l         [N][n_vec][2] output, user order;  cost [n_vec] output
+ *  nodes     [n_vec] output (int64) or NULL: tree nodes visited
+ *
+ * Errors: as vp_search (no K / paths), plus max_nodes <= 0 -> VP_EINVAL.
+ */
+int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym,
+                     int n_r, const float *radius, int64_t max_nodes, int8_t *l, float *cost, int64_t *nodes,
+                     void *stream);
 
 /* Human-readable text for a return code. */
 const char *vp_strerror(int code);

@@ -1,8 +1,24 @@
-// Most-promising-path selection (Sec. III-A-2, eq_mop): the paper's
-// breadth-first K-best search over the Metric of Promise
-// M(r) = sum_i w_i r_i, one 256-thread workgroup per subcarrier.
+// Most-promising-path selection (Sec. III-A-2, eq_mop): the K position
+// vectors r in {0..8}^N with the smallest Metric of Promise
+// M(r) = sum_i w_i r_i (float64, level order), ties in lexicographic order.
+// One 256-thread workgroup per subcarrier.
 //
-// At level l the K survivors P (sorted by (M, lexicographic prefix)) expand
+// k_mop_thr (main path).  Because M is a sum of non-negative per-level
+// terms, the K smallest vectors are exactly the K smallest of
+// S(T) = {r : M(r) <= T} for any T with |S(T)| >= K, and every prefix of a
+// member of S(T) is itself a member padded with zeros.  So: (1) a counting
+// recursion over a discretised metric (each term rounded up to a grid of
+// step h, which can only under-count) picks the smallest grid threshold T
+// with at least K members, first on a coarse grid, then on a fine grid
+// below the coarse answer; (2) S(T) is enumerated level by level, keeping
+// every prefix whose partial metric is <= T (the frontier never exceeds
+// |S(T)|); (3) S(T) is bucket-sorted by M over [0, T] and each bucket sorted
+// by the exact key (M, lexicographic r); the first K are the result.  This
+// does one enumeration and one sort instead of a K-way selection per
+// level.  A subcarrier whose S(T) does not fit the buffer (clustered or
+// equal weights) is marked and handled by the K-best kernel below.
+//
+// k_mop (fallback): the paper's breadth-first K-best search.  At level l the K survivors P (sorted by (M, lexicographic prefix)) expand
 // into nine candidate lists L_r = P + w_l r, r = 0..8.  Each list is already
 // sorted, and its a-th element is preceded by at least (a+1)(r+1)-1
 // candidates, so only its first floor(K/(r+1)) elements can survive.  The
@@ -38,11 +54,14 @@ __device__ __forceinline__ void list_elem(const MopSmem &S, double wl, int r, in
     tag = (uint32_t)(S.plex[a] * 9 + r) | ((uint32_t)a << 14);
 }
 
-__global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ paths) {
+__global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ paths,
+                                            uint16_t *__restrict__ lexorder, int only_marked) {
     extern __shared__ unsigned char smem_raw[];
     MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
     const int sc = blockIdx.x;
     const int t = threadIdx.x;
+    if (only_marked && paths[(size_t)sc * K * N] != 0xFF) return;
+    __syncthreads();   // every thread has read the marker before it is overwritten
 
     if (t == 0) {
         S.pm[0] = 0.0;
@@ -162,17 +181,296 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N,
         const int k = idx / N, i = idx % N;
         out[idx] = (uint8_t)((S.pword[k] >> (4 * i)) & 15ull);
     }
+    if (lexorder)   // survivors carry their lexicographic rank
+        for (int k = t; k < K; k += kT) lexorder[(size_t)sc * K + S.plex[k]] = (uint16_t)k;
+}
+
+
+// ---------------------------------------------------------------------------
+// threshold + enumeration + bucket sort
+// ---------------------------------------------------------------------------
+
+constexpr uint8_t kRedo = 0xFF;   // first byte of a subcarrier's table: K-best must redo it
+
+// Exclusive scan of one value per thread across the workgroup; returns the
+// prefix and writes the total to *total.
+__device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratch, uint32_t *total) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t incl = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) scratch[wv] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kT / 64; ++q) {
+        const uint32_t x = scratch[q];
+        if (q < wv) base += x;
+        tot += x;
+    }
+    *total = tot;
+    __syncthreads();
+    return base + incl - v;
+}
+
+// Smallest grid index b with count(b) >= K of the rounded-up metric, on a
+// grid of step h with NB points (-1 if none); dp is [2][NB] scratch.  The
+// rounding up makes the count a lower bound of the true count at b * h.
+template <int NB>
+__device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t (*dp)[NB], int *sbest) {
+    const int t = threadIdx.x;
+    const double inv_h = (1.0 + 0x1p-40) / h;   // the tiny excess keeps every term rounded up
+    for (int b = t; b < NB; b += kT) dp[0][b] = 1u;
+    if (t == 0) *sbest = NB;
+    __syncthreads();
+    int cur = 0;
+    for (int l = N - 1; l >= 0; --l) {
+        int d[9];
+        const double wl = w[l] * inv_h;
+#pragma unroll
+        for (int r = 0; r < 9; ++r) {
+            const double x = ceil(wl * (double)r);
+            d[r] = x < (double)NB ? (int)x : NB;
+        }
+        for (int b = t; b < NB; b += kT) {
+            unsigned long long acc = 0;
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+                if (d[r] <= b) acc += dp[cur][b - d[r]];
+            dp[cur ^ 1][b] = acc > 0x7fffffffull ? 0x7fffffffu : (uint32_t)acc;
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    int mine = NB;
+    for (int b = t; b < NB; b += kT)
+        if (dp[cur][b] >= (uint32_t)K) {
+            mine = b;
+            break;
+        }
+    atomicMin(sbest, mine);
+    __syncthreads();
+    const int r = *sbest;
+    __syncthreads();
+    return r < NB ? r : -1;
+}
+
+constexpr int kNB = 512;   // grid points of the counting recursion
+
+template <int CAP>
+struct ThrSmem {
+    double fm[CAP];               // S(T) members / frontier: metric
+    unsigned long long fw[CAP];   // rank nibbles (level i at bits 4i), later the lexicographic key
+    uint16_t fe[CAP];             // enumeration (= lexicographic) position, carried through the sort
+    uint16_t rank_of[CAP];        // enumeration position -> MoP rank (or 0xffff beyond K)
+    uint32_t dp[2][kNB];          // counting recursion; later bucket starts / cursors
+    double w[kMaxN];
+    uint32_t scan[kT / 64];
+    int best;
+};
+
+template <int CAP>
+__global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, int N, int K,
+                                                uint8_t *__restrict__ paths, uint16_t *__restrict__ lexorder) {
+    constexpr int PER = CAP / kT;   // frontier entries held per thread
+    extern __shared__ unsigned char smem_raw[];
+    ThrSmem<CAP> &S = *reinterpret_cast<ThrSmem<CAP> *>(smem_raw);
+    const int sc = blockIdx.x;
+    const int t = threadIdx.x;
+    uint8_t *out = paths + (size_t)sc * K * N;
+
+    if (t < N) S.w[t] = (double)w2[(size_t)sc * N + t];
+    __syncthreads();
+    bool valid = true;
+    double wsum = 0.0;
+    for (int i = 0; i < N; ++i) {
+        valid &= (S.w[i] > 0.0) && isfinite(S.w[i]);
+        wsum += S.w[i];
+    }
+    if (!valid) {   // failed preprocessing: a deterministic all-zero table
+        for (int idx = t; idx < K * N; idx += kT) out[idx] = 0;
+        if (lexorder)
+            for (int k = t; k < K; k += kT) lexorder[(size_t)sc * K + k] = (uint16_t)k;
+        return;
+    }
+    // (1) threshold on a coarse grid over the whole range, then a finer one
+    const double h0 = 8.0 * wsum / (double)(kNB - 1);
+    const int b0 = dp_threshold<kNB>(S.w, N, K, h0, S.dp, &S.best);
+    double T = (b0 < 0 ? (double)(kNB - 1) : (double)b0) * h0;
+    if (b0 > 0) {
+        const double h1 = 1.25 * T / (double)(kNB - 1);
+        const int b1 = dp_threshold<kNB>(S.w, N, K, h1, S.dp, &S.best);
+        if (b1 >= 0) T = (double)b1 * h1;
+    }
+    // (2) enumerate S(T) level by level, in place: every thread first takes its
+    // contiguous share of the frontier into registers, then writes the children
+    if (t == 0) {
+        S.fm[0] = 0.0;
+        S.fw[0] = 0ull;
+    }
+    uint32_t n = 1;
+    bool fail = false;
+    __syncthreads();
+    for (int l = 0; l < N; ++l) {
+        const double wl = S.w[l];
+        const uint32_t chunk = (n + kT - 1) / kT;
+        const uint32_t j0 = t * chunk;
+        double m[PER];
+        unsigned long long wd[PER];
+        int R[PER];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            R[q] = 0;
+            if ((uint32_t)q < chunk && j0 + q < n) {
+                m[q] = S.fm[j0 + q];
+                wd[q] = S.fw[j0 + q];
+                int r = 1;
+                while (r < 9 && m[q] + wl * (double)r <= T) ++r;
+                R[q] = r;
+                cnt += r;
+            }
+        }
+        uint32_t total;
+        uint32_t off = block_scan_excl(cnt, S.scan, &total);   // also a barrier: all reads done
+        if (total > (uint32_t)CAP) {
+            fail = true;
+            break;
+        }
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            for (int r = 0; r < R[q]; ++r) {
+                S.fm[off] = m[q] + wl * (double)r;
+                S.fw[off] = wd[q] | ((unsigned long long)r << (4 * l));
+                ++off;
+            }
+        __syncthreads();
+        n = total;
+    }
+    if (fail || n < (uint32_t)K) {
+        if (t == 0) out[0] = kRedo;
+        return;
+    }
+    // (3) bucket sort by M over [0, T], then exact (M, lexicographic r) inside buckets
+    const double scale = T > 0.0 ? (double)kNB / T : 0.0;
+    for (int b = t; b < kNB; b += kT) S.dp[0][b] = 0u;
+    double m[PER];
+    unsigned long long lex[PER];
+    int bk[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const uint32_t j = t + q * kT;
+        bk[q] = -1;
+        if (j < n) {
+            S.rank_of[j] = 0xffff;
+            m[q] = S.fm[j];
+            const unsigned long long wd = S.fw[j];
+            unsigned long long x = 0;   // level 0 in the most significant nibble
+            for (int i = 0; i < N; ++i) x |= ((wd >> (4 * i)) & 15ull) << (4 * (N - 1 - i));
+            lex[q] = x;
+            bk[q] = min(kNB - 1, (int)(m[q] * scale));
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (bk[q] >= 0) atomicAdd(&S.dp[0][bk[q]], 1u);
+    __syncthreads();
+    {
+        constexpr int BPT = kNB / kT;
+        uint32_t loc = 0;
+        for (int q = 0; q < BPT; ++q) loc += S.dp[0][t * BPT + q];
+        uint32_t tot;
+        uint32_t base = block_scan_excl(loc, S.scan, &tot);
+        for (int q = 0; q < BPT; ++q) {
+            const uint32_t c = S.dp[0][t * BPT + q];
+            S.dp[0][t * BPT + q] = base;   // bucket start
+            S.dp[1][t * BPT + q] = base;   // fill cursor
+            base += c;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (bk[q] >= 0) {
+            const uint32_t pos = atomicAdd(&S.dp[1][bk[q]], 1u);
+            S.fm[pos] = m[q];
+            S.fw[pos] = lex[q];
+            S.fe[pos] = (uint16_t)(t + q * kT);
+        }
+    __syncthreads();
+    for (int b = t; b < kNB; b += kT) {
+        const uint32_t lo = S.dp[0][b], hi = S.dp[1][b];
+        for (uint32_t a = lo + 1; a < hi; ++a) {   // insertion sort on (M, lex)
+            const double mm = S.fm[a];
+            const unsigned long long x = S.fw[a];
+            const uint16_t e = S.fe[a];
+            uint32_t c = a;
+            while (c > lo && (S.fm[c - 1] > mm || (S.fm[c - 1] == mm && S.fw[c - 1] > x))) {
+                S.fm[c] = S.fm[c - 1];
+                S.fw[c] = S.fw[c - 1];
+                S.fe[c] = S.fe[c - 1];
+                --c;
+            }
+            S.fm[c] = mm;
+            S.fw[c] = x;
+            S.fe[c] = e;
+        }
+    }
+    __syncthreads();
+    for (int idx = t; idx < K * N; idx += kT) {
+        const int k = idx / N, i = idx % N;
+        out[idx] = (uint8_t)((S.fw[k] >> (4 * (N - 1 - i))) & 15ull);
+    }
+    if (lexorder) {
+        // the enumeration visited S(T) in lexicographic order: the selected
+        // paths, in enumeration order, are the path table in lexicographic order
+        for (int k = t; k < K; k += kT) S.rank_of[S.fe[k]] = (uint16_t)k;
+        __syncthreads();
+        uint32_t sel[PER];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const uint32_t j = t * PER + q;
+            sel[q] = (j < n && S.rank_of[j] != 0xffff) ? 1u : 0u;
+            cnt += sel[q];
+        }
+        uint32_t tot;
+        uint32_t pos = block_scan_excl(cnt, S.scan, &tot);
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (sel[q]) lexorder[(size_t)sc * K + pos++] = S.rank_of[t * PER + q];
+    }
 }
 
 }  // namespace
 
-int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, hipStream_t st) {
+int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *lexorder, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
-    const size_t smem = sizeof(MopSmem);
-    static const int attr_once =
-        (hipFuncSetAttribute((const void *)k_mop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem), 0);
+    static const int attr_once = (
+        hipFuncSetAttribute((const void *)k_mop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(MopSmem)),
+        hipFuncSetAttribute((const void *)k_mop_thr<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(ThrSmem<1024>)),
+        hipFuncSetAttribute((const void *)k_mop_thr<2048>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(ThrSmem<2048>)),
+        0);
     (void)attr_once;
-    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), smem, st, w2, N, K, paths);
+    if (K <= 512)
+        hipLaunchKernelGGL(k_mop_thr<1024>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<1024>), st, w2, N, K, paths,
+                           lexorder);
+    else
+        hipLaunchKernelGGL(k_mop_thr<2048>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<2048>), st, w2, N, K, paths,
+                           lexorder);
+    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, lexorder, 1);
+    return launch_status();
+}
+
+int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *lexorder, hipStream_t st) {
+    if (n_sc == 0) return VP_OK;
+    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, lexorder, 0);
     return launch_status();
 }
 

@@ -43,8 +43,11 @@ __device__ __forceinline__ float2 stilde_over_tau(const float2 *__restrict__ Wc,
     return make_float2(re * inv_tau, im * inv_tau);
 }
 
-// Walk one path.  r: residuals / tau (in: s-tilde / tau, destroyed), linv_i =
-// 1 / W_ii, wdiag_i = W_ii.  Returns sum_i |r_i + W_ii l_i|^2; with REC the chosen offsets.
+// Walk one path over levels [LO, HI).  r: residuals / tau (in: their values
+// after level LO-1, destroyed), linv_i = 1 / W_ii, wdiag_i = W_ii, ped: the
+// PED so far.  Returns ped + sum_{LO<=i<HI} |r_i + W_ii l_i|^2; with REC the
+// chosen offsets.  A walk split into consecutive ranges performs exactly the
+// arithmetic of the whole walk.
 // Hides a wave-uniform pointer from loop-invariant code motion, so that the W
 // column of each level is scalar-loaded where it is used instead of all 240
 // coefficients being hoisted (and spilled) at once.  Loads through the
@@ -59,13 +62,13 @@ __device__ __forceinline__ cfloat *opaque_uniform(const float2 *p, float after) 
     return (cfloat *)p;
 }
 
-template <int N, bool UNIFORM_TIERS, bool REC>
+template <int N, bool UNIFORM_TIERS, bool REC, int LO = 0, int HI = N>
 __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float *linv, const float *wdiag, float2 (&r)[N],
-                                      unsigned long long word, const uint8_t *lut, float *ra, float *rb) {
+                                      unsigned long long word, const uint8_t *lut, float *ra, float *rb,
+                                      float ped = 0.f) {
     constexpr int CH = 4;   // W rows per scalar load (8 dwords)
-    float ped = 0.f;
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int i = LO; i < HI; ++i) {
         const int rank = (int)((word >> (4 * i)) & 15ull);
         const float li = linv[i];
         const float cx = -(r[i].x * li);
@@ -207,6 +210,156 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
     }
 }
 
+// Prefix-sharing search (paths given in lexicographic order by `lexorder`).
+// Stage 1: each distinct prefix of levels [0, P1) is walked once, one lane per
+// prefix, and its residuals below P1 and its PED are kept in LDS.  Stage 2:
+// each path continues from its prefix's state over levels [P1, N).  More
+// than kMaxPrefix distinct prefixes (an unusual table) -> every path is
+// walked from the root instead.  Same per-path arithmetic as a direct walk.
+constexpr int kTT = 128;          // threads of the prefix-sharing search
+constexpr int kMaxPrefix = kTT;   // stage-1 prefixes held in LDS
+
+template <int N>
+constexpr int prefix_levels() { return N >= 4 ? N / 4 : 0; }
+
+template <int N>
+__global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                                     const float2 *__restrict__ s, float tau,
+                                                     const uint8_t *__restrict__ paths,
+                                                     const uint16_t *__restrict__ lexorder, int K,
+                                                     long long pstride, int n_sym, unsigned flags,
+                                                     float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
+    constexpr int P1 = prefix_levels<N>();
+    constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
+    extern __shared__ unsigned long long s_words[];   // [K] rank nibbles, lexicographic order
+    uint16_t *s_k = reinterpret_cast<uint16_t *>(s_words + K);     // [K] path index of lex position
+    uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of lex position
+    __shared__ float s_state[kMaxPrefix * SW];
+    __shared__ uint16_t s_first[kMaxPrefix];   // first lex position of each prefix
+    __shared__ float2 s_r0[N];
+    __shared__ float s_linv[N];
+    __shared__ float s_wdiag[N];
+    __shared__ uint8_t s_perm[N];
+    __shared__ uint32_t s_scan[kTT / 64];
+    __shared__ unsigned long long s_red[kTT / 64];
+
+    constexpr int NP = VP_PACKED(N);
+    const size_t v = blockIdx.x;
+    const int sc = (int)(v / n_sym);
+    const int t = threadIdx.x;
+    const size_t n_vec = (size_t)gridDim.x;
+    const float2 *__restrict__ Wc = W + (size_t)sc * NP;
+    const float w00 = Wc[0].x;
+    if (!(w00 > 0.f) || !isfinite(w00)) {
+        if (t == 0) {
+            cost_out[v] = __int_as_float(0x7fc00000);
+            kidx_out[v] = -1;
+        }
+        return;
+    }
+    const uint8_t *P = paths + (size_t)sc * pstride;
+    const uint16_t *LX = lexorder + (size_t)sc * K;
+    if (t < N) {
+        s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
+        s_linv[t] = 1.0f / s_wdiag[t];
+        s_perm[t] = perm[(size_t)sc * N + t];
+    }
+    for (int j = t; j < K; j += kTT) {
+        int k = LX[j];
+        k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
+        s_k[j] = (uint16_t)k;
+        s_words[j] = load_word<N>(P, k);
+    }
+    __syncthreads();
+    if (t < N) s_r0[t] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, t, 1.0f / tau);
+    // prefix boundaries: contiguous chunk of lex positions per thread, then a block scan
+    constexpr unsigned long long PMASK = P1 >= 16 ? ~0ull : ((1ull << (4 * P1)) - 1ull);
+    const int chunk = (K + kTT - 1) / kTT;
+    const int j0 = t * chunk, j1 = min(K, j0 + chunk);
+    uint32_t cnt = 0;
+    for (int j = j0; j < j1; ++j)
+        cnt += (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull) ? 1u : 0u;
+    uint32_t incl = cnt;
+    {
+        const int lane = t & 63, wv = t >> 6;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) s_scan[wv] = incl;
+        __syncthreads();
+        for (int q = 0; q < wv; ++q) incl += s_scan[q];
+    }
+    const uint32_t n1 = s_scan[0] + (kTT / 64 > 1 ? s_scan[1] : 0);
+    uint32_t node = incl - cnt;
+    for (int j = j0; j < j1; ++j) {
+        const bool start = (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull);
+        if (start) {
+            if (node < (uint32_t)kMaxPrefix) s_first[node] = (uint16_t)j;
+            ++node;
+        }
+        s_node[j] = (uint16_t)(node - 1);
+    }
+    __syncthreads();
+    const float tau2 = tau * tau;
+    unsigned long long best = ~0ull;
+    if (P1 > 0 && n1 <= (uint32_t)kMaxPrefix) {
+        if (t < (int)n1) {   // stage 1: one lane per distinct prefix
+            float2 r[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) r[i] = s_r0[i];
+            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_first[t]],
+                                                           VP_DEMAP_LUT, nullptr, nullptr);
+            float *st = s_state + t * SW;
+#pragma unroll
+            for (int i = P1; i < N; ++i) {
+                st[2 * (i - P1)] = r[i].x;
+                st[2 * (i - P1) + 1] = r[i].y;
+            }
+            st[SW - 1] = ped;
+        }
+        __syncthreads();
+        for (int j = t; j < K; j += kTT) {   // stage 2: every path from its prefix
+            const float *st = s_state + s_node[j] * SW;
+            float2 r[N];
+#pragma unroll
+            for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
+#pragma unroll
+            for (int i = P1; i < N; ++i) r[i] = make_float2(st[2 * (i - P1)], st[2 * (i - P1) + 1]);
+            const float ped = walk<N, true, false, P1, N>(Wc, s_linv, s_wdiag, r, s_words[j], VP_DEMAP_LUT,
+                                                           nullptr, nullptr, st[SW - 1]);
+            best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)s_k[j]);
+        }
+    } else {
+        for (int j = t; j < K; j += kTT) {
+            float2 r[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) r[i] = s_r0[i];
+            const float ped = walk<N, true, false>(Wc, s_linv, s_wdiag, r, s_words[j], VP_DEMAP_LUT, nullptr,
+                                                   nullptr);
+            best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)s_k[j]);
+        }
+    }
+    if ((flags & VP_INCLUDE_ZERO) && t == 0) {
+        float z = 0.f;
+        for (int i = 0; i < N; ++i) {
+            z = fmaf(s_r0[i].x, s_r0[i].x, z);
+            z = fmaf(s_r0[i].y, s_r0[i].y, z);
+        }
+        best = umin64(best, ((unsigned long long)__float_as_uint(z * tau2) << 32) | (unsigned)K);
+    }
+    best = wave_min(best);
+    if ((t & 63) == 0) s_red[t >> 6] = best;
+    __syncthreads();
+    if (t == 0) {
+        unsigned long long b = s_red[0];
+        for (int w = 1; w < kTT / 64; ++w) b = umin64(b, s_red[w]);
+        cost_out[v] = __uint_as_float((unsigned)(b >> 32));
+        kidx_out[v] = (int32_t)(b & 0xffffffffull);
+    }
+}
+
 template <int N>
 __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict__ W,
                                                         const uint8_t *__restrict__ perm,
@@ -251,12 +404,22 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
 }
 
 template <int N>
-int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths, int K,
-                    int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l, float *cost, int32_t *kidx,
-                    hipStream_t st) {
+int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+                    const uint16_t *lexorder, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
+                    float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
-    hipLaunchKernelGGL(k_search<N>, dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
-                       (long long)pstride, n_sym, flags, cost, kidx);
+    if (lexorder) {
+        const size_t smem = (size_t)K * (sizeof(unsigned long long) + 2 * sizeof(uint16_t));
+        static const int attr_once = (hipFuncSetAttribute((const void *)k_search_trie<N>,
+                                                          hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024),
+                                      0);
+        (void)attr_once;
+        hipLaunchKernelGGL(k_search_trie<N>, dim3((unsigned)n_vec), dim3(kTT), smem, st, W, perm, s, tau, paths,
+                           lexorder, K, (long long)pstride, n_sym, flags, cost, kidx);
+    } else {
+        hipLaunchKernelGGL(k_search<N>, dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
+                           (long long)pstride, n_sym, flags, cost, kidx);
+    }
     hipLaunchKernelGGL(k_search_finalize<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
                        tau, paths, K, (long long)pstride, n_sc, n_sym, kidx, l);
     return launch_status();
@@ -264,13 +427,15 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
 
 }  // namespace
 
-int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths, int K,
-                  int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags, int8_t *l, float *cost,
-                  int32_t *kidx, hipStream_t st) {
+int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+                  const uint16_t *lexorder, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
+                  int8_t *l, float *cost, int32_t *kidx, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
     switch (N) {
-#define VP_CASE(n) \
-    case n: return launch_search_n<n>(W, perm, s, tau, paths, K, pstride, n_sc, n_sym, flags, l, cost, kidx, st);
+#define VP_CASE(n)                                                                                            \
+    case n:                                                                                                   \
+        return launch_search_n<n>(W, perm, s, tau, paths, lexorder, K, pstride, n_sc, n_sym, flags, l, cost, \
+                                  kidx, st);
         VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
         VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
 #undef VP_CASE

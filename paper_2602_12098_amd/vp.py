@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import VP_INCLUDE_ZERO, check
 
-__all__ = ["Prep", "SearchOut", "preprocess", "paths_mop", "search", "precode", "packed_size",
+__all__ = ["Prep", "SearchOut", "SEOut", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
            "VP_INCLUDE_ZERO", "version"]
 
 
@@ -74,21 +74,26 @@ def preprocess(H: torch.Tensor, alpha: float, want_G: bool = True, out: Optional
     return out
 
 
-def paths_mop(w2: torch.Tensor, K: int, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """vp_paths_mop: w2 float32 [n_sc][N] -> paths uint8 [n_sc][K][N]."""
+def paths_mop(w2: torch.Tensor, K: int, out: Optional[torch.Tensor] = None,
+              lexorder: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vp_paths_mop: w2 float32 [n_sc][N] -> paths uint8 [n_sc][K][N].  If `lexorder`
+    (int16 [n_sc][K], read as uint16) is given it receives the lexicographic order."""
     lib = _lib.load()
     n_sc, N = w2.shape
     if out is None:
         out = torch.empty((n_sc, K, N), dtype=torch.uint8, device=w2.device)
     pw = _req(w2, "w2", torch.float32)
     po = _req(out, "paths", torch.uint8, (n_sc, K, N))
-    check(lib.vp_paths_mop(pw, n_sc, N, int(K), po, _stream()), "vp_paths_mop")
+    pl = _req(lexorder, "lexorder", torch.int16, (n_sc, K)) if lexorder is not None else None
+    check(lib.vp_paths_mop(pw, n_sc, N, int(K), po, pl, _stream()), "vp_paths_mop")
     return out
 
 
 def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
-           n_sym: int, flags: int = VP_INCLUDE_ZERO, out: Optional[SearchOut] = None) -> SearchOut:
-    """vp_search: paths is [K][N] (one table for all subcarriers) or [n_sc][K][N]."""
+           n_sym: int, flags: int = VP_INCLUDE_ZERO, out: Optional[SearchOut] = None,
+           lexorder: Optional[torch.Tensor] = None) -> SearchOut:
+    """vp_search: paths is [K][N] (one table for all subcarriers) or [n_sc][K][N];
+    lexorder (int16 [n_sc][K] from paths_mop) enables prefix sharing."""
     lib = _lib.load()
     n_sc = W.shape[0]
     N = perm.shape[1]
@@ -113,7 +118,8 @@ def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, pat
     pl = _req(out.l, "l", torch.int8, (N, n_vec, 2))
     pc = _req(out.cost, "cost", torch.float32, (n_vec,))
     pk = _req(out.kidx, "kidx", torch.int32, (n_vec,))
-    check(lib.vp_search(pW, pp, ps, float(tau), pP, int(K), int(stride), n_sc, int(n_sym), N, int(flags),
+    plx = _req(lexorder, "lexorder", torch.int16, (n_sc, K)) if lexorder is not None else None
+    check(lib.vp_search(pW, pp, ps, float(tau), pP, plx, int(K), int(stride), n_sc, int(n_sym), N, int(flags),
                         pl, pc, pk, _stream()), "vp_search")
     return out
 
@@ -138,3 +144,34 @@ def precode(G: torch.Tensor, s: torch.Tensor, l: torch.Tensor, tau: float, cost:
 
 def version() -> str:
     return _lib.load().vp_version().decode()
+
+
+class SEOut(NamedTuple):
+    l: torch.Tensor       # int8 [N][n_vec][2]
+    cost: torch.Tensor    # float32 [n_vec] (NaN: no point inside the radius / budget exhausted)
+    nodes: torch.Tensor   # int64 [n_vec]
+
+
+def sphere_encode(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, n_sym: int,
+                  radius: Optional[torch.Tensor] = None, max_nodes: int = 1 << 22,
+                  out: Optional[SEOut] = None) -> SEOut:
+    """vp_sphere_encode: exact VP over the box (optionally seeded with a radius)."""
+    lib = _lib.load()
+    n_sc = W.shape[0]
+    N = perm.shape[1]
+    n_vec = n_sc * n_sym
+    dev = W.device
+    if out is None:
+        out = SEOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
+                    torch.empty((n_vec,), dtype=torch.float32, device=dev),
+                    torch.empty((n_vec,), dtype=torch.int64, device=dev))
+    pW = _req(W, "W", torch.complex64, (n_sc, packed_size(N)))
+    pp = _req(perm, "perm", torch.uint8, (n_sc, N))
+    ps = _req(s, "s", torch.complex64, (N, n_vec))
+    pr = _req(radius, "radius", torch.float32, (n_vec,)) if radius is not None else None
+    pl = _req(out.l, "l", torch.int8, (N, n_vec, 2))
+    pc = _req(out.cost, "cost", torch.float32, (n_vec,))
+    pn = _req(out.nodes, "nodes", torch.int64, (n_vec,))
+    check(lib.vp_sphere_encode(pW, pp, ps, float(tau), n_sc, int(n_sym), N, pr, int(max_nodes), pl, pc, pn,
+                               _stream()), "vp_sphere_encode")
+    return out

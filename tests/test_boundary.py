@@ -53,18 +53,18 @@ def test_argument_validation(lib):
     assert lib.vp_preprocess(None, 0, 4, 4, 0.1, None, None, None, None, None, None) == VP_OK
     assert lib.vp_preprocess(None, -1, 4, 4, 0.1, None, None, None, None, None, None) == VP_EINVAL
     # vp_paths_mop
-    assert lib.vp_paths_mop(None, 1, 2, 82, None, None) == VP_EINVAL          # K > 9^2
-    assert lib.vp_paths_mop(None, 1, 16, 1025, None, None) == VP_EUNSUPPORTED
-    assert lib.vp_paths_mop(None, 1, 16, 0, None, None) == VP_EINVAL
-    assert lib.vp_paths_mop(None, 0, 4, 32, None, None) == VP_OK
-    assert lib.vp_paths_mop(None, 3, 4, 32, None, None) == VP_EINVAL          # null pointers
+    assert lib.vp_paths_mop(None, 1, 2, 82, None, None, None) == VP_EINVAL          # K > 9^2
+    assert lib.vp_paths_mop(None, 1, 16, 1025, None, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_paths_mop(None, 1, 16, 0, None, None, None) == VP_EINVAL
+    assert lib.vp_paths_mop(None, 0, 4, 32, None, None, None) == VP_OK
+    assert lib.vp_paths_mop(None, 3, 4, 32, None, None, None) == VP_EINVAL          # null pointers
     # vp_search
     args = dict(tau=8.0, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1)
 
     def search(**kw):
         a = dict(args, **kw)
-        return lib.vp_search(None, None, None, a["tau"], None, a["K"], a["stride"], a["n_sc"], a["n_sym"],
-                             a["N"], a["flags"], None, None, None, None)
+        return lib.vp_search(None, None, None, a["tau"], None, a.get("lex"), a["K"], a["stride"], a["n_sc"],
+                             a["n_sym"], a["N"], a["flags"], None, None, None, None)
     assert search() == VP_EINVAL
     assert search(n_sc=0) == VP_OK
     assert search(tau=0.0, n_sc=0) == VP_EINVAL
@@ -75,6 +75,7 @@ def test_argument_validation(lib):
     assert search(stride=-1, n_sc=0) == VP_EINVAL
     assert search(flags=2, n_sc=0) == VP_EINVAL
     assert search(n_sym=0, n_sc=0) == VP_EINVAL
+    assert search(lex=1, stride=0, n_sc=0) == VP_EINVAL       # lexorder needs a per-subcarrier table
     # vp_precode
     assert lib.vp_precode(None, None, None, 8.0, None, 0, 14, 4, 4, 0.0, None, None) == VP_OK
     assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 4, 4, 1.0, None, None) == VP_EINVAL

@@ -35,7 +35,8 @@ def _to_dev(x):
     return torch.from_numpy(np.ascontiguousarray(x)).to(DEV)
 
 
-def run_pipeline(vp, wl, K=None, want_G=True, include_zero=True, H=None, s=None, n_sym=None, alpha=None):
+def run_pipeline(vp, wl, K=None, want_G=True, include_zero=True, H=None, s=None, n_sym=None, alpha=None,
+                 shared_prefix=True):
     K = K or wl.K
     H = wl.H if H is None else H
     s = wl.s if s is None else s
@@ -43,9 +44,10 @@ def run_pipeline(vp, wl, K=None, want_G=True, include_zero=True, H=None, s=None,
     alpha = wl.alpha if alpha is None else alpha
     Hd, sd = _to_dev(H), _to_dev(s)
     prep = vp.preprocess(Hd, alpha, want_G=want_G)
-    paths = vp.paths_mop(prep.w2, K)
+    lex = torch.empty((H.shape[0], K), dtype=torch.int16, device=DEV) if shared_prefix else None
+    paths = vp.paths_mop(prep.w2, K, lexorder=lex)
     flags = vp.VP_INCLUDE_ZERO if include_zero else 0
-    out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, n_sym, flags=flags)
+    out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, n_sym, flags=flags, lexorder=lex)
     torch.cuda.synchronize()
     return prep, paths, out, sd
 
@@ -311,3 +313,82 @@ def test_deterministic_reruns(vp):
     b = run_pipeline(vp, wl)
     for x, y in ((a[2].l, b[2].l), (a[2].cost, b[2].cost), (a[2].kidx, b[2].kidx), (a[1], b[1]), (a[0].W, b[0].W)):
         assert torch.equal(x, y)
+
+
+def test_paths_mop_clustered_weights_use_fallback(vp):
+    # 16 equal weights: with K = 1024 the threshold set holds C(20,4) = 4845
+    # vectors, more than the enumeration buffer -> the K-best kernel redoes it.
+    for K in (512, 1024):
+        w = torch.full((2, 16), 0.3, dtype=torch.float32, device=DEV)
+        p = host(vp.paths_mop(w, K))
+        ref = O.mop_paths_kbest(np.full(16, np.float32(0.3)).astype(np.float64), K)
+        assert np.array_equal(p[0], ref) and np.array_equal(p[1], ref), K
+
+
+def test_paths_mop_invalid_weights_give_zero_table(vp):
+    w = torch.tensor([[0.2, float("inf"), 0.3], [0.1, 0.2, 0.3]], dtype=torch.float32, device=DEV)
+    p = host(vp.paths_mop(w, 10))
+    assert np.all(p[0] == 0)
+    assert np.array_equal(p[1], O.mop_paths_kbest(np.array([0.1, 0.2, 0.3], np.float32).astype(np.float64), 10))
+
+
+def test_sphere_encoder_matches_oracle(vp):
+    from oracle import se_c
+    for wl, K in ((vpgen.cfg1(n_sc=16), 32), (vpgen.cfg2(20, n_sc=8), 64), (vpgen.cfg3(512, n_sc=6), 512)):
+        _say("se", wl.name)
+        prep, paths, out, sd = run_pipeline(vp, wl)
+        Wd = unpack_W(host(prep.W), wl.N)
+        perm = host(prep.perm).astype(np.int64)
+        wsel = np.repeat(np.arange(wl.n_sc), wl.n_sym).astype(np.int32)
+        lo, co, _ = se_c.sphere_encode_batch(Wd, perm, wl.s, wl.tau, wsel=wsel)
+        for seeded in (False, True):
+            rad = out.cost * (1 + 1e-5) if seeded else None
+            se = vp.sphere_encode(prep.W, prep.perm, sd, wl.tau, wl.n_sym, radius=rad)
+            torch.cuda.synchronize()
+            lg = l_from_gpu(host(se.l))
+            cg = host(se.cost)
+            assert np.all(np.isfinite(cg))
+            ties = 0
+            for v in range(wl.n_vec):
+                c64 = O.cost_tri(Wd[v // wl.n_sym], perm[v // wl.n_sym], wl.s[:, v], lg[v], wl.tau)
+                assert abs(cg[v] - c64) <= 1e-5 * c64
+                if not np.array_equal(lg[v], lo[v]):
+                    assert abs(c64 - co[v]) <= 1e-5 * co[v], (v, c64, co[v])
+                    ties += 1
+            _say("  seeded" if seeded else "  unseeded", "cost ties:", ties, "nodes median",
+                 float(np.median(host(se.nodes))))
+            # exact VP is never worse than the K-path search
+            assert np.all(cg <= host(out.cost) * (1 + 1e-5))
+
+
+def test_paths_mop_lexorder(vp):
+    for wl, K in ((vpgen.cfg3(512, n_sc=10), 512), (vpgen.cfg1(n_sc=6), 32)):
+        Hd = _to_dev(wl.H)
+        prep = vp.preprocess(Hd, wl.alpha)
+        lo = torch.empty((wl.n_sc, K), dtype=torch.int16, device=DEV)
+        P = host(vp.paths_mop(prep.w2, K, lexorder=lo))
+        L = host(lo).astype(np.int64) & 0xffff
+        for sc in range(wl.n_sc):
+            assert sorted(L[sc].tolist()) == list(range(K))
+            rows = [tuple(P[sc, k]) for k in L[sc]]
+            assert rows == sorted(rows)
+    # the K-best fallback produces it too (16 equal weights, K = 1024)
+    w = torch.full((1, 16), 0.3, dtype=torch.float32, device=DEV)
+    lo = torch.empty((1, 1024), dtype=torch.int16, device=DEV)
+    P = host(vp.paths_mop(w, 1024, lexorder=lo))
+    L = host(lo).astype(np.int64) & 0xffff
+    rows = [tuple(P[0, k]) for k in L[0]]
+    assert rows == sorted(rows) and sorted(L[0].tolist()) == list(range(1024))
+
+
+@pytest.mark.parametrize("N,K", [(16, 512), (8, 64), (4, 32), (12, 300), (3, 50)])
+def test_prefix_sharing_is_bit_identical(vp, N, K):
+    # the prefix-sharing search and the plain per-path search give identical bits
+    rng = np.random.default_rng(7 * N + K)
+    n_sc, n_sym = 12, 7
+    H = vpgen.draw_correlated(rng, n_sc, N, N, 0.5) if N > 3 else vpgen.draw_rayleigh(rng, n_sc, N, N)
+    s = vpgen.draw_symbols(rng, N, n_sc * n_sym, 256)
+    wl = vpgen.Workload("pfx", N, N, n_sc, n_sym, 256, 0.1, K, H, s, 0)
+    a = run_pipeline(vp, wl, shared_prefix=True)
+    b = run_pipeline(vp, wl, shared_prefix=False)
+    assert torch.equal(a[2].cost, b[2].cost) and torch.equal(a[2].kidx, b[2].kidx) and torch.equal(a[2].l, b[2].l)
