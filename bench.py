@@ -106,6 +106,7 @@ def main():
                    torch.empty((n_sc, M, N), dtype=torch.complex64, device=dev),
                    torch.empty((n_sc,), dtype=torch.int32, device=dev))
     paths = torch.empty((n_sc, K, N), dtype=torch.uint8, device=dev)
+    lexo = torch.empty((n_sc, K), dtype=torch.int16, device=dev)
     sout = vp.SearchOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
                         torch.empty((n_vec,), dtype=torch.float32, device=dev),
                         torch.empty((n_vec,), dtype=torch.int32, device=dev))
@@ -115,9 +116,9 @@ def main():
         if ev: ev[0].record()
         vp.preprocess(H, wl.alpha, out=prep)
         if ev: ev[1].record()
-        vp.paths_mop(prep.w2, K, out=paths)
+        vp.paths_mop(prep.w2, K, out=paths, lexorder=lexo)
         if ev: ev[2].record()
-        vp.search(prep.W, prep.perm, s, wl.tau, paths, n_sym, out=sout)
+        vp.search(prep.W, prep.perm, s, wl.tau, paths, n_sym, out=sout, lexorder=lexo)
         if ev: ev[3].record()
         vp.precode(prep.G, s, sout.l, wl.tau, sout.cost, n_sym, P_T=1.0, out=x)
         if ev: ev[4].record()
@@ -145,7 +146,7 @@ def main():
     achieved = flops / (stage["search"] * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
-            "kernel": "vp_search (k_search + k_search_finalize)",
+            "kernel": "vp_search (k_search_trie + k_search_finalize)",
             "work": f"{search_cm_per_vector(M, K)} complex mult/vector x {FLOP_PER_CM} flop x {n_vec} vectors"}
 
     line = {
