@@ -106,7 +106,7 @@ def main():
                    torch.empty((n_sc, M, N), dtype=torch.complex64, device=dev),
                    torch.empty((n_sc,), dtype=torch.int32, device=dev))
     paths = torch.empty((n_sc, K, N), dtype=torch.uint8, device=dev)
-    lexo = torch.empty((n_sc, K), dtype=torch.int16, device=dev)
+    order = torch.empty((n_sc, 2, K), dtype=torch.int16, device=dev)
     sout = vp.SearchOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
                         torch.empty((n_vec,), dtype=torch.float32, device=dev),
                         torch.empty((n_vec,), dtype=torch.int32, device=dev))
@@ -116,9 +116,9 @@ def main():
         if ev: ev[0].record()
         vp.preprocess(H, wl.alpha, out=prep)
         if ev: ev[1].record()
-        vp.paths_mop(prep.w2, K, out=paths, lexorder=lexo)
+        vp.paths_mop(prep.w2, K, out=paths, order=order)
         if ev: ev[2].record()
-        vp.search(prep.W, prep.perm, s, wl.tau, paths, n_sym, out=sout, lexorder=lexo)
+        vp.search(prep.W, prep.perm, s, wl.tau, paths, n_sym, out=sout, order=order)
         if ev: ev[3].record()
         vp.precode(prep.G, s, sout.l, wl.tau, sout.cost, n_sym, P_T=1.0, out=x)
         if ev: ev[4].record()

@@ -111,14 +111,18 @@ int vp_preprocess(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c
  *  w2       [n_sc][N]     input (from vp_preprocess), finite and > 0; a
  *                         subcarrier with any other weight gets all-zero ranks
  *  paths    [n_sc][K][N]  output ranks 0..8, uint8
- *  lexorder [n_sc][K]     output or NULL: lexorder[j] is the path index k of
- *                         the j-th path in lexicographic order.  vp_search
- *                         uses it to share the work of common path prefixes.
+ *  order    [n_sc][2][K]  output or NULL: order[sc][0][j] is the path index k
+ *                         of the j-th path in lexicographic order (level 0
+ *                         most significant); order[sc][1][j] the same with
+ *                         the deepest level most significant.  vp_search uses
+ *                         the first to share the work of common path prefixes
+ *                         and the second to batch paths whose deep levels need
+ *                         the same kind of DEMAP work.
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, N < 1, K < 1, K > 9^N;
  * VP_EUNSUPPORTED for N > 16 or K > 1024.
  */
-int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint16_t *lexorder, void *stream);
+int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint16_t *order, void *stream);
 
 /*
  * vp_search -- per-vector evaluation of K paths and argmin (Sec. II-B PED
@@ -139,8 +143,8 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  *  tau      perturbation interval 2 sqrt(Q) (Sec. II-B), > 0
  *  paths    ranks uint8; subcarrier sc uses paths + sc * paths_sc_stride,
  *           a [K][N] table (stride 0 = one table for every subcarrier)
- *  lexorder [n_sc][K] or NULL: the tables' lexicographic order as written by
- *           vp_paths_mop (requires paths_sc_stride == K*N).  With it, the
+ *  order    [n_sc][2][K] or NULL: the tables' two orders as written by
+ *           vp_paths_mop (requires paths_sc_stride == K*N).  With them, the
  *           work of each distinct prefix of the first N/4 levels is done once
  *           per vector instead of once per path; results are identical.
  *  l        [N][n_vec][2] output int8 (re, im) in {-1, 0, 1}, user order
@@ -151,11 +155,11 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  * gets l = 0, cost = NaN, kidx = -1.
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, N < 1, K < 1,
- * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N), lexorder
+ * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N), order
  * given with paths_sc_stride != K*N; VP_EUNSUPPORTED for N > 16 or K > 4096.
  */
 int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
-              const uint8_t *paths, const uint16_t *lexorder, int K, int64_t paths_sc_stride, int n_sc,
+              const uint8_t *paths, const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc,
               int n_sym, int n_r, uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream);
 
 /*

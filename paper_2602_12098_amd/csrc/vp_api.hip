@@ -45,26 +45,26 @@ int vp_preprocess(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c
                              (hipStream_t)stream);
 }
 
-int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint16_t *lexorder, void *stream) {
+int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint16_t *order, void *stream) {
     if (n_sc < 0 || n_r < 1 || K < 1) return VP_EINVAL;
     if (n_r > kMaxN || K > kMaxKMop) return VP_EUNSUPPORTED;
     if (k_exceeds_box(K, n_r)) return VP_EINVAL;
     if (n_sc == 0) return VP_OK;
     if (!w2 || !paths) return VP_EINVAL;
-    return launch_mop(w2, n_sc, n_r, K, paths, lexorder, (hipStream_t)stream);
+    return launch_mop(w2, n_sc, n_r, K, paths, order, (hipStream_t)stream);
 }
 
 int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const uint8_t *paths,
-              const uint16_t *lexorder, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
+              const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
               uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream) {
     if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
     if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
     if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
-    if (lexorder && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;   // one order per subcarrier table
+    if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;   // one order per subcarrier table
     if (flags & ~(uint32_t)VP_INCLUDE_ZERO) return VP_EINVAL;
     if (n_sc == 0) return VP_OK;
     if (!W || !perm || !s || !paths || !l || !cost || !kidx) return VP_EINVAL;
-    return launch_search((const float2 *)W, perm, (const float2 *)s, tau, paths, lexorder, K, paths_sc_stride, n_sc,
+    return launch_search((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K, paths_sc_stride, n_sc,
                          n_sym,
                          n_r, flags, l, cost, kidx, (hipStream_t)stream);
 }

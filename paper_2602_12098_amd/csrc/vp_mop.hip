@@ -44,6 +44,48 @@ struct MopSmem {
     uint32_t part[kT];
 };
 
+// In-LDS bitonic sort of n (a power of two) 64-bit keys with 16-bit payloads.
+__device__ void block_bitonic_sort(unsigned long long *key, uint16_t *val, int n) {
+    const int t = threadIdx.x;
+    for (int size = 2; size <= n; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = t; i < (n >> 1); i += kT) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const unsigned long long a = key[lo], b = key[hi];
+                if ((a > b) == up) {
+                    key[lo] = b;
+                    key[hi] = a;
+                    const uint16_t x = val[lo];
+                    val[lo] = val[hi];
+                    val[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// Writes order[1]: the path indices sorted with the deepest level most
+// significant.  word(k) must return path k's rank nibbles (level i at bits 4i),
+// which is exactly that key.  key/val are LDS scratch of >= pow2(K) entries.
+template <class WordFn>
+__device__ void write_suffix_order(WordFn word, int K, unsigned long long *key, uint16_t *val,
+                                   uint16_t *__restrict__ out) {
+    const int t = threadIdx.x;
+    int n = 1;
+    while (n < K) n <<= 1;
+    for (int k = t; k < n; k += kT) {
+        key[k] = k < K ? word(k) : ~0ull;
+        val[k] = (uint16_t)k;
+    }
+    __syncthreads();
+    block_bitonic_sort(key, val, n);
+    for (int k = t; k < K; k += kT) out[k] = val[k];
+    __syncthreads();
+}
+
 __device__ __forceinline__ bool key_less(double ma, uint32_t ta, double mb, uint32_t tb) {
     return ma < mb || (ma == mb && (ta & 0x3fffu) < (tb & 0x3fffu));
 }
@@ -55,7 +97,7 @@ __device__ __forceinline__ void list_elem(const MopSmem &S, double wl, int r, in
 }
 
 __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ paths,
-                                            uint16_t *__restrict__ lexorder, int only_marked) {
+                                            uint16_t *__restrict__ order, int only_marked) {
     extern __shared__ unsigned char smem_raw[];
     MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
     const int sc = blockIdx.x;
@@ -181,8 +223,12 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N,
         const int k = idx / N, i = idx % N;
         out[idx] = (uint8_t)((S.pword[k] >> (4 * i)) & 15ull);
     }
-    if (lexorder)   // survivors carry their lexicographic rank
-        for (int k = t; k < K; k += kT) lexorder[(size_t)sc * K + S.plex[k]] = (uint16_t)k;
+    if (order) {   // survivors carry their lexicographic rank
+        for (int k = t; k < K; k += kT) order[(size_t)sc * 2 * K + S.plex[k]] = (uint16_t)k;
+        __syncthreads();
+        write_suffix_order([&](int k) { return S.pword[k]; }, K,
+                           reinterpret_cast<unsigned long long *>(S.tm[0]), S.scan, order + (size_t)sc * 2 * K + K);
+    }
 }
 
 
@@ -274,7 +320,7 @@ struct ThrSmem {
 
 template <int CAP>
 __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, int N, int K,
-                                                uint8_t *__restrict__ paths, uint16_t *__restrict__ lexorder) {
+                                                uint8_t *__restrict__ paths, uint16_t *__restrict__ order) {
     constexpr int PER = CAP / kT;   // frontier entries held per thread
     extern __shared__ unsigned char smem_raw[];
     ThrSmem<CAP> &S = *reinterpret_cast<ThrSmem<CAP> *>(smem_raw);
@@ -292,8 +338,8 @@ __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, in
     }
     if (!valid) {   // failed preprocessing: a deterministic all-zero table
         for (int idx = t; idx < K * N; idx += kT) out[idx] = 0;
-        if (lexorder)
-            for (int k = t; k < K; k += kT) lexorder[(size_t)sc * K + k] = (uint16_t)k;
+        if (order)
+            for (int k = t; k < 2 * K; k += kT) order[(size_t)sc * 2 * K + k] = (uint16_t)(k % K);
         return;
     }
     // (1) threshold on a coarse grid over the whole range, then a finer one
@@ -425,7 +471,8 @@ __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, in
         const int k = idx / N, i = idx % N;
         out[idx] = (uint8_t)((S.fw[k] >> (4 * (N - 1 - i))) & 15ull);
     }
-    if (lexorder) {
+    if (order) {
+        uint16_t *lexorder = order + (size_t)sc * 2 * K;
         // the enumeration visited S(T) in lexicographic order: the selected
         // paths, in enumeration order, are the path table in lexicographic order
         for (int k = t; k < K; k += kT) S.rank_of[S.fe[k]] = (uint16_t)k;
@@ -442,13 +489,23 @@ __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, in
         uint32_t pos = block_scan_excl(cnt, S.scan, &tot);
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            if (sel[q]) lexorder[(size_t)sc * K + pos++] = S.rank_of[t * PER + q];
+            if (sel[q]) lexorder[pos++] = S.rank_of[t * PER + q];
+        // suffix-major order: the nibble reversal of the lexicographic key
+        const int NN = N;
+        write_suffix_order(
+            [&](int k) {
+                const unsigned long long x = S.fw[k];
+                unsigned long long wd = 0;
+                for (int i = 0; i < NN; ++i) wd |= ((x >> (4 * (NN - 1 - i))) & 15ull) << (4 * i);
+                return wd;
+            },
+            K, reinterpret_cast<unsigned long long *>(S.fm), S.fe, lexorder + K);
     }
 }
 
 }  // namespace
 
-int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *lexorder, hipStream_t st) {
+int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
     static const int attr_once = (
         hipFuncSetAttribute((const void *)k_mop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(MopSmem)),
@@ -460,17 +517,17 @@ int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t
     (void)attr_once;
     if (K <= 512)
         hipLaunchKernelGGL(k_mop_thr<1024>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<1024>), st, w2, N, K, paths,
-                           lexorder);
+                           order);
     else
         hipLaunchKernelGGL(k_mop_thr<2048>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<2048>), st, w2, N, K, paths,
-                           lexorder);
-    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, lexorder, 1);
+                           order);
+    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, order, 1);
     return launch_status();
 }
 
-int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *lexorder, hipStream_t st) {
+int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
-    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, lexorder, 0);
+    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, order, 0);
     return launch_status();
 }
 

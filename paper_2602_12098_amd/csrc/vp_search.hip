@@ -76,7 +76,8 @@ __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float
         float a, b;
         if (UNIFORM_TIERS) {
             if (__any(rank > 1)) vp_demapN(cx, cy, rank, lut, a, b);
-            else vp_demap1(cx, cy, rank, a, b);
+            else if (__any(rank != 0)) vp_demap1(cx, cy, rank, a, b);
+            else vp_demap0(cx, cy, a, b);
         } else {
             vp_demapN(cx, cy, rank, lut, a, b);
         }
@@ -210,23 +211,26 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
     }
 }
 
-// Prefix-sharing search (paths given in lexicographic order by `lexorder`).
+// Prefix-sharing search (path orders from vp_paths_mop: lexicographic, and
+// deepest level most significant).
 // Stage 1: each distinct prefix of levels [0, P1) is walked once, one lane per
 // prefix, and its residuals below P1 and its PED are kept in LDS.  Stage 2:
-// each path continues from its prefix's state over levels [P1, N).  More
-// than kMaxPrefix distinct prefixes (an unusual table) -> every path is
-// walked from the root instead.  Same per-path arithmetic as a direct walk.
+// each path continues from its prefix's state over levels [P1, N), taken in
+// deepest-level-first order so that the lanes of a wave mostly need the same
+// DEMAP work.  A table with more than kMaxPrefix distinct prefixes is done in
+// chunks of kMaxPrefix prefixes (their paths are contiguous in lexicographic
+// order).  Every path sees exactly the arithmetic of a direct walk.
 constexpr int kTT = 128;          // threads of the prefix-sharing search
-constexpr int kMaxPrefix = kTT;   // stage-1 prefixes held in LDS
+constexpr int kMaxPrefix = kTT;   // stage-1 prefixes held in LDS at a time
 
 template <int N>
-constexpr int prefix_levels() { return N >= 4 ? N / 4 : 0; }
+constexpr int prefix_levels() { return N >= 4 ? N / 4 : 1; }
 
 template <int N>
 __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
                                                      const float2 *__restrict__ s, float tau,
                                                      const uint8_t *__restrict__ paths,
-                                                     const uint16_t *__restrict__ lexorder, int K,
+                                                     const uint16_t *__restrict__ order, int K,
                                                      long long pstride, int n_sym, unsigned flags,
                                                      float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
     constexpr int P1 = prefix_levels<N>();
@@ -234,8 +238,9 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
     extern __shared__ unsigned long long s_words[];   // [K] rank nibbles, lexicographic order
     uint16_t *s_k = reinterpret_cast<uint16_t *>(s_words + K);     // [K] path index of lex position
     uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of lex position
+    uint16_t *s_lexpos = s_node + K;                                // [K] lex position of path k
+    uint16_t *s_first = s_lexpos + K;                               // [K + 1] first lex position of a prefix
     __shared__ float s_state[kMaxPrefix * SW];
-    __shared__ uint16_t s_first[kMaxPrefix];   // first lex position of each prefix
     __shared__ float2 s_r0[N];
     __shared__ float s_linv[N];
     __shared__ float s_wdiag[N];
@@ -258,7 +263,8 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         return;
     }
     const uint8_t *P = paths + (size_t)sc * pstride;
-    const uint16_t *LX = lexorder + (size_t)sc * K;
+    const uint16_t *LX = order + (size_t)sc * 2 * K;        // lexicographic
+    const uint16_t *SX = LX + K;                            // deepest level most significant
     if (t < N) {
         s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
         s_linv[t] = 1.0f / s_wdiag[t];
@@ -268,6 +274,7 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         int k = LX[j];
         k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
         s_k[j] = (uint16_t)k;
+        s_lexpos[k] = (uint16_t)j;
         s_words[j] = load_word<N>(P, k);
     }
     __syncthreads();
@@ -291,25 +298,24 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         __syncthreads();
         for (int q = 0; q < wv; ++q) incl += s_scan[q];
     }
-    const uint32_t n1 = s_scan[0] + (kTT / 64 > 1 ? s_scan[1] : 0);
+    uint32_t n1 = 0;
+    for (int q = 0; q < kTT / 64; ++q) n1 += s_scan[q];
     uint32_t node = incl - cnt;
     for (int j = j0; j < j1; ++j) {
-        const bool start = (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull);
-        if (start) {
-            if (node < (uint32_t)kMaxPrefix) s_first[node] = (uint16_t)j;
-            ++node;
-        }
+        if (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull) s_first[node++] = (uint16_t)j;
         s_node[j] = (uint16_t)(node - 1);
     }
+    if (t == 0) s_first[n1] = (uint16_t)K;
     __syncthreads();
     const float tau2 = tau * tau;
     unsigned long long best = ~0ull;
-    if (P1 > 0 && n1 <= (uint32_t)kMaxPrefix) {
-        if (t < (int)n1) {   // stage 1: one lane per distinct prefix
+    for (uint32_t base = 0; base < n1; base += kMaxPrefix) {
+        const uint32_t nc = min(n1 - base, (uint32_t)kMaxPrefix);
+        if (t < (int)nc) {   // stage 1: one lane per distinct prefix
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) r[i] = s_r0[i];
-            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_first[t]],
+            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_first[base + t]],
                                                            VP_DEMAP_LUT, nullptr, nullptr);
             float *st = s_state + t * SW;
 #pragma unroll
@@ -320,8 +326,21 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
             st[SW - 1] = ped;
         }
         __syncthreads();
-        for (int j = t; j < K; j += kTT) {   // stage 2: every path from its prefix
-            const float *st = s_state + s_node[j] * SW;
+        // stage 2: all paths at once in deepest-level-first order, or (chunked
+        // case) the contiguous lexicographic range of this chunk's prefixes
+        const bool whole = (n1 <= (uint32_t)kMaxPrefix);
+        const int q0 = whole ? 0 : s_first[base];
+        const int q1 = whole ? K : s_first[base + nc];
+        for (int q = q0 + t; q < q1; q += kTT) {
+            int j;
+            if (whole) {
+                int kk = SX[q];
+                kk = kk < K ? kk : K - 1;
+                j = s_lexpos[kk];
+            } else {
+                j = q;
+            }
+            const float *st = s_state + (s_node[j] - base) * SW;
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
@@ -331,15 +350,7 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
                                                            nullptr, nullptr, st[SW - 1]);
             best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)s_k[j]);
         }
-    } else {
-        for (int j = t; j < K; j += kTT) {
-            float2 r[N];
-#pragma unroll
-            for (int i = 0; i < N; ++i) r[i] = s_r0[i];
-            const float ped = walk<N, true, false>(Wc, s_linv, s_wdiag, r, s_words[j], VP_DEMAP_LUT, nullptr,
-                                                   nullptr);
-            best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)s_k[j]);
-        }
+        __syncthreads();
     }
     if ((flags & VP_INCLUDE_ZERO) && t == 0) {
         float z = 0.f;
@@ -405,17 +416,17 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
 
 template <int N>
 int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
-                    const uint16_t *lexorder, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
+                    const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
                     float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
-    if (lexorder) {
-        const size_t smem = (size_t)K * (sizeof(unsigned long long) + 2 * sizeof(uint16_t));
+    if (order) {
+        const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(4 * K + 1) * sizeof(uint16_t);
         static const int attr_once = (hipFuncSetAttribute((const void *)k_search_trie<N>,
                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024),
                                       0);
         (void)attr_once;
         hipLaunchKernelGGL(k_search_trie<N>, dim3((unsigned)n_vec), dim3(kTT), smem, st, W, perm, s, tau, paths,
-                           lexorder, K, (long long)pstride, n_sym, flags, cost, kidx);
+                           order, K, (long long)pstride, n_sym, flags, cost, kidx);
     } else {
         hipLaunchKernelGGL(k_search<N>, dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
                            (long long)pstride, n_sym, flags, cost, kidx);
@@ -428,13 +439,13 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
 }  // namespace
 
 int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
-                  const uint16_t *lexorder, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
+                  const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                   int8_t *l, float *cost, int32_t *kidx, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
     switch (N) {
 #define VP_CASE(n)                                                                                            \
     case n:                                                                                                   \
-        return launch_search_n<n>(W, perm, s, tau, paths, lexorder, K, pstride, n_sc, n_sym, flags, l, cost, \
+        return launch_search_n<n>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, l, cost, \
                                   kidx, st);
         VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
         VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)

@@ -75,25 +75,25 @@ def preprocess(H: torch.Tensor, alpha: float, want_G: bool = True, out: Optional
 
 
 def paths_mop(w2: torch.Tensor, K: int, out: Optional[torch.Tensor] = None,
-              lexorder: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """vp_paths_mop: w2 float32 [n_sc][N] -> paths uint8 [n_sc][K][N].  If `lexorder`
-    (int16 [n_sc][K], read as uint16) is given it receives the lexicographic order."""
+              order: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vp_paths_mop: w2 float32 [n_sc][N] -> paths uint8 [n_sc][K][N].  If `order`
+    (int16 [n_sc][2][K], read as uint16) is given it receives the two path orders."""
     lib = _lib.load()
     n_sc, N = w2.shape
     if out is None:
         out = torch.empty((n_sc, K, N), dtype=torch.uint8, device=w2.device)
     pw = _req(w2, "w2", torch.float32)
     po = _req(out, "paths", torch.uint8, (n_sc, K, N))
-    pl = _req(lexorder, "lexorder", torch.int16, (n_sc, K)) if lexorder is not None else None
+    pl = _req(order, "order", torch.int16, (n_sc, 2, K)) if order is not None else None
     check(lib.vp_paths_mop(pw, n_sc, N, int(K), po, pl, _stream()), "vp_paths_mop")
     return out
 
 
 def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
            n_sym: int, flags: int = VP_INCLUDE_ZERO, out: Optional[SearchOut] = None,
-           lexorder: Optional[torch.Tensor] = None) -> SearchOut:
+           order: Optional[torch.Tensor] = None) -> SearchOut:
     """vp_search: paths is [K][N] (one table for all subcarriers) or [n_sc][K][N];
-    lexorder (int16 [n_sc][K] from paths_mop) enables prefix sharing."""
+    order (int16 [n_sc][2][K] from paths_mop) enables prefix sharing."""
     lib = _lib.load()
     n_sc = W.shape[0]
     N = perm.shape[1]
@@ -118,7 +118,7 @@ def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, pat
     pl = _req(out.l, "l", torch.int8, (N, n_vec, 2))
     pc = _req(out.cost, "cost", torch.float32, (n_vec,))
     pk = _req(out.kidx, "kidx", torch.int32, (n_vec,))
-    plx = _req(lexorder, "lexorder", torch.int16, (n_sc, K)) if lexorder is not None else None
+    plx = _req(order, "order", torch.int16, (n_sc, 2, K)) if order is not None else None
     check(lib.vp_search(pW, pp, ps, float(tau), pP, plx, int(K), int(stride), n_sc, int(n_sym), N, int(flags),
                         pl, pc, pk, _stream()), "vp_search")
     return out

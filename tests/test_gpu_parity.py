@@ -44,10 +44,10 @@ def run_pipeline(vp, wl, K=None, want_G=True, include_zero=True, H=None, s=None,
     alpha = wl.alpha if alpha is None else alpha
     Hd, sd = _to_dev(H), _to_dev(s)
     prep = vp.preprocess(Hd, alpha, want_G=want_G)
-    lex = torch.empty((H.shape[0], K), dtype=torch.int16, device=DEV) if shared_prefix else None
-    paths = vp.paths_mop(prep.w2, K, lexorder=lex)
+    order = torch.empty((H.shape[0], 2, K), dtype=torch.int16, device=DEV) if shared_prefix else None
+    paths = vp.paths_mop(prep.w2, K, order=order)
     flags = vp.VP_INCLUDE_ZERO if include_zero else 0
-    out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, n_sym, flags=flags, lexorder=lex)
+    out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, n_sym, flags=flags, order=order)
     torch.cuda.synchronize()
     return prep, paths, out, sd
 
@@ -361,24 +361,27 @@ def test_sphere_encoder_matches_oracle(vp):
             assert np.all(cg <= host(out.cost) * (1 + 1e-5))
 
 
-def test_paths_mop_lexorder(vp):
-    for wl, K in ((vpgen.cfg3(512, n_sc=10), 512), (vpgen.cfg1(n_sc=6), 32)):
+def _check_orders(P, L, K):
+    rows = [tuple(P[k]) for k in L[0]]
+    assert rows == sorted(rows) and sorted(L[0].tolist()) == list(range(K))
+    rows = [tuple(P[k][::-1]) for k in L[1]]
+    assert rows == sorted(rows) and sorted(L[1].tolist()) == list(range(K))
+
+
+def test_paths_mop_orders(vp):
+    for wl, K in ((vpgen.cfg3(512, n_sc=10), 512), (vpgen.cfg1(n_sc=6), 32), (vpgen.cfg2(20, n_sc=4), 100)):
         Hd = _to_dev(wl.H)
         prep = vp.preprocess(Hd, wl.alpha)
-        lo = torch.empty((wl.n_sc, K), dtype=torch.int16, device=DEV)
-        P = host(vp.paths_mop(prep.w2, K, lexorder=lo))
+        lo = torch.empty((wl.n_sc, 2, K), dtype=torch.int16, device=DEV)
+        P = host(vp.paths_mop(prep.w2, K, order=lo))
         L = host(lo).astype(np.int64) & 0xffff
         for sc in range(wl.n_sc):
-            assert sorted(L[sc].tolist()) == list(range(K))
-            rows = [tuple(P[sc, k]) for k in L[sc]]
-            assert rows == sorted(rows)
-    # the K-best fallback produces it too (16 equal weights, K = 1024)
+            _check_orders(P[sc], L[sc], K)
+    # the K-best fallback writes them too (16 equal weights, K = 1024)
     w = torch.full((1, 16), 0.3, dtype=torch.float32, device=DEV)
-    lo = torch.empty((1, 1024), dtype=torch.int16, device=DEV)
-    P = host(vp.paths_mop(w, 1024, lexorder=lo))
-    L = host(lo).astype(np.int64) & 0xffff
-    rows = [tuple(P[0, k]) for k in L[0]]
-    assert rows == sorted(rows) and sorted(L[0].tolist()) == list(range(1024))
+    lo = torch.empty((1, 2, 1024), dtype=torch.int16, device=DEV)
+    P = host(vp.paths_mop(w, 1024, order=lo))
+    _check_orders(P[0], host(lo)[0].astype(np.int64) & 0xffff, 1024)
 
 
 @pytest.mark.parametrize("N,K", [(16, 512), (8, 64), (4, 32), (12, 300), (3, 50)])
