@@ -57,7 +57,8 @@ enum {
 
 /* flags for vp_search */
 enum {
-    VP_INCLUDE_ZERO = 1 /* also evaluate l = 0 (plain RZF) as candidate index K */
+    VP_INCLUDE_ZERO = 1,    /* also evaluate l = 0 (plain RZF) as candidate index K */
+    VP_PATHS_PER_VECTOR = 2 /* one [K][N] table per vector (paths + v * paths_sc_stride) */
 };
 
 /* Size (in vp_c32) of one packed lower-triangular N x N matrix. */
@@ -142,7 +143,9 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  *  s        [N][n_vec]  symbols, structure of arrays (user-major), user order
  *  tau      perturbation interval 2 sqrt(Q) (Sec. II-B), > 0
  *  paths    ranks uint8; subcarrier sc uses paths + sc * paths_sc_stride,
- *           a [K][N] table (stride 0 = one table for every subcarrier)
+ *           a [K][N] table (stride 0 = one table for every subcarrier).
+ *           With VP_PATHS_PER_VECTOR vector v uses paths + v * paths_sc_stride
+ *           (stride must be K*N; e.g. the tables of vp_learned_paths).
  *  order    [n_sc][2][K] or NULL: the tables' two orders as written by
  *           vp_paths_mop (requires paths_sc_stride == K*N).  With them, the
  *           work of each distinct prefix of the first N/4 levels is done once
@@ -156,7 +159,9 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, N < 1, K < 1,
  * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N), order
- * given with paths_sc_stride != K*N; VP_EUNSUPPORTED for N > 16 or K > 4096.
+ * given with paths_sc_stride != K*N, unknown flags, VP_PATHS_PER_VECTOR with
+ * an order or with paths_sc_stride != K*N; VP_EUNSUPPORTED for N > 16 or
+ * K > 4096.
  */
 int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
               const uint8_t *paths, const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc,

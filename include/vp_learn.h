@@ -1,0 +1,155 @@
+/*
+ * vp_learn.h -- C ABI of the learned path proposal (gfx950).
+ *
+ * The paper selects the K candidate paths of a subcarrier from the channel
+ * alone, by the Metric of Promise (Sec. III-A-2, eq. for M(r)).  The entry
+ * points below let a small network propose a short per-vector path list
+ * instead, scored over a fixed vocabulary of position vectors r (one rank
+ * 0..8 per level); the proposal is evaluated by the unchanged path search of
+ * vp.h (vp_search with VP_PATHS_PER_VECTOR), so the perturbation l is still an
+ * exact Gaussian integer and its cost the exact PED sum of Sec. II-B.  The
+ * paper itself has no learned component: this is an extension, and every
+ * choice below (features, network shape, labels) is a stated design choice.
+ *
+ * Network: features (64) -> Linear 64x256 -> ReLU -> Linear 256x256 -> ReLU
+ * -> Linear 256xV (logits over the vocabulary) -> 64 best entries.
+ *
+ * Conventions are those of vp.h (device pointers owned by the caller, calls
+ * only enqueue on `stream`, VP_OK or a negative code).  bf16 values are passed
+ * as their uint16_t bit patterns (the upper half of an IEEE float32).
+ * Matrices are row-major with an explicit leading dimension (elements between
+ * consecutive rows of the STORED matrix).
+ */
+#ifndef VP_LEARN_H
+#define VP_LEARN_H
+
+#include <stdint.h>
+
+#include "vp.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VP_MLP_FEATURES 64 /* features per vector */
+#define VP_TOPK 64         /* entries kept per vector by vp_topk64 */
+#define VP_MAX_VOCAB 4096  /* largest vocabulary vp_topk64 accepts */
+
+/* epilogue flags of vp_gemm_bf16 */
+enum {
+    VP_EPI_RELU = 1 /* C = max(C, 0) after the bias */
+};
+
+/*
+ * vp_mlp_features -- the network input of every vector (bf16 [n_vec][64]).
+ *
+ * With W, perm from vp_preprocess and the zero-perturbation centres of the
+ * tree, c0_i = -(W s_pi)_i / (tau W_ii) (the centres of Sec. III-A-2 before
+ * any perturbation is chosen), the features of vector v are, for levels
+ * i < N (slots of levels >= N are 0):
+ *   [i]       W_ii / mean_j W_jj      (the MoP weights of the subcarrier)
+ *   [16 + i]  Re c0_i
+ *   [32 + i]  Im c0_i
+ *   [48 + i]  W_ii^2 |c0_i - b0(c0_i)|^2 / mean_j W_jj^2, b0 = nearest box point
+ * A failed subcarrier (W_00 not finite and > 0) gets all-zero features.
+ * Computed in float32 and rounded once to bf16 (round to nearest even).
+ *
+ * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, n_r < 1, tau <= 0
+ * or not finite; VP_EUNSUPPORTED for n_r > 16.
+ */
+int vp_mlp_features(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym,
+                    int n_r, uint16_t *feat, void *stream);
+
+/*
+ * vp_path_ranks -- the position vector of a given perturbation (labels).
+ *
+ * Walks the tree of vector v with the given l (user order, [N][n_vec][2] as
+ * written by vp_search / vp_sphere_encode) and writes, per level i, the rank
+ * of l_{perm[i]} among the 9 box points ordered by distance to the level's
+ * centre c_i (ties in canonical order; the same float32 arithmetic as
+ * vp_search), so that vp_search on that position vector reproduces l.  A
+ * symbol outside the box is rank 15.  ranks: uint8 [n_vec][N].
+ *
+ * Errors: as vp_mlp_features, plus NULL l or ranks.
+ */
+int vp_path_ranks(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const int8_t *l, int n_sc,
+                  int n_sym, int n_r, uint8_t *ranks, void *stream);
+
+/*
+ * vp_gemm_bf16 -- C = epilogue(alpha * op(A) op(B) + bias) on the matrix cores.
+ *
+ * op(A) is m x k: A stored [m][lda] (trans_a = 0) or [k][lda] (trans_a = 1);
+ * op(B) is k x n: B stored [k][ldb] (trans_b = 0) or [n][ldb] (trans_b = 1)
+ * -- a torch Linear weight [out][in] is op(B) with trans_b = 1.  bf16
+ * operands, float32 accumulation (v_mfma_f32_32x32x16_bf16).  Epilogue, in
+ * order: bias[n] (float32, or NULL), VP_EPI_RELU, then if mask is non-NULL
+ * every element whose mask entry (bf16 [m][ldm]) is not > 0 becomes 0 (the
+ * ReLU derivative in a backward pass).  Output to C (float32 [m][ldc]) and/or
+ * C_bf16 (bf16 [m][ldc], rounded to nearest even); at least one non-NULL.
+ * k = 0 gives C = epilogue(bias).
+ *
+ * Errors: VP_EINVAL for m, n or k < 0, a leading dimension smaller than the
+ * stored row length, NULL operands (when m, n > 0), both outputs NULL, or
+ * unknown epilogue flags.
+ */
+int vp_gemm_bf16(int m, int n, int k, const uint16_t *A, int64_t lda, int trans_a, const uint16_t *B, int64_t ldb,
+                 int trans_b, const float *bias, uint32_t epilogue, const uint16_t *mask, int64_t ldm, float alpha,
+                 float *C, uint16_t *C_bf16, int64_t ldc, void *stream);
+
+/*
+ * vp_topk64 -- the 64 largest of each row of scores (float32 [rows][C]).
+ *
+ * idx (int32 [rows][64]) lists the selected columns by decreasing score,
+ * equal scores by increasing column (a total order, so the result is unique;
+ * -0.0 ranks below +0.0, NaN above everything).  mass (float32 [rows], or
+ * NULL) receives the softmax probability mass of the selected columns,
+ * sum_sel exp(x - max) / sum_all exp(x - max).
+ *
+ * Errors: VP_EINVAL for rows < 0, C < 64, NULL pointers; VP_EUNSUPPORTED for
+ * C > 4096.
+ */
+int vp_topk64(const float *scores, int rows, int C, int32_t *idx, float *mass, void *stream);
+
+/*
+ * vp_softmax_xent -- softmax cross-entropy and its gradient (training).
+ *
+ * Per row: loss = logsumexp(z) - z[label]; dz = (softmax(z) - onehot(label))
+ * * scale, written as bf16 [rows][C].  A row with label outside [0, C) (e.g.
+ * -1: no label) has loss 0 and dz 0.  logits float32 [rows][C], label int32
+ * [rows], loss float32 [rows].
+ *
+ * Errors: VP_EINVAL for rows < 0, C < 1, NULL pointers, scale not finite.
+ */
+int vp_softmax_xent(const float *logits, int rows, int C, const int32_t *label, float scale, float *loss,
+                    uint16_t *dlogits, void *stream);
+
+/*
+ * vp_colsum_bf16 -- out[j] = sum_i X[i][j] over a bf16 [rows][cols] matrix,
+ * accumulated in float32 in row order (the bias gradient).
+ *
+ * Errors: VP_EINVAL for rows < 0, cols < 0, NULL pointers.
+ */
+int vp_colsum_bf16(const uint16_t *X, int rows, int cols, float *out, void *stream);
+
+/*
+ * vp_learned_paths -- per-vector path tables for vp_search.
+ *
+ * table (uint8 [n_vec][K_learned + K_fixed][N]) holds, for vector v, the
+ * vocabulary rows top[v][0..K_learned) (vocab: uint8 [V][N] rank vectors;
+ * an index outside [0, V) is clamped), then the first K_fixed paths of the
+ * subcarrier's fixed table (fixed: uint8 [n_sc][K_fixed_table][N], e.g. from
+ * vp_paths_mop).  Use with vp_search(..., K_learned + K_fixed, stride
+ * (K_learned + K_fixed) * N, flags | VP_PATHS_PER_VECTOR).
+ *
+ * Errors: VP_EINVAL for NULL pointers (where the sizes use them), negative
+ * sizes, K_fixed > K_fixed_table, K_learned + K_fixed < 1, V < 1 with
+ * K_learned > 0; VP_EUNSUPPORTED for n_r > 16 or K_learned + K_fixed > 4096.
+ */
+int vp_learned_paths(const uint8_t *vocab, int V, int n_r, const int32_t *top, int K_learned, const uint8_t *fixed,
+                     int K_fixed_table, int K_fixed, int n_sc, int n_sym, uint8_t *table, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VP_LEARN_H */

@@ -2,6 +2,7 @@
 
 The hot path (preprocess -> most-promising paths -> path search + argmin ->
 precode) and the exact sphere encoder run in hand-written HIP kernels behind
-the C ABI of include/vp.h; this package only marshals torch device tensors."""
-from .vp import (VP_INCLUDE_ZERO, Prep, SearchOut, SEOut, packed_size, paths_mop,  # noqa: F401
+the C ABI of include/vp.h; the learned path proposal (module `learn`) sits
+behind include/vp_learn.h.  This package only marshals torch device tensors."""
+from .vp import (VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, Prep, SearchOut, SEOut, packed_size, paths_mop,  # noqa: F401
                  precode, preprocess, search, sphere_encode, version)

@@ -14,6 +14,7 @@ VP_EINVAL = -1
 VP_EUNSUPPORTED = -2
 VP_ELAUNCH = -3
 VP_INCLUDE_ZERO = 1
+VP_PATHS_PER_VECTOR = 2
 
 _lib = None
 

@@ -20,7 +20,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "libvp.so")
 HOSTLIB = os.path.join(HERE, "libvphost.so")
 
-HIP_SOURCES = ["vp_api.hip", "vp_preprocess.hip", "vp_mop.hip", "vp_search.hip", "vp_precode.hip", "vp_se.hip"]
+HIP_SOURCES = ["vp_api.hip", "vp_preprocess.hip", "vp_mop.hip", "vp_search.hip", "vp_precode.hip", "vp_se.hip",
+               "vp_learn.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",

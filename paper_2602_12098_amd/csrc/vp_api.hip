@@ -61,7 +61,8 @@ int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, 
     if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
     if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
     if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;   // one order per subcarrier table
-    if (flags & ~(uint32_t)VP_INCLUDE_ZERO) return VP_EINVAL;
+    if (flags & ~(uint32_t)(VP_INCLUDE_ZERO | VP_PATHS_PER_VECTOR)) return VP_EINVAL;
+    if ((flags & VP_PATHS_PER_VECTOR) && (order || paths_sc_stride != (int64_t)K * n_r)) return VP_EINVAL;
     if (n_sc == 0) return VP_OK;
     if (!W || !perm || !s || !paths || !l || !cost || !kidx) return VP_EINVAL;
     return launch_search((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K, paths_sc_stride, n_sc,
@@ -89,6 +90,75 @@ int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, floa
     if (!W || !perm || !s || !l || !cost) return VP_EINVAL;
     return launch_sphere((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, radius, l, cost, nodes,
                          (long long)max_nodes, (hipStream_t)stream);
+}
+
+int vp_mlp_features(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym, int n_r,
+                    uint16_t *feat, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+    if (n_r > kMaxN) return VP_EUNSUPPORTED;
+    if (n_sc == 0) return VP_OK;
+    if (!W || !perm || !s || !feat) return VP_EINVAL;
+    return launch_features((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, feat,
+                           (hipStream_t)stream);
+}
+
+int vp_path_ranks(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const int8_t *l, int n_sc,
+                  int n_sym, int n_r, uint8_t *ranks, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+    if (n_r > kMaxN) return VP_EUNSUPPORTED;
+    if (n_sc == 0) return VP_OK;
+    if (!W || !perm || !s || !l || !ranks) return VP_EINVAL;
+    return launch_ranks((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, l, ranks,
+                        (hipStream_t)stream);
+}
+
+int vp_gemm_bf16(int m, int n, int k, const uint16_t *A, int64_t lda, int trans_a, const uint16_t *B, int64_t ldb,
+                 int trans_b, const float *bias, uint32_t epilogue, const uint16_t *mask, int64_t ldm, float alpha,
+                 float *C, uint16_t *C_bf16, int64_t ldc, void *stream) {
+    if (m < 0 || n < 0 || k < 0 || (epilogue & ~(uint32_t)VP_EPI_RELU) || !isfinite(alpha)) return VP_EINVAL;
+    if (!C && !C_bf16) return VP_EINVAL;
+    if (m == 0 || n == 0) return VP_OK;
+    if (k > 0 && (!A || !B)) return VP_EINVAL;
+    if (k > 0 && lda < (int64_t)(trans_a ? m : k)) return VP_EINVAL;
+    if (k > 0 && ldb < (int64_t)(trans_b ? k : n)) return VP_EINVAL;
+    if (ldc < n || (mask && ldm < n)) return VP_EINVAL;
+    return launch_gemm(m, n, k, A, (long long)lda, trans_a != 0, B, (long long)ldb, trans_b != 0, C, C_bf16,
+                       (long long)ldc, bias, (int)(epilogue & VP_EPI_RELU), mask, (long long)ldm, alpha,
+                       (hipStream_t)stream);
+}
+
+int vp_topk64(const float *scores, int rows, int C, int32_t *idx, float *mass, void *stream) {
+    if (rows < 0 || C < VP_TOPK) return VP_EINVAL;
+    if (C > VP_MAX_VOCAB) return VP_EUNSUPPORTED;
+    if (rows == 0) return VP_OK;
+    if (!scores || !idx) return VP_EINVAL;
+    return launch_topk64(scores, rows, C, idx, mass, (hipStream_t)stream);
+}
+
+int vp_softmax_xent(const float *logits, int rows, int C, const int32_t *label, float scale, float *loss,
+                    uint16_t *dlogits, void *stream) {
+    if (rows < 0 || C < 1 || !isfinite(scale)) return VP_EINVAL;
+    if (rows == 0) return VP_OK;
+    if (!logits || !label || !loss || !dlogits) return VP_EINVAL;
+    return launch_softmax_ce(logits, rows, C, label, scale, loss, dlogits, (hipStream_t)stream);
+}
+
+int vp_colsum_bf16(const uint16_t *X, int rows, int cols, float *out, void *stream) {
+    if (rows < 0 || cols < 0) return VP_EINVAL;
+    if (cols == 0) return VP_OK;
+    if (!out || (rows > 0 && !X)) return VP_EINVAL;
+    return launch_colsum(X, rows, cols, out, (hipStream_t)stream);
+}
+
+int vp_learned_paths(const uint8_t *vocab, int V, int n_r, const int32_t *top, int K_learned, const uint8_t *fixed,
+                     int K_fixed_table, int K_fixed, int n_sc, int n_sym, uint8_t *table, void *stream) {
+    if (n_r < 1 || n_sc < 0 || n_sym < 1 || K_learned < 0 || K_fixed < 0 || K_fixed_table < 0) return VP_EINVAL;
+    if (K_fixed > K_fixed_table || K_learned + K_fixed < 1 || (K_learned > 0 && V < 1)) return VP_EINVAL;
+    if (n_r > kMaxN || K_learned + K_fixed > kMaxKSearch) return VP_EUNSUPPORTED;
+    if (n_sc == 0) return VP_OK;
+    if (!table || (K_learned > 0 && (!vocab || !top)) || (K_fixed > 0 && !fixed)) return VP_EINVAL;
+    return launch_learned_table(vocab, V, n_r, top, K_learned, fixed, K_fixed_table, K_fixed, n_sc, n_sym, table,
+                                (hipStream_t)stream);
 }
 
 const char *vp_strerror(int code) {

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "../../include/vp.h"
+#include "../../include/vp_learn.h"
 
 namespace vp {
 
@@ -30,5 +31,20 @@ int launch_precode(const float2 *G, const float2 *s, const int8_t *l, float tau,
 int launch_sphere(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
                   const float *radius, int8_t *l, float *cost, int64_t *nodes, long long max_nodes,
                   hipStream_t st);
+
+// Learned path proposal (vp_learn.hip).
+int launch_gemm(int M, int N, int K, const uint16_t *A, long long lda, int transA, const uint16_t *B, long long ldb,
+                int transB, float *Cf, uint16_t *Cb, long long ldc, const float *bias, int relu,
+                const uint16_t *mask, long long ldm, float alpha, hipStream_t st);
+int launch_features(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
+                    uint16_t *feat, hipStream_t st);
+int launch_ranks(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
+                 const int8_t *l, uint8_t *ranks, hipStream_t st);
+int launch_topk64(const float *S, int rows, int C, int32_t *idx, float *mass, hipStream_t st);
+int launch_softmax_ce(const float *Z, int rows, int C, const int32_t *label, float scale, float *loss,
+                      uint16_t *dZ, hipStream_t st);
+int launch_colsum(const uint16_t *X, int rows, int cols, float *out, hipStream_t st);
+int launch_learned_table(const uint8_t *vocab, int V, int N, const int32_t *top, int Kl, const uint8_t *fixed,
+                         int Kfix, int Kf, int n_sc, int n_sym, uint8_t *table, hipStream_t st);
 
 }  // namespace vp

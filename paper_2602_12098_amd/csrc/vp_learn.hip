@@ -1,0 +1,529 @@
+// Learned path proposal: kernels for a small MLP that scores a vocabulary of
+// position vectors per vector (features -> 256 -> 256 -> V logits, ReLU),
+// its training (softmax cross-entropy, hand-written backward) and its use
+// (top-64 per vector -> per-vector path table for the path search).
+//
+// The proposal only chooses which position vectors the search walks; the
+// search itself (Sec. II-B PED, Sec. III-A-2 DEMAP, Alg. 2 argmin) is
+// unchanged, so l stays an exact Gaussian integer.  Labels are the position
+// vectors of the exact (sphere-encoder) solutions: the rank of each level's
+// exact symbol in the DEMAP order of that level's centre.
+//
+// GEMM: bf16 operands, fp32 accumulation on the matrix cores
+// (v_mfma_f32_32x32x16_bf16), 64x64 tiles per 256-thread workgroup, one
+// 32x32 block per wave, K staged through LDS in steps of 32.
+#include "vp_internal.hpp"
+
+#define VP_LUT_STORAGE static __constant__
+#include "vp_device.hpp"
+
+namespace vp {
+namespace {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);   // NaN stays NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM  C[M][N] = epi(alpha A[M][K] B[K][N] + bias[N])
+//   TA: A is stored as [K][M] (lda = row stride of the stored matrix)
+//   TB: B is stored as [N][K]
+// 128 x 128 tile per workgroup, 2 x 2 waves of 64 x 64 (2 x 2 MFMA blocks of
+// 32 x 32 each), K in steps of 32 through LDS ([row][k] with a padded row).
+// ---------------------------------------------------------------------------
+constexpr int GT = 256, BM = 128, BN = 128, BK = 32, LDK = BK + 8;
+
+// 8 consecutive elements of a stored row starting at `start` (< limit), zero
+// beyond `limit`; one 16-byte load when the row is 16-byte aligned there.
+__device__ __forceinline__ uint4 load8(const uint16_t *__restrict__ row, int start, int limit, bool vec) {
+    if (vec && start + 8 <= limit) return *reinterpret_cast<const uint4 *>(row + start);
+    uint16_t e[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) e[j] = (start + j < limit) ? row[start + j] : (uint16_t)0;
+    uint4 r;
+    r.x = e[0] | ((uint32_t)e[1] << 16);
+    r.y = e[2] | ((uint32_t)e[3] << 16);
+    r.z = e[4] | ((uint32_t)e[5] << 16);
+    r.w = e[6] | ((uint32_t)e[7] << 16);
+    return r;
+}
+
+// Stage a ROWS x BK tile of op(X) (rows = m or n) into S[row][k].  CONTIG_K:
+// the stored matrix is contiguous along k (X[row][k]); else along rows (X[k][row]).
+template <bool CONTIG_K, int ROWS>
+__device__ __forceinline__ void stage(uint16_t (*S)[LDK], const uint16_t *__restrict__ X, long long ld, int r0,
+                                      int nrows, int k0, int K, bool vec, int t) {
+    constexpr int CH = ROWS * BK / 8;   // 8-element chunks in the tile
+#pragma unroll
+    for (int q = 0; q < CH / GT; ++q) {
+        const int c = q * GT + t;
+        if (CONTIG_K) {
+            const int rr = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+            const int gr = r0 + rr;
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (gr < nrows && k0 + kk < K) x = load8(X + (size_t)gr * ld, k0 + kk, K, vec);
+            *reinterpret_cast<uint4 *>(&S[rr][kk]) = x;
+        } else {
+            const int kk = c / (ROWS / 8), rr = (c % (ROWS / 8)) * 8;
+            const int gk = k0 + kk;
+            uint4 x = make_uint4(0, 0, 0, 0);
+            if (gk < K && r0 + rr < nrows) x = load8(X + (size_t)gk * ld, r0 + rr, nrows, vec);
+            const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                S[rr + 2 * j][kk] = (uint16_t)(w[j] & 0xffffu);
+                S[rr + 2 * j + 1][kk] = (uint16_t)(w[j] >> 16);
+            }
+        }
+    }
+}
+
+template <bool TA, bool TB>
+__global__ __launch_bounds__(GT) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, long long lda,
+                                             const uint16_t *__restrict__ B, long long ldb, int vec_a, int vec_b,
+                                             float *__restrict__ Cf, uint16_t *__restrict__ Cb, long long ldc,
+                                             const float *__restrict__ bias, int relu,
+                                             const uint16_t *__restrict__ mask, long long ldm, float alpha) {
+    __shared__ __attribute__((aligned(16))) uint16_t As[BM][LDK];   // [m][k]
+    __shared__ __attribute__((aligned(16))) uint16_t Bs[BN][LDK];   // [n][k]
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int wm = (wv >> 1) * 64, wn = (wv & 1) * 64;
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        stage<!TA, BM>(As, A, lda, m0, M, k0, K, vec_a != 0, t);
+        stage<TB, BN>(Bs, B, ldb, n0, N, k0, K, vec_b != 0, t);
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 16) {
+            // lane l: row (l % 32) of a 32-row block, k = kk + 8 (l / 32) .. +7
+            const int kl = kk + 8 * (lane >> 5);
+            bf16x8 fa[2], fb[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) fa[a] = *reinterpret_cast<const bf16x8 *>(&As[wm + 32 * a + (lane & 31)][kl]);
+#pragma unroll
+            for (int b = 0; b < 2; ++b) fb[b] = *reinterpret_cast<const bf16x8 *>(&Bs[wn + 32 * b + (lane & 31)][kl]);
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // D layout of a 32 x 32 block: register r of lane l is row 8 (r / 4) + 4 (l / 32) + r % 4, column l % 32
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int gm = m0 + wm + 32 * a + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+                const int gn = n0 + wn + 32 * b + (lane & 31);
+                if (gm < M && gn < N) {
+                    float v = alpha * acc[a][b][r];
+                    if (bias) v += bias[gn];
+                    if (relu) v = fmaxf(v, 0.f);
+                    if (mask && !(bf2f(mask[(size_t)gm * ldm + gn]) > 0.f)) v = 0.f;
+                    if (Cf) Cf[(size_t)gm * ldc + gn] = v;
+                    if (Cb) Cb[(size_t)gm * ldc + gn] = f2bf(v);
+                }
+            }
+}
+
+// ---------------------------------------------------------------------------
+// features: 64 per vector
+//   [0,16)  W_ii / mean_j W_jj                  (the MoP weights, Sec. III-A-2)
+//   [16,32) Re c0_i, [32,48) Im c0_i           c0_i = -(s-tilde_i / tau) / W_ii, the
+//                                                level centres of the zero perturbation
+//   [48,64) w_i |c0_i - round_box(c0_i)|^2 / mean w   (rank-0 PED share per level)
+// levels beyond N are zero.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64) void k_features(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                                 const float2 *__restrict__ s, float tau, int n_sc, int n_sym,
+                                                 uint16_t *__restrict__ feat) {
+    constexpr int NP = VP_PACKED(N);
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const size_t v = (size_t)blockIdx.x * 64 + threadIdx.x;
+    if (v >= n_vec) return;
+    const int sc = (int)(v / n_sym);
+    const float2 *Wc = W + (size_t)sc * NP;
+    const uint8_t *pm = perm + (size_t)sc * N;
+    uint16_t *f = feat + v * 64;
+    float wd[N], mean = 0.f, wmean = 0.f;
+    for (int i = 0; i < N; ++i) {
+        wd[i] = Wc[vp_pidx(N, i, i)].x;
+        mean += wd[i];
+        wmean += wd[i] * wd[i];
+    }
+    mean /= N;
+    wmean /= N;
+    const bool ok = (wd[0] > 0.f) && isfinite(wd[0]) && (mean > 0.f) && isfinite(mean) && isfinite(wmean);
+    const float inv_tau = 1.0f / tau;
+    for (int i = 0; i < 16; ++i) {
+        float a = 0.f, cx = 0.f, cy = 0.f, d0 = 0.f;
+        if (i < N && ok) {
+            float re = 0.f, im = 0.f;
+            for (int j = 0; j <= i; ++j) {
+                const float2 w = Wc[vp_pidx(N, i, j)];
+                const int u = pm[j] < N ? pm[j] : N - 1;
+                const float2 x = s[(size_t)u * n_vec + v];
+                re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
+                im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+            }
+            a = wd[i] / mean;
+            cx = -(re * inv_tau) / wd[i];
+            cy = -(im * inv_tau) / wd[i];
+            const float ex = cx - vp_nearest_offset(cx), ey = cy - vp_nearest_offset(cy);
+            d0 = wd[i] * wd[i] * (ex * ex + ey * ey) / wmean;
+        }
+        f[i] = f2bf(a);
+        f[16 + i] = f2bf(cx);
+        f[32 + i] = f2bf(cy);
+        f[48 + i] = f2bf(d0);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// ranks of a given perturbation along the tree (labels): at each level the
+// rank r with DEMAP(c_i, r) == l_i, the same DEMAP the search uses; 15 if the
+// symbol is not in the box.  Walks with the search's arithmetic.
+// ---------------------------------------------------------------------------
+template <int N>
+__global__ __launch_bounds__(64) void k_ranks(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                              const float2 *__restrict__ s, float tau, int n_sc, int n_sym,
+                                              const int8_t *__restrict__ l, uint8_t *__restrict__ ranks) {
+    constexpr int NP = VP_PACKED(N);
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const size_t v = (size_t)blockIdx.x * 64 + threadIdx.x;
+    if (v >= n_vec) return;
+    const int sc = (int)(v / n_sym);
+    const float2 *Wc = W + (size_t)sc * NP;
+    const uint8_t *pm = perm + (size_t)sc * N;
+    const float inv_tau = 1.0f / tau;
+    float2 r[N];
+    for (int i = 0; i < N; ++i) {
+        float re = 0.f, im = 0.f;
+        for (int j = 0; j <= i; ++j) {
+            const float2 w = Wc[vp_pidx(N, i, j)];
+            const int u = pm[j] < N ? pm[j] : N - 1;
+            const float2 x = s[(size_t)u * n_vec + v];
+            re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
+            im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+        }
+        r[i] = make_float2(re * inv_tau, im * inv_tau);
+    }
+    for (int i = 0; i < N; ++i) {
+        const int u = pm[i] < N ? pm[i] : N - 1;
+        const int8_t *li = l + ((size_t)u * n_vec + v) * 2;
+        const float la = (float)li[0], lb = (float)li[1];
+        const float wii = Wc[vp_pidx(N, i, i)].x;
+        const float linv = 1.0f / wii;
+        const float cx = -(r[i].x * linv), cy = -(r[i].y * linv);
+        int rk = 15;
+        for (int q = 8; q >= 0; --q) {
+            float a, b;
+            vp_demapN(cx, cy, q, VP_DEMAP_LUT, a, b);
+            if (a == la && b == lb) rk = q;
+        }
+        ranks[v * N + i] = (uint8_t)rk;
+        for (int m = i + 1; m < N; ++m) {
+            const float2 w = Wc[vp_pidx(N, m, i)];
+            r[m].x = fmaf(w.x, la, fmaf(-w.y, lb, r[m].x));
+            r[m].y = fmaf(w.x, lb, fmaf(w.y, la, r[m].y));
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// top-64 of each row of fp32 scores [rows][C] (C <= 4096): indices ordered by
+// (score desc, index asc), and the softmax mass of the selected 64.  One wave
+// per row: 4 radix passes of 8 bits over order-preserving keys find the 64th
+// key, then the selected entries are sorted by a wave bitonic sort.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t okey(float f) {   // larger float -> larger key
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+__global__ __launch_bounds__(64) void k_topk64(const float *__restrict__ S, int rows, int C,
+                                               int32_t *__restrict__ idx_out, float *__restrict__ mass_out) {
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t sel_key[64];
+    __shared__ uint32_t sel_idx[64];
+    const int row = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (row >= rows) return;
+    const float *x = S + (size_t)row * C;
+    constexpr int PER = 4096 / 64;
+    uint32_t key[PER];
+    float mx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = q * 64 + lane;
+        const float f = c < C ? x[c] : -INFINITY;
+        key[q] = c < C ? okey(f) : 0u;
+        mx = fmaxf(mx, f);
+    }
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    // radix select: find the key of rank 63 in descending order
+    uint32_t prefix = 0, pmask = 0;
+    int need = 64;   // how many still to take at or below the current prefix
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (int b = lane; b < 256; b += 64) hist[b] = 0;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q)
+            if (q * 64 + lane < C && (key[q] & pmask) == prefix) atomicAdd(&hist[(key[q] >> shift) & 255u], 1u);
+        __syncthreads();
+        // from the top bin down, find the bin where the cumulative count reaches need
+        uint32_t h[4];
+        for (int j = 0; j < 4; ++j) h[j] = hist[255 - (lane * 4 + j)];
+        uint32_t local = h[0] + h[1] + h[2] + h[3];
+        uint32_t incl = local;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        const uint32_t excl = incl - local;
+        int found_bin = -1, taken_before = 0;
+        uint32_t run = excl;
+        for (int j = 0; j < 4; ++j) {
+            if (found_bin < 0 && run + h[j] >= (uint32_t)need && run < (uint32_t)need) {
+                found_bin = 255 - (lane * 4 + j);
+                taken_before = (int)run;
+            }
+            run += h[j];
+        }
+        const unsigned long long bal = __ballot(found_bin >= 0);
+        const int src = __ffsll((long long)bal) - 1;
+        const int fb = __shfl(found_bin, src);
+        const int tb = __shfl(taken_before, src);
+        prefix |= (uint32_t)fb << shift;
+        pmask |= 255u << shift;
+        need -= tb;
+        __syncthreads();
+    }
+    // prefix is the key of the 64th largest; take every key above it and the
+    // `need` equal ones of smallest column
+    const uint32_t T = prefix;
+    int nsel = 0, eq_taken = 0;
+    float se = 0.f, sall = 0.f;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int c = q * 64 + lane;
+        const bool in = c < C;
+        const float f = in ? x[c] : 0.f;
+        const float e = in ? __expf(f - mx) : 0.f;
+        sall += e;
+        const bool gt = in && key[q] > T;
+        const bool eq = in && key[q] == T;
+        const unsigned long long bg = __ballot(gt);
+        if (gt) {
+            const int pos = min(nsel + __popcll(bg & ((1ull << lane) - 1ull)), 63);
+            sel_key[pos] = key[q];
+            sel_idx[pos] = (uint32_t)c;
+            se += e;
+        }
+        nsel += __popcll(bg);
+        const unsigned long long be = __ballot(eq);
+        const int before = __popcll(be & ((1ull << lane) - 1ull));
+        if (eq && eq_taken + before < need && nsel + before < 64) {
+            sel_key[nsel + before] = key[q];
+            sel_idx[nsel + before] = (uint32_t)c;
+            se += e;
+        }
+        const int took = min(__popcll(be), need - eq_taken);
+        nsel += took;
+        eq_taken += took;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        se += __shfl_xor(se, off);
+        sall += __shfl_xor(sall, off);
+    }
+    __syncthreads();
+    // bitonic sort of 64 (key desc, index asc) across the wave
+    uint32_t k = sel_key[lane], id = sel_idx[lane];
+    for (int size = 2; size <= 64; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t ok_ = __shfl_xor(k, stride), oi = __shfl_xor(id, stride);
+            const bool lower = (lane & stride) == 0;
+            const bool desc = (lane & size) == 0;   // this block sorts descending
+            // "a before b" in the final order: larger key, or equal key and smaller index
+            const bool mine_first = (k > ok_) || (k == ok_ && id < oi);
+            const bool keep = (lower == desc) ? mine_first : !mine_first;
+            if (!keep) {
+                k = ok_;
+                id = oi;
+            }
+        }
+    }
+    idx_out[(size_t)row * 64 + lane] = (int32_t)id;
+    if (lane == 0 && mass_out) mass_out[row] = sall > 0.f ? se / sall : 0.f;
+}
+
+// ---------------------------------------------------------------------------
+// softmax cross-entropy over rows of fp32 logits with integer labels (-1 =
+// ignored row): loss per row (fp32) and d loss / d logits = (p - onehot) *
+// scale, written in bf16 (scale = 1 / number of labelled rows).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_softmax_ce(const float *__restrict__ Z, int rows, int C,
+                                                    const int32_t *__restrict__ label, float scale,
+                                                    float *__restrict__ loss, uint16_t *__restrict__ dZ) {
+    __shared__ float red[4];
+    const int row = blockIdx.x, t = threadIdx.x;
+    const float *z = Z + (size_t)row * C;
+    const int y = label[row];
+    float mx = -INFINITY;
+    for (int c = t; c < C; c += 256) mx = fmaxf(mx, z[c]);
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((t & 63) == 0) red[t >> 6] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    __syncthreads();
+    float se = 0.f;
+    for (int c = t; c < C; c += 256) se += __expf(z[c] - mx);
+    for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
+    if ((t & 63) == 0) red[t >> 6] = se;
+    __syncthreads();
+    se = red[0] + red[1] + red[2] + red[3];
+    const float lse = mx + __logf(se);
+    const bool use = y >= 0 && y < C;
+    for (int c = t; c < C; c += 256) {
+        const float p = __expf(z[c] - lse);
+        dZ[(size_t)row * C + c] = f2bf(use ? (p - (c == y ? 1.f : 0.f)) * scale : 0.f);
+    }
+    if (t == 0) loss[row] = use ? lse - z[y] : 0.f;
+}
+
+// column sums of a bf16 matrix [rows][cols] -> fp32 [cols]
+__global__ __launch_bounds__(256) void k_colsum(const uint16_t *__restrict__ X, int rows, int cols,
+                                                float *__restrict__ out) {
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= cols) return;
+    float acc = 0.f;
+    for (int r = 0; r < rows; ++r) acc += bf2f(X[(size_t)r * cols + c]);
+    out[c] = acc;
+}
+
+// per-vector path table: the Kl proposed vocabulary entries, then the first
+// Kf paths of the subcarrier's fixed (MoP) table.
+__global__ __launch_bounds__(256) void k_learned_table(const uint8_t *__restrict__ vocab, int V, int N,
+                                                       const int32_t *__restrict__ top, int Kl,
+                                                       const uint8_t *__restrict__ fixed, int Kfix_stride,
+                                                       int Kf, int n_sc, int n_sym, uint8_t *__restrict__ table) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const int Kt = Kl + Kf;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= n_vec * Kt * N) return;
+    const size_t v = e / ((size_t)Kt * N);
+    const int rem = (int)(e % ((size_t)Kt * N));
+    const int k = rem / N, i = rem % N;
+    uint8_t r;
+    if (k < Kl) {
+        int id = top[v * Kl + k];
+        id = id < 0 ? 0 : (id >= V ? V - 1 : id);
+        r = vocab[(size_t)id * N + i];
+    } else {
+        const int sc = (int)(v / n_sym);
+        r = fixed[(size_t)sc * Kfix_stride * N + (size_t)(k - Kl) * N + i];
+    }
+    table[e] = r;
+}
+
+}  // namespace
+
+int launch_gemm(int M, int N, int K, const uint16_t *A, long long lda, int transA, const uint16_t *B, long long ldb,
+                int transB, float *Cf, uint16_t *Cb, long long ldc, const float *bias, int relu,
+                const uint16_t *mask, long long ldm, float alpha, hipStream_t st) {
+    if (M == 0 || N == 0) return VP_OK;
+    const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
+    // 16-byte loads need 16-byte aligned rows
+    const int va = ((reinterpret_cast<uintptr_t>(A) & 15) == 0) && (lda % 8 == 0);
+    const int vb = ((reinterpret_cast<uintptr_t>(B) & 15) == 0) && (ldb % 8 == 0);
+#define VP_G(ta, tb)                                                                                              \
+    hipLaunchKernelGGL((k_gemm<ta, tb>), grid, dim3(GT), 0, st, M, N, K, A, lda, B, ldb, va, vb, Cf, Cb, ldc, bias, \
+                       relu, mask, ldm, alpha)
+    if (!transA && !transB) VP_G(false, false);
+    else if (!transA && transB) VP_G(false, true);
+    else if (transA && !transB) VP_G(true, false);
+    else VP_G(true, true);
+#undef VP_G
+    return launch_status();
+}
+
+int launch_features(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
+                    uint16_t *feat, hipStream_t st) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    if (n_vec == 0) return VP_OK;
+    const dim3 g((unsigned)((n_vec + 63) / 64));
+    switch (N) {
+#define VP_CASE(n) \
+    case n: hipLaunchKernelGGL(k_features<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, feat); break;
+        VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
+        VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
+#undef VP_CASE
+        default: return VP_EUNSUPPORTED;
+    }
+    return launch_status();
+}
+
+int launch_ranks(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
+                 const int8_t *l, uint8_t *ranks, hipStream_t st) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    if (n_vec == 0) return VP_OK;
+    const dim3 g((unsigned)((n_vec + 63) / 64));
+    switch (N) {
+#define VP_CASE(n) \
+    case n: hipLaunchKernelGGL(k_ranks<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, l, ranks); break;
+        VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
+        VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
+#undef VP_CASE
+        default: return VP_EUNSUPPORTED;
+    }
+    return launch_status();
+}
+
+int launch_topk64(const float *S, int rows, int C, int32_t *idx, float *mass, hipStream_t st) {
+    if (rows == 0) return VP_OK;
+    hipLaunchKernelGGL(k_topk64, dim3(rows), dim3(64), 0, st, S, rows, C, idx, mass);
+    return launch_status();
+}
+
+int launch_softmax_ce(const float *Z, int rows, int C, const int32_t *label, float scale, float *loss,
+                      uint16_t *dZ, hipStream_t st) {
+    if (rows == 0) return VP_OK;
+    hipLaunchKernelGGL(k_softmax_ce, dim3(rows), dim3(256), 0, st, Z, rows, C, label, scale, loss, dZ);
+    return launch_status();
+}
+
+int launch_colsum(const uint16_t *X, int rows, int cols, float *out, hipStream_t st) {
+    if (cols == 0) return VP_OK;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, st, X, rows, cols, out);
+    return launch_status();
+}
+
+int launch_learned_table(const uint8_t *vocab, int V, int N, const int32_t *top, int Kl, const uint8_t *fixed,
+                         int Kfix, int Kf, int n_sc, int n_sym, uint8_t *table, hipStream_t st) {
+    const size_t total = (size_t)n_sc * n_sym * (Kl + Kf) * N;
+    if (total == 0) return VP_OK;
+    hipLaunchKernelGGL(k_learned_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, vocab, V, N, top,
+                       Kl, fixed, Kfix, Kf, n_sc, n_sym, table);
+    return launch_status();
+}
+
+}  // namespace vp

@@ -182,7 +182,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
     if (t < N) s_r0[t] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, t, 1.0f / tau);
     __syncthreads();
 
-    const uint8_t *P = paths + (size_t)sc * pstride;
+    const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride;
     unsigned long long best = ~0ull;
     for (int k = t; k < K; k += kT) {
         const unsigned long long wd = load_word<N>(P, k);
@@ -371,12 +371,84 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
     }
 }
 
+// Small path tables (K up to a few hundred, e.g. per-vector proposals): one
+// wave per vector, four vectors per workgroup, so that no lane idles on a
+// table shorter than the workgroup.
+constexpr int kWV = 4;          // vectors (waves) per workgroup
+constexpr int kWaveMaxK = 192;  // tables up to this size use one wave per vector
+
+template <int N>
+__global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restrict__ W,
+                                                          const uint8_t *__restrict__ perm,
+                                                          const float2 *__restrict__ s, float tau,
+                                                          const uint8_t *__restrict__ paths, int K,
+                                                          long long pstride, int n_sym, size_t n_vec,
+                                                          unsigned flags, float *__restrict__ cost_out,
+                                                          int32_t *__restrict__ kidx_out) {
+    __shared__ float2 s_r0[kWV][N];
+    __shared__ float s_linv[kWV][N];
+    __shared__ float s_wdiag[kWV][N];
+    __shared__ uint8_t s_perm[kWV][N];
+
+    constexpr int NP = VP_PACKED(N);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int t = threadIdx.x & 63;
+    const size_t v0 = (size_t)blockIdx.x * kWV + wv;
+    const bool live = v0 < n_vec;   // the last workgroup may hold fewer vectors
+    const size_t v = live ? v0 : n_vec - 1;
+    const int sc = (int)(v / n_sym);
+    const float2 *__restrict__ Wc = W + (size_t)sc * NP;
+    const float w00 = Wc[0].x;
+    const bool ok = (w00 > 0.f) && isfinite(w00);
+    if (t < N) {
+        s_wdiag[wv][t] = Wc[vp_pidx(N, t, t)].x;
+        s_linv[wv][t] = 1.0f / s_wdiag[wv][t];
+        s_perm[wv][t] = perm[(size_t)sc * N + t];
+    }
+    __syncthreads();
+    if (t < N) s_r0[wv][t] = stilde_over_tau<N>(Wc, s_perm[wv], s, v, n_vec, t, 1.0f / tau);
+    __syncthreads();
+    if (!live) return;
+    if (!ok) {   // failed preprocessing: l = 0, cost = NaN
+        if (t == 0) {
+            cost_out[v] = __int_as_float(0x7fc00000);
+            kidx_out[v] = -1;
+        }
+        return;
+    }
+
+    const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride;
+    const float tau2 = tau * tau;
+    unsigned long long best = ~0ull;
+    for (int k = t; k < K; k += 64) {
+        const unsigned long long wd = load_word<N>(P, k);
+        float2 r[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i] = s_r0[wv][i];
+        const float ped = walk<N, true, false>(Wc, s_linv[wv], s_wdiag[wv], r, wd, VP_DEMAP_LUT, nullptr, nullptr);
+        best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
+    }
+    if ((flags & VP_INCLUDE_ZERO) && t == 0) {
+        float z = 0.f;
+        for (int i = 0; i < N; ++i) {
+            z = fmaf(s_r0[wv][i].x, s_r0[wv][i].x, z);
+            z = fmaf(s_r0[wv][i].y, s_r0[wv][i].y, z);
+        }
+        best = umin64(best, ((unsigned long long)__float_as_uint(z * tau2) << 32) | (unsigned)K);
+    }
+    best = wave_min(best);
+    if (t == 0) {
+        cost_out[v] = __uint_as_float((unsigned)(best >> 32));
+        kidx_out[v] = (int32_t)(best & 0xffffffffull);
+    }
+}
+
 template <int N>
 __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict__ W,
                                                         const uint8_t *__restrict__ perm,
                                                         const float2 *__restrict__ s, float tau,
                                                         const uint8_t *__restrict__ paths, int K,
-                                                        long long pstride, int n_sc, int n_sym,
+                                                        long long pstride, int n_sc, int n_sym, unsigned flags,
                                                         const int32_t *__restrict__ kidx,
                                                         int8_t *__restrict__ l_out) {
     constexpr int NP = VP_PACKED(N);
@@ -400,7 +472,7 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
             linv[i] = 1.0f / wdiag[i];
             r[i] = stilde_over_tau<N>(Wc, pm, s, v, n_vec, i, inv_tau);
         }
-        const uint8_t *P = paths + (size_t)sc * pstride + (size_t)k * N;
+        const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride + (size_t)k * N;
         unsigned long long wd = 0;
         for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
         (void)walk<N, false, true>(Wc, linv, wdiag, r, wd, VP_DEMAP_LUT, ra, rb);
@@ -427,12 +499,15 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
         (void)attr_once;
         hipLaunchKernelGGL(k_search_trie<N>, dim3((unsigned)n_vec), dim3(kTT), smem, st, W, perm, s, tau, paths,
                            order, K, (long long)pstride, n_sym, flags, cost, kidx);
+    } else if (K <= kWaveMaxK) {
+        hipLaunchKernelGGL(k_search_wave<N>, dim3((unsigned)((n_vec + kWV - 1) / kWV)), dim3(64 * kWV), 0, st, W,
+                           perm, s, tau, paths, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx);
     } else {
         hipLaunchKernelGGL(k_search<N>, dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
                            (long long)pstride, n_sym, flags, cost, kidx);
     }
     hipLaunchKernelGGL(k_search_finalize<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
-                       tau, paths, K, (long long)pstride, n_sc, n_sym, kidx, l);
+                       tau, paths, K, (long long)pstride, n_sc, n_sym, flags, kidx, l);
     return launch_status();
 }
 

@@ -11,10 +11,10 @@ from typing import NamedTuple, Optional
 import torch
 
 from . import _lib
-from ._lib import VP_INCLUDE_ZERO, check
+from ._lib import VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, check
 
 __all__ = ["Prep", "SearchOut", "SEOut", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
-           "VP_INCLUDE_ZERO", "version"]
+           "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "version"]
 
 
 def packed_size(n: int) -> int:
@@ -92,8 +92,9 @@ def paths_mop(w2: torch.Tensor, K: int, out: Optional[torch.Tensor] = None,
 def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
            n_sym: int, flags: int = VP_INCLUDE_ZERO, out: Optional[SearchOut] = None,
            order: Optional[torch.Tensor] = None) -> SearchOut:
-    """vp_search: paths is [K][N] (one table for all subcarriers) or [n_sc][K][N];
-    order (int16 [n_sc][2][K] from paths_mop) enables prefix sharing."""
+    """vp_search: paths is [K][N] (one table for all subcarriers), [n_sc][K][N],
+    or with VP_PATHS_PER_VECTOR in flags [n_vec][K][N]; order (int16
+    [n_sc][2][K] from paths_mop) enables prefix sharing."""
     lib = _lib.load()
     n_sc = W.shape[0]
     N = perm.shape[1]
@@ -101,8 +102,9 @@ def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, pat
     if paths.dim() == 2:
         K, stride = paths.shape[0], 0
     else:
-        if paths.shape[0] != n_sc:
-            raise ValueError("paths: first dimension must be n_sc")
+        lead = n_vec if (flags & VP_PATHS_PER_VECTOR) else n_sc
+        if paths.shape[0] != lead:
+            raise ValueError(f"paths: first dimension must be {lead}")
         K, stride = paths.shape[1], paths.shape[1] * paths.shape[2]
     if paths.shape[-1] != N:
         raise ValueError("paths: last dimension must be N")

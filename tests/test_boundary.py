@@ -14,7 +14,8 @@ import pytest
 from oracle import vp_oracle as O
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "vp.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 PKG = os.path.join(ROOT, "paper_2602_12098_amd")
 
 
@@ -25,13 +26,15 @@ def lib():
 
 
 def declared_functions():
-    text = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(vp_[a-z_]+)\(", text, flags=re.M)))
+    text = "".join(open(h).read() for h in HEADERS)
+    return sorted(set(re.findall(r"^(?:int|const char \*)\s*(vp_[a-z0-9_]+)\(", text, flags=re.M)))
 
 
 def test_header_symbols_exported(lib):
     names = declared_functions()
-    assert {"vp_preprocess", "vp_paths_mop", "vp_search", "vp_precode", "vp_strerror"} <= set(names)
+    assert {"vp_preprocess", "vp_paths_mop", "vp_search", "vp_precode", "vp_strerror", "vp_sphere_encode",
+            "vp_mlp_features", "vp_path_ranks", "vp_gemm_bf16", "vp_topk64", "vp_softmax_xent", "vp_colsum_bf16",
+            "vp_learned_paths"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(PKG, "libvp.so")],
@@ -153,3 +156,42 @@ def test_product_never_imports_oracle():
             if f.endswith((".py", ".hip", ".hpp", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in re.sub(r"#.*|//.*", "", text).lower(), f
+
+
+def test_learned_argument_validation():
+    from paper_2602_12098_amd import learn
+    from paper_2602_12098_amd._lib import VP_EINVAL, VP_EUNSUPPORTED, VP_OK
+    lib = learn._load()
+    P = ctypes.c_void_p(16)   # never dereferenced: validation fails or returns before any launch
+    assert lib.vp_mlp_features(None, None, None, 8.0, 1, 14, 4, None, None) == VP_EINVAL
+    assert lib.vp_mlp_features(P, P, P, 0.0, 1, 14, 4, P, None) == VP_EINVAL
+    assert lib.vp_mlp_features(P, P, P, 8.0, 1, 14, 17, P, None) == VP_EUNSUPPORTED
+    assert lib.vp_mlp_features(None, None, None, 8.0, 0, 14, 4, None, None) == VP_OK
+    assert lib.vp_path_ranks(P, P, P, 8.0, None, 1, 14, 4, P, None) == VP_EINVAL
+    assert lib.vp_path_ranks(P, P, P, 8.0, P, 1, 0, 4, P, None) == VP_EINVAL
+    # gemm: bad sizes, leading dimensions, flags, no output
+    assert lib.vp_gemm_bf16(-1, 4, 4, P, 4, 0, P, 4, 0, None, 0, None, 0, 1.0, P, None, 4, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(4, 4, 4, P, 3, 0, P, 4, 0, None, 0, None, 0, 1.0, P, None, 4, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(4, 5, 8, P, 8, 0, P, 4, 0, None, 0, None, 0, 1.0, P, None, 5, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(4, 5, 8, P, 8, 0, P, 8, 1, None, 2, None, 0, 1.0, P, None, 5, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(4, 5, 8, P, 8, 0, P, 8, 1, None, 0, None, 0, 1.0, None, None, 5, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(4, 5, 8, P, 8, 0, P, 8, 1, None, 0, P, 4, 1.0, P, None, 5, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(4, 5, 8, P, 8, 0, P, 8, 1, None, 0, None, 0, 1.0, P, None, 4, None) == VP_EINVAL
+    assert lib.vp_gemm_bf16(0, 5, 8, None, 8, 0, None, 8, 1, None, 0, None, 0, 1.0, P, None, 5, None) == VP_OK
+    assert lib.vp_gemm_bf16(4, 5, 8, None, 8, 0, P, 8, 1, None, 0, None, 0, 1.0, P, None, 5, None) == VP_EINVAL
+    # top-k / loss / colsum / tables
+    assert lib.vp_topk64(P, 4, 63, P, None, None) == VP_EINVAL
+    assert lib.vp_topk64(P, 4, 4097, P, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_topk64(None, 0, 100, None, None, None) == VP_OK
+    assert lib.vp_topk64(None, 3, 100, P, None, None) == VP_EINVAL
+    assert lib.vp_softmax_xent(P, 3, 0, P, 1.0, P, P, None) == VP_EINVAL
+    assert lib.vp_softmax_xent(P, 3, 10, P, float("inf"), P, P, None) == VP_EINVAL
+    assert lib.vp_softmax_xent(P, 3, 10, None, 1.0, P, P, None) == VP_EINVAL
+    assert lib.vp_colsum_bf16(P, -1, 3, P, None) == VP_EINVAL
+    assert lib.vp_colsum_bf16(None, 3, 3, P, None) == VP_EINVAL
+    assert lib.vp_learned_paths(P, 10, 4, P, 64, P, 8, 9, 2, 14, P, None) == VP_EINVAL     # K_fixed > table
+    assert lib.vp_learned_paths(P, 0, 4, P, 64, P, 8, 8, 2, 14, P, None) == VP_EINVAL     # empty vocabulary
+    assert lib.vp_learned_paths(P, 10, 17, P, 64, P, 8, 8, 2, 14, P, None) == VP_EUNSUPPORTED
+    assert lib.vp_learned_paths(P, 10, 4, P, 4000, P, 200, 200, 2, 14, P, None) == VP_EUNSUPPORTED
+    assert lib.vp_learned_paths(P, 10, 4, P, 0, P, 8, 0, 2, 14, P, None) == VP_EINVAL     # empty table
+    assert lib.vp_learned_paths(P, 10, 4, None, 64, P, 8, 8, 2, 14, P, None) == VP_EINVAL
