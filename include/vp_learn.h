@@ -40,25 +40,35 @@ enum {
     VP_EPI_RELU = 1 /* C = max(C, 0) after the bias */
 };
 
+/* feature kinds of vp_mlp_features */
+enum {
+    VP_FEAT_ZERO_CENTRES = 0, /* centres of the zero perturbation */
+    VP_FEAT_RANK0_WALK = 1    /* centres along the rank-0 (nearest point) walk */
+};
+
 /*
  * vp_mlp_features -- the network input of every vector (bf16 [n_vec][64]).
  *
- * With W, perm from vp_preprocess and the zero-perturbation centres of the
- * tree, c0_i = -(W s_pi)_i / (tau W_ii) (the centres of Sec. III-A-2 before
- * any perturbation is chosen), the features of vector v are, for levels
- * i < N (slots of levels >= N are 0):
+ * W, perm from vp_preprocess.  For levels i < N (slots of levels >= N are 0),
+ * with the level centres c_i of Sec. III-A-2:
  *   [i]       W_ii / mean_j W_jj      (the MoP weights of the subcarrier)
- *   [16 + i]  Re c0_i
- *   [32 + i]  Im c0_i
+ * and, for kind VP_FEAT_ZERO_CENTRES, the centres of the zero perturbation,
+ * c0_i = -(W s_pi)_i / (tau W_ii):
+ *   [16 + i]  Re c0_i,  [32 + i]  Im c0_i
  *   [48 + i]  W_ii^2 |c0_i - b0(c0_i)|^2 / mean_j W_jj^2, b0 = nearest box point
+ * or, for kind VP_FEAT_RANK0_WALK, the centres c_i of the path that takes the
+ * nearest box point b_i at every level (float32, the search's own walk):
+ *   [16 + i]  Re (c_i - b_i),  [32 + i]  Im (c_i - b_i)
+ *   [48 + i]  W_ii^2 (d1_i - d0_i) / mean_j W_jj^2, d0_i / d1_i the squared
+ *             distances of c_i to its nearest / second-nearest box point
  * A failed subcarrier (W_00 not finite and > 0) gets all-zero features.
  * Computed in float32 and rounded once to bf16 (round to nearest even).
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, n_r < 1, tau <= 0
- * or not finite; VP_EUNSUPPORTED for n_r > 16.
+ * or not finite, an unknown kind; VP_EUNSUPPORTED for n_r > 16.
  */
 int vp_mlp_features(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym,
-                    int n_r, uint16_t *feat, void *stream);
+                    int n_r, uint32_t kind, uint16_t *feat, void *stream);
 
 /*
  * vp_path_ranks -- the position vector of a given perturbation (labels).

@@ -10,6 +10,7 @@ Contents, each a plain restatement of its definition in float64:
   bf16_round       IEEE binary32 -> bfloat16, round to nearest even (the format)
   features         the 64 network inputs: MoP weights and zero-perturbation
                    centres of the tree (Sec. III-A-2 centres with l = 0)
+  features_walk    the same weights with the centres along the rank-0 walk
   path_ranks       position vector of a given perturbation: the rank of each
                    level's symbol in the (distance, canonical index) box order
   mlp_forward      64 -> 256 -> 256 -> V, ReLU (optionally rounding the hidden
@@ -21,7 +22,8 @@ Contents, each a plain restatement of its definition in float64:
 
 Pins (tests/test_oracle_learn.py): bf16 rounding against hand-worked bit
 patterns and torch's own conversion; features against the first-level centre,
-the rank-0 PED and the zero-perturbation cost; ranks as the inverse of the
+the rank-0 PED and the zero-perturbation cost; walk features against the
+search oracle's rank-0 path cost and its rank-1 neighbours; ranks as the inverse of the
 search's rank walk; the backward against central finite differences and
 torch autograd in float64; the loss against log C for constant logits.
 """
@@ -31,7 +33,7 @@ from typing import NamedTuple, Optional
 
 import numpy as np
 
-from .vp_oracle import BOX, demap_walk
+from .vp_oracle import BOX, demap_walk, sqabs
 
 N_FEATURES = 64
 MAXN = 16
@@ -84,8 +86,47 @@ def features(W, perm, s, tau) -> np.ndarray:
     f[:, :n] = d[None, :] / d.mean()
     f[:, 16:16 + n] = c0.real
     f[:, 32:32 + n] = c0.imag
-    f[:, 48:48 + n] = (d[None, :] ** 2) * np.abs(c0 - b0) ** 2 / np.mean(d ** 2)
+    f[:, 48:48 + n] = (d[None, :] ** 2) * sqabs(c0 - b0) / np.mean(d ** 2)
     return f
+
+
+def features_walk(W, perm, s, tau):
+    """Network input along the rank-0 walk, float64 [V][64]: the path that
+    takes the nearest box point b_i (rank 0 of the box order) at every level
+    has centres c_i (Sec. III-A-2, with the earlier levels' choices in the
+    residual); with d0_i, d1_i the squared distances of c_i to its nearest and
+    second-nearest box points:
+      [i]      W_ii / mean_j W_jj
+      [16+i]   Re (c_i - b_i),   [32+i]  Im (c_i - b_i)
+      [48+i]   W_ii^2 (d1_i - d0_i) / mean_j W_jj^2
+    Slots of levels >= N are zero.  Also returns the smallest gap between the
+    first and second distances along the walk (near 0: the rank-0 choice is
+    close to a tie and float32 may walk another path; d1 itself does not
+    depend on which of two equally far points is second)."""
+    W = np.asarray(W, dtype=np.complex128)
+    perm = np.asarray(perm, dtype=np.int64)
+    s = np.asarray(s, dtype=np.complex128)
+    if s.ndim == 1:
+        s = s[:, None]
+    n, V = s.shape
+    d = np.real(np.diag(W))
+    resid = (W @ s[perm, :]).T
+    f = np.zeros((V, N_FEATURES))
+    f[:, :n] = d[None, :] / d.mean()
+    gap = np.full(V, np.inf)
+    for i in range(n):
+        c = -resid[:, i] / (tau * W[i, i])
+        dist = sqabs(c[:, None] - BOX[None, :])
+        order = np.argsort(dist, axis=1, kind="stable")
+        ds = np.take_along_axis(dist, order, axis=1)
+        b = BOX[order[:, 0]]
+        f[:, 16 + i] = (c - b).real
+        f[:, 32 + i] = (c - b).imag
+        f[:, 48 + i] = d[i] ** 2 * (ds[:, 1] - ds[:, 0]) / np.mean(d ** 2)
+        gap = np.minimum(gap, ds[:, 1] - ds[:, 0])
+        if i + 1 < n:
+            resid[:, i + 1:] += tau * W[None, i + 1:, i] * b[:, None]
+    return f, gap
 
 
 def path_ranks(W, perm, s, tau, l):
@@ -111,7 +152,7 @@ def path_ranks(W, perm, s, tau, l):
     margin = np.full(V, np.inf)
     for i in range(n):
         c = -resid[:, i] / (tau * W[i, i])
-        dist = np.abs(c[:, None] - BOX[None, :]) ** 2
+        dist = sqabs(c[:, None] - BOX[None, :])
         order = np.argsort(dist, axis=1, kind="stable")
         pos = np.argmax(BOX[order] == lp[:, i:i + 1], axis=1)
         found = np.any(BOX[order] == lp[:, i:i + 1], axis=1)

@@ -50,6 +50,14 @@ import numpy as np
 BOX = np.array([complex(bx, by) for bx in (-1, 0, 1) for by in (-1, 0, 1)], dtype=np.complex128)
 NBOX = 9
 
+def sqabs(z):
+    """|z|^2 as Re^2 + Im^2: no square root, so two equal distances compare
+    equal whenever their operands are exact (the tie rule of the box order
+    needs exact ties to be seen as ties)."""
+    z = np.asarray(z)
+    return z.real ** 2 + z.imag ** 2
+
+
 STATUS_OK = 0
 STATUS_NOT_PD = 1
 STATUS_NONFINITE = 2
@@ -260,7 +268,7 @@ def demap_walk(W, st, tau, ranks):
     for i in range(n):
         wii = W[i, i]
         c = -resid[:, :, i] / (tau * wii)
-        d = np.abs(c[:, :, None] - BOX[None, None, :]) ** 2             # [V][P][9]
+        d = sqabs(c[:, :, None] - BOX[None, None, :])                    # [V][P][9]
         order = np.argsort(d, axis=2, kind="stable")                      # (d, j) order
         dsorted = np.take_along_axis(d, order, axis=2)
         r = np.broadcast_to(ranks[None, :, i], (V, P))[:, :, None]
@@ -359,7 +367,7 @@ def sphere_encode(W, perm, s, tau, radius: float = math.inf):
     def rec(i, resid, ped):
         wii = W[i, i]
         c = -resid[i] / (tau * wii)
-        d = np.abs(c - BOX) ** 2
+        d = sqabs(c - BOX)
         for j in np.argsort(d, kind="stable"):
             nped = ped + tau * tau * abs(wii) ** 2 * d[j]
             if nped >= best[0]:

@@ -93,12 +93,13 @@ int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, floa
 }
 
 int vp_mlp_features(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym, int n_r,
-                    uint16_t *feat, void *stream) {
+                    uint32_t kind, uint16_t *feat, void *stream) {
     if (n_sc < 0 || n_sym < 1 || n_r < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+    if (kind != VP_FEAT_ZERO_CENTRES && kind != VP_FEAT_RANK0_WALK) return VP_EINVAL;
     if (n_r > kMaxN) return VP_EUNSUPPORTED;
     if (n_sc == 0) return VP_OK;
     if (!W || !perm || !s || !feat) return VP_EINVAL;
-    return launch_features((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, feat,
+    return launch_features((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, kind, feat,
                            (hipStream_t)stream);
 }
 

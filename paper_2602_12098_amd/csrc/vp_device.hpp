@@ -29,7 +29,9 @@ struct vp_axis {
     float o0, o1, o2, A, B;
 };
 
-VP_HD float vp_nearest_offset(float x) { return fminf(fmaxf(rintf(x), -1.0f), 1.0f); }
+// Nearest box offset; half-way between two offsets the smaller one (the
+// canonical index order of equal distances).
+VP_HD float vp_nearest_offset(float x) { return (x == -0.5f) ? -1.0f : fminf(fmaxf(rintf(x), -1.0f), 1.0f); }
 
 VP_HD vp_axis vp_axis_order(float x) {
     vp_axis r;
@@ -66,16 +68,19 @@ VP_HD void vp_demap1(float cx, float cy, int rank, float &a, float &b) {
 // Any rank 0..8: eight cell comparisons form the signature of the box order,
 // a 256 x 9 table gives the cell (p, q) of the requested rank.
 VP_HD int vp_demap_signature(const vp_axis &X, const vp_axis &Y) {
+    // each bit: the first cell comes first in the (distance, j) order; the two
+    // cells always differ in x offset, which decides equal distances
     const float A = X.A, B = X.B, C = Y.A, D = Y.B;
     const float AC = A + C, BC = B + C, AD = A + D;
-    int sig = (int)((C < A) | ((C == A) & (X.o0 < X.o1)));       // (0,1) before (1,0)
-    sig |= (int)(C < B) << 1;                                    // (0,1) before (2,0)
-    sig |= (int)(D < A) << 2;                                    // (0,2) before (1,0)
-    sig |= (int)(D < AC) << 3;                                   // (0,2) before (1,1)
-    sig |= (int)((D < B) | ((D == B) & (X.o0 < X.o2))) << 4;     // (0,2) before (2,0)
-    sig |= (int)(D < BC) << 5;                                   // (0,2) before (2,1)
-    sig |= (int)(AC < B) << 6;                                   // (1,1) before (2,0)
-    sig |= (int)(AD < B) << 7;                                   // (1,2) before (2,0)
+    const bool x01 = X.o0 < X.o1, x02 = X.o0 < X.o2, x12 = X.o1 < X.o2;
+    int sig = (int)((C < A) | ((C == A) & x01));               // (0,1) before (1,0)
+    sig |= (int)((C < B) | ((C == B) & x02)) << 1;             // (0,1) before (2,0)
+    sig |= (int)((D < A) | ((D == A) & x01)) << 2;             // (0,2) before (1,0)
+    sig |= (int)((D < AC) | ((D == AC) & x01)) << 3;           // (0,2) before (1,1)
+    sig |= (int)((D < B) | ((D == B) & x02)) << 4;             // (0,2) before (2,0)
+    sig |= (int)((D < BC) | ((D == BC) & x02)) << 5;           // (0,2) before (2,1)
+    sig |= (int)((AC < B) | ((AC == B) & x12)) << 6;           // (1,1) before (2,0)
+    sig |= (int)((AD < B) | ((AD == B) & x12)) << 7;           // (1,2) before (2,0)
     return sig;
 }
 

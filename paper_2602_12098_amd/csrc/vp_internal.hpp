@@ -32,12 +32,40 @@ int launch_sphere(const float2 *W, const uint8_t *perm, const float2 *s, float t
                   const float *radius, int8_t *l, float *cost, int64_t *nodes, long long max_nodes,
                   hipStream_t st);
 
+// Batched workload: one descriptor per group of subcarriers that share the
+// number of users, perturbation interval, regularisation and path count.
+// Arrays are concatenated group after group; offsets are in elements.
+struct BatchGroup {
+    int U;           // users = tree levels (1..16)
+    int K;           // paths
+    int n_sc;        // subcarriers
+    int n_vec;       // n_sc * n_sym
+    int vt;          // search tile: vectors per wave (1, 2, 4)
+    int pl;          // search tile: paths per lane
+    float tau, alpha;
+    int sc0;         // first subcarrier (over all groups)
+    int v0;          // first vector (over all groups)
+    long long offH;  // H  [n_sc][U][M]
+    long long offW;  // W  [n_sc][U(U+1)/2]
+    long long offN;  // w2 / perm [n_sc][U]
+    long long offG;  // G  [n_sc][M][U]
+    long long offP;  // paths [n_sc][K][U]
+    long long offS;  // s [U][n_vec] (and l [U][n_vec][2] at twice this offset)
+};
+
+int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, int M,
+                            const float2 *H, float2 *W, float *w2, uint8_t *perm, float2 *G, int32_t *status,
+                            hipStream_t st);
+void prepare_batch_kernels();   // kernel attributes, set once before a graph capture
+int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, const float *w2,
+                     uint8_t *paths, hipStream_t st);
+
 // Learned path proposal (vp_learn.hip).
 int launch_gemm(int M, int N, int K, const uint16_t *A, long long lda, int transA, const uint16_t *B, long long ldb,
                 int transB, float *Cf, uint16_t *Cb, long long ldc, const float *bias, int relu,
                 const uint16_t *mask, long long ldm, float alpha, hipStream_t st);
 int launch_features(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
-                    uint16_t *feat, hipStream_t st);
+                    unsigned kind, uint16_t *feat, hipStream_t st);
 int launch_ranks(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
                  const int8_t *l, uint8_t *ranks, hipStream_t st);
 int launch_topk64(const float *S, int rows, int C, int32_t *idx, float *mass, hipStream_t st);

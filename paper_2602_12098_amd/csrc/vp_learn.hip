@@ -198,6 +198,74 @@ __global__ __launch_bounds__(64) void k_features(const float2 *__restrict__ W, c
     }
 }
 
+// features along the rank-0 walk (kind VP_FEAT_RANK0_WALK): the centres c_i
+// of the path that takes the nearest box point b_i at every level (the same
+// float32 walk as the search's rank-0 path), and per level
+//   [i]     W_ii / mean W_jj
+//   [16+i]  Re (c_i - b_i),  [32+i]  Im (c_i - b_i)
+//   [48+i]  W_ii^2 (d1_i - d0_i) / mean W_jj^2, d0 / d1 the squared distances
+//           of c_i to its nearest and second-nearest box points (the PED cost,
+//           in units of tau^2, of taking rank 1 instead of rank 0 at level i)
+template <int N>
+__global__ __launch_bounds__(64) void k_features_walk(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                                      const float2 *__restrict__ s, float tau, int n_sc, int n_sym,
+                                                      uint16_t *__restrict__ feat) {
+    constexpr int NP = VP_PACKED(N);
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const size_t v = (size_t)blockIdx.x * 64 + threadIdx.x;
+    if (v >= n_vec) return;
+    const int sc = (int)(v / n_sym);
+    const float2 *Wc = W + (size_t)sc * NP;
+    const uint8_t *pm = perm + (size_t)sc * N;
+    uint16_t *f = feat + v * 64;
+    float wd[N], mean = 0.f, wmean = 0.f;
+    for (int i = 0; i < N; ++i) {
+        wd[i] = Wc[vp_pidx(N, i, i)].x;
+        mean += wd[i];
+        wmean += wd[i] * wd[i];
+    }
+    mean /= N;
+    wmean /= N;
+    const bool ok = (wd[0] > 0.f) && isfinite(wd[0]) && (mean > 0.f) && isfinite(mean) && isfinite(wmean);
+    if (!ok) {
+        for (int i = 0; i < 64; ++i) f[i] = 0;
+        return;
+    }
+    const float inv_tau = 1.0f / tau;
+    float2 r[N];
+    for (int i = 0; i < N; ++i) {
+        float re = 0.f, im = 0.f;
+        for (int j = 0; j <= i; ++j) {
+            const float2 w = Wc[vp_pidx(N, i, j)];
+            const int u = pm[j] < N ? pm[j] : N - 1;
+            const float2 x = s[(size_t)u * n_vec + v];
+            re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
+            im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+        }
+        r[i] = make_float2(re * inv_tau, im * inv_tau);
+    }
+    for (int i = 0; i < N; ++i) {
+        const float linv = 1.0f / wd[i];
+        const float cx = -(r[i].x * linv), cy = -(r[i].y * linv);
+        float a, b, a1, b1;
+        vp_demap0(cx, cy, a, b);
+        vp_demap1(cx, cy, 1, a1, b1);
+        const float ex = cx - a, ey = cy - b;
+        const float fx = cx - a1, fy = cy - b1;
+        const float d0 = ex * ex + ey * ey, d1 = fx * fx + fy * fy;
+        f[i] = f2bf(wd[i] / mean);
+        f[16 + i] = f2bf(ex);
+        f[32 + i] = f2bf(ey);
+        f[48 + i] = f2bf(wd[i] * wd[i] * (d1 - d0) / wmean);
+        for (int m = i + 1; m < N; ++m) {
+            const float2 w = Wc[vp_pidx(N, m, i)];
+            r[m].x = fmaf(w.x, a, fmaf(-w.y, b, r[m].x));
+            r[m].y = fmaf(w.x, b, fmaf(w.y, a, r[m].y));
+        }
+    }
+    for (int i = N; i < 16; ++i) f[i] = f[16 + i] = f[32 + i] = f[48 + i] = 0;
+}
+
 // ---------------------------------------------------------------------------
 // ranks of a given perturbation along the tree (labels): at each level the
 // rank r with DEMAP(c_i, r) == l_i, the same DEMAP the search uses; 15 if the
@@ -467,13 +535,18 @@ int launch_gemm(int M, int N, int K, const uint16_t *A, long long lda, int trans
 }
 
 int launch_features(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
-                    uint16_t *feat, hipStream_t st) {
+                    unsigned kind, uint16_t *feat, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
     if (n_vec == 0) return VP_OK;
     const dim3 g((unsigned)((n_vec + 63) / 64));
     switch (N) {
-#define VP_CASE(n) \
-    case n: hipLaunchKernelGGL(k_features<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, feat); break;
+#define VP_CASE(n)                                                                                           \
+    case n:                                                                                                  \
+        if (kind == VP_FEAT_RANK0_WALK)                                                                      \
+            hipLaunchKernelGGL(k_features_walk<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, feat); \
+        else                                                                                                 \
+            hipLaunchKernelGGL(k_features<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, feat);      \
+        break;
         VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
         VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
 #undef VP_CASE

@@ -96,13 +96,12 @@ __device__ __forceinline__ void list_elem(const MopSmem &S, double wl, int r, in
     tag = (uint32_t)(S.plex[a] * 9 + r) | ((uint32_t)a << 14);
 }
 
-__global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ paths,
-                                            uint16_t *__restrict__ order, int only_marked) {
-    extern __shared__ unsigned char smem_raw[];
-    MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
-    const int sc = blockIdx.x;
+// One subcarrier: w2 its N weights, out its [K][N] table, order its [2][K]
+// orders or NULL.  With only_marked, a table not marked for redoing is left.
+__device__ void mop_kbest_one(MopSmem &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
+                              uint16_t *__restrict__ order, int only_marked) {
     const int t = threadIdx.x;
-    if (only_marked && paths[(size_t)sc * K * N] != 0xFF) return;
+    if (only_marked && out[0] != 0xFF) return;
     __syncthreads();   // every thread has read the marker before it is overwritten
 
     if (t == 0) {
@@ -114,7 +113,7 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N,
     __syncthreads();
 
     for (int lvl = 0; lvl < N; ++lvl) {
-        const double wl = (double)w2[(size_t)sc * N + lvl];
+        const double wl = (double)w2[lvl];
         // list 0 -> buffer 0
         int len0 = n < K ? n : K;
         for (int a = t; a < len0; a += kT) list_elem(S, wl, 0, a, S.tm[0][a], S.ttag[0][a]);
@@ -218,17 +217,25 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N,
         n = lenT;
         __syncthreads();
     }
-    uint8_t *out = paths + (size_t)sc * K * N;
     for (int idx = t; idx < K * N; idx += kT) {
         const int k = idx / N, i = idx % N;
         out[idx] = (uint8_t)((S.pword[k] >> (4 * i)) & 15ull);
     }
     if (order) {   // survivors carry their lexicographic rank
-        for (int k = t; k < K; k += kT) order[(size_t)sc * 2 * K + S.plex[k]] = (uint16_t)k;
+        for (int k = t; k < K; k += kT) order[S.plex[k]] = (uint16_t)k;
         __syncthreads();
         write_suffix_order([&](int k) { return S.pword[k]; }, K,
-                           reinterpret_cast<unsigned long long *>(S.tm[0]), S.scan, order + (size_t)sc * 2 * K + K);
+                           reinterpret_cast<unsigned long long *>(S.tm[0]), S.scan, order + K);
     }
+}
+
+__global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ paths,
+                                            uint16_t *__restrict__ order, int only_marked) {
+    extern __shared__ unsigned char smem_raw[];
+    MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
+    const int sc = blockIdx.x;
+    mop_kbest_one(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
+                  order ? order + (size_t)sc * 2 * K : nullptr, only_marked);
 }
 
 
@@ -318,17 +325,15 @@ struct ThrSmem {
     int best;
 };
 
+// One subcarrier (pointers as for mop_kbest_one).  Marks the table for the
+// K-best kernel when the threshold enumeration does not fit.
 template <int CAP>
-__global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, int N, int K,
-                                                uint8_t *__restrict__ paths, uint16_t *__restrict__ order) {
+__device__ void mop_thr_one(ThrSmem<CAP> &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
+                            uint16_t *__restrict__ order) {
     constexpr int PER = CAP / kT;   // frontier entries held per thread
-    extern __shared__ unsigned char smem_raw[];
-    ThrSmem<CAP> &S = *reinterpret_cast<ThrSmem<CAP> *>(smem_raw);
-    const int sc = blockIdx.x;
     const int t = threadIdx.x;
-    uint8_t *out = paths + (size_t)sc * K * N;
 
-    if (t < N) S.w[t] = (double)w2[(size_t)sc * N + t];
+    if (t < N) S.w[t] = (double)w2[t];
     __syncthreads();
     bool valid = true;
     double wsum = 0.0;
@@ -339,7 +344,7 @@ __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, in
     if (!valid) {   // failed preprocessing: a deterministic all-zero table
         for (int idx = t; idx < K * N; idx += kT) out[idx] = 0;
         if (order)
-            for (int k = t; k < 2 * K; k += kT) order[(size_t)sc * 2 * K + k] = (uint16_t)(k % K);
+            for (int k = t; k < 2 * K; k += kT) order[k] = (uint16_t)(k % K);
         return;
     }
     // (1) threshold on a coarse grid over the whole range, then a finer one
@@ -472,7 +477,7 @@ __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, in
         out[idx] = (uint8_t)((S.fw[k] >> (4 * (N - 1 - i))) & 15ull);
     }
     if (order) {
-        uint16_t *lexorder = order + (size_t)sc * 2 * K;
+        uint16_t *lexorder = order;
         // the enumeration visited S(T) in lexicographic order: the selected
         // paths, in enumeration order, are the path table in lexicographic order
         for (int k = t; k < K; k += kT) S.rank_of[S.fe[k]] = (uint16_t)k;
@@ -503,7 +508,58 @@ __global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, in
     }
 }
 
+template <int CAP>
+__global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, int N, int K,
+                                                uint8_t *__restrict__ paths, uint16_t *__restrict__ order) {
+    extern __shared__ unsigned char smem_raw[];
+    ThrSmem<CAP> &S = *reinterpret_cast<ThrSmem<CAP> *>(smem_raw);
+    const int sc = blockIdx.x;
+    mop_thr_one<CAP>(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
+                     order ? order + (size_t)sc * 2 * K : nullptr);
+}
+
+// Batched: one workgroup per subcarrier of any group (K <= 512), then the
+// K-best kernel for the tables the threshold pass marked.
+__global__ __launch_bounds__(kT) void k_batch_mop_thr(const BatchGroup *__restrict__ groups,
+                                                      const int32_t *__restrict__ sc_group,
+                                                      const float *__restrict__ w2, uint8_t *__restrict__ paths) {
+    extern __shared__ unsigned char smem_raw[];
+    ThrSmem<1024> &S = *reinterpret_cast<ThrSmem<1024> *>(smem_raw);
+    const int sc = blockIdx.x;
+    const BatchGroup g = groups[sc_group[sc]];
+    const long long j = sc - g.sc0;
+    mop_thr_one<1024>(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr);
+}
+
+__global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__restrict__ groups,
+                                                        const int32_t *__restrict__ sc_group,
+                                                        const float *__restrict__ w2, uint8_t *__restrict__ paths) {
+    extern __shared__ unsigned char smem_raw[];
+    MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
+    const int sc = blockIdx.x;
+    const BatchGroup g = groups[sc_group[sc]];
+    const long long j = sc - g.sc0;
+    mop_kbest_one(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr, 1);
+}
+
 }  // namespace
+
+void prepare_batch_kernels() {
+    (void)hipFuncSetAttribute((const void *)k_batch_mop_thr, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(ThrSmem<1024>));
+    (void)hipFuncSetAttribute((const void *)k_batch_mop_kbest, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)sizeof(MopSmem));
+}
+
+int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, const float *w2,
+                     uint8_t *paths, hipStream_t st) {
+    if (n_sc_total == 0) return VP_OK;
+    hipLaunchKernelGGL(k_batch_mop_thr, dim3(n_sc_total), dim3(kT), sizeof(ThrSmem<1024>), st, groups, sc_group, w2,
+                       paths);
+    hipLaunchKernelGGL(k_batch_mop_kbest, dim3(n_sc_total), dim3(kT), sizeof(MopSmem), st, groups, sc_group, w2,
+                       paths);
+    return launch_status();
+}
 
 int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st) {
     if (n_sc == 0) return VP_OK;

@@ -16,10 +16,11 @@ namespace {
 
 constexpr int kT = 256;
 
-__global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H, int N, int M, float alpha,
-                                                   float2 *__restrict__ Wout, float *__restrict__ w2out,
-                                                   uint8_t *__restrict__ perm_out, float2 *__restrict__ Gout,
-                                                   int32_t *__restrict__ status_out) {
+// One subcarrier: Hs its [N][M] channel; Wsc, w2sc, permsc, Gsc (or NULL),
+// status_sc its outputs.
+__device__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha, float2 *__restrict__ Wsc,
+                               float *__restrict__ w2sc, uint8_t *__restrict__ permsc, float2 *__restrict__ Gsc,
+                               int32_t *__restrict__ status_sc) {
     __shared__ float2 sH[kMaxN * kMaxM];
     __shared__ float2 S[kMaxN][kMaxN + 1];    // Schur complement, user indices
     __shared__ float2 Lc[kMaxN][kMaxN + 1];   // Lc[u][k]: user u's entry of factor column k
@@ -30,10 +31,8 @@ __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H,
     __shared__ float spiv;
     __shared__ int sstatus;
 
-    const int sc = blockIdx.x;
     const int t = threadIdx.x;
     const int NM = N * M;
-    const float2 *Hs = H + (size_t)sc * NM;
 
     int bad = 0;
     for (int idx = t; idx < NM; idx += kT) {
@@ -107,17 +106,16 @@ __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H,
 
     const int st = sstatus;
     const int NP = VP_PACKED(N);
-    float2 *Wsc = Wout + (size_t)sc * NP;
     if (st != VP_STATUS_OK) {
         const float qnan = __int_as_float(0x7fc00000);
         for (int idx = t; idx < NP; idx += kT) Wsc[idx] = make_float2(qnan, qnan);
         if (t < N) {
-            w2out[(size_t)sc * N + t] = __int_as_float(0x7f800000);
-            perm_out[(size_t)sc * N + t] = (uint8_t)t;
+            w2sc[t] = __int_as_float(0x7f800000);
+            permsc[t] = (uint8_t)t;
         }
-        if (Gout)
-            for (int idx = t; idx < NM; idx += kT) Gout[(size_t)sc * NM + idx] = make_float2(qnan, qnan);
-        if (t == 0) status_out[sc] = st;
+        if (Gsc)
+            for (int idx = t; idx < NM; idx += kT) Gsc[idx] = make_float2(qnan, qnan);
+        if (t == 0) *status_sc = st;
         return;
     }
 
@@ -164,10 +162,10 @@ __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H,
     }
     if (t < N) {
         const float d = Wl[t][t].x;
-        w2out[(size_t)sc * N + t] = d * d;
-        perm_out[(size_t)sc * N + t] = (uint8_t)sperm[t];
+        w2sc[t] = d * d;
+        permsc[t] = (uint8_t)sperm[t];
     }
-    if (Gout) {   // G[m][u] = sum_v conj(H_vm) Ainv_vu
+    if (Gsc) {   // G[m][u] = sum_v conj(H_vm) Ainv_vu
         for (int idx = t; idx < NM; idx += kT) {
             const int m = idx / N, u = idx % N;
             float re = 0.f, im = 0.f;
@@ -176,13 +174,46 @@ __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H,
                 re = fmaf(h.x, a.x, fmaf(h.y, a.y, re));
                 im = fmaf(h.x, a.y, fmaf(-h.y, a.x, im));
             }
-            Gout[(size_t)sc * NM + idx] = make_float2(re, im);
+            Gsc[idx] = make_float2(re, im);
         }
     }
-    if (t == 0) status_out[sc] = st;
+    if (t == 0) *status_sc = st;
+}
+
+__global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H, int N, int M, float alpha,
+                                                   float2 *__restrict__ Wout, float *__restrict__ w2out,
+                                                   uint8_t *__restrict__ perm_out, float2 *__restrict__ Gout,
+                                                   int32_t *__restrict__ status_out) {
+    const size_t sc = blockIdx.x;
+    const size_t NM = (size_t)N * M;
+    preprocess_one(H + sc * NM, N, M, alpha, Wout + sc * VP_PACKED(N), w2out + sc * N, perm_out + sc * N,
+                   Gout ? Gout + sc * NM : nullptr, status_out + sc);
+}
+
+// Batched: one workgroup per subcarrier of any group.
+__global__ __launch_bounds__(kT) void k_batch_preprocess(const BatchGroup *__restrict__ groups,
+                                                         const int32_t *__restrict__ sc_group, int M,
+                                                         const float2 *__restrict__ H, float2 *__restrict__ W,
+                                                         float *__restrict__ w2, uint8_t *__restrict__ perm,
+                                                         float2 *__restrict__ G, int32_t *__restrict__ status) {
+    const int sc = blockIdx.x;
+    const BatchGroup g = groups[sc_group[sc]];
+    const long long j = sc - g.sc0;
+    const long long UM = (long long)g.U * M;
+    preprocess_one(H + g.offH + j * UM, g.U, M, g.alpha, W + g.offW + j * VP_PACKED(g.U), w2 + g.offN + j * g.U,
+                   perm + g.offN + j * g.U, G + g.offG + j * UM, status + sc);
 }
 
 }  // namespace
+
+int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, int M,
+                            const float2 *H, float2 *W, float *w2, uint8_t *perm, float2 *G, int32_t *status,
+                            hipStream_t st) {
+    if (n_sc_total == 0) return VP_OK;
+    hipLaunchKernelGGL(k_batch_preprocess, dim3(n_sc_total), dim3(kT), 0, st, groups, sc_group, M, H, W, w2, perm, G,
+                       status);
+    return launch_status();
+}
 
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
                       uint8_t *perm, float2 *G, int32_t *status, hipStream_t st) {

@@ -30,6 +30,8 @@ __all__ = ["VP_EPI_RELU", "VP_PATHS_PER_VECTOR", "N_FEATURES", "TOPK", "mlp_feat
 
 VP_EPI_RELU = 1
 VP_PATHS_PER_VECTOR = 2
+VP_FEAT_ZERO_CENTRES = 0
+VP_FEAT_RANK0_WALK = 1
 N_FEATURES = 64
 TOPK = 64
 HIDDEN = 256
@@ -40,7 +42,7 @@ _F = ctypes.c_float
 _I64 = ctypes.c_int64
 
 SIGNATURES = {
-    "vp_mlp_features": [_P, _P, _P, _F, _I, _I, _I, _P, _P],
+    "vp_mlp_features": [_P, _P, _P, _F, _I, _I, _I, ctypes.c_uint32, _P, _P],
     "vp_path_ranks": [_P, _P, _P, _F, _P, _I, _I, _I, _P, _P],
     "vp_gemm_bf16": [_I, _I, _I, _P, _I64, _I, _P, _I64, _I, _P, ctypes.c_uint32, _P, _I64, _F, _P, _P, _I64, _P],
     "vp_topk64": [_P, _I, _I, _P, _P, _P],
@@ -64,7 +66,7 @@ def _load():
 
 
 def mlp_features(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, n_sym: int,
-                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                 kind: int = VP_FEAT_RANK0_WALK, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """vp_mlp_features -> bf16 [n_vec][64]."""
     lib = _load()
     n_sc, N = perm.shape
@@ -73,7 +75,7 @@ def mlp_features(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: floa
         out = torch.empty((n_vec, N_FEATURES), dtype=torch.bfloat16, device=W.device)
     check(lib.vp_mlp_features(_req(W, "W", torch.complex64, (n_sc, packed_size(N))),
                               _req(perm, "perm", torch.uint8, (n_sc, N)),
-                              _req(s, "s", torch.complex64, (N, n_vec)), float(tau), n_sc, int(n_sym), N,
+                              _req(s, "s", torch.complex64, (N, n_vec)), float(tau), n_sc, int(n_sym), N, int(kind),
                               _req(out, "feat", torch.bfloat16, (n_vec, N_FEATURES)), _stream()), "vp_mlp_features")
     return out
 
@@ -212,6 +214,10 @@ class MLPFunction(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, x, W1, b1, W2, b2, W3, b3):
+        # weights may be float32 masters (rounded to bf16 here) or bf16 already;
+        # the gradients returned are float32 either way
+        W1, W2, W3 = (w.to(torch.bfloat16).contiguous() for w in (W1, W2, W3))
+        b1, b2, b3 = (b.float().contiguous() for b in (b1, b2, b3))
         h1 = gemm_bf16(x, W1, trans_b=True, bias=b1, relu=True, out_f32=False, out_bf16=True)
         h2 = gemm_bf16(h1, W2, trans_b=True, bias=b2, relu=True, out_f32=False, out_bf16=True)
         z = gemm_bf16(h2, W3, trans_b=True, bias=b3)
@@ -267,7 +273,8 @@ def pack_ranks(ranks: torch.Tensor) -> torch.Tensor:
 class Proposer:
     """A trained network plus its vocabulary: proposes per-vector path tables."""
 
-    def __init__(self, params: MLPParams, vocab: torch.Tensor):
+    def __init__(self, params: MLPParams, vocab: torch.Tensor, feature_kind: int = VP_FEAT_RANK0_WALK):
+        self.kind = int(feature_kind)
         self.p = MLPParams(*[t.to(torch.bfloat16).contiguous() if t.dim() == 2 else t.float().contiguous()
                              for t in params])
         self.vocab = vocab.contiguous()   # uint8 [V][N]
@@ -277,7 +284,7 @@ class Proposer:
         """Features -> logits -> top-64 -> table [n_vec][64 + K_fixed][N].
         Returns (table, mass)."""
         n_sc = perm.shape[0]
-        x = mlp_features(W, perm, s, tau, n_sym)
+        x = mlp_features(W, perm, s, tau, n_sym, kind=self.kind)
         z = MLPFunction.forward(_NoCtx(), x, *self.p)
         top, mass = topk64(z)
         table = learned_paths(self.vocab, top, fixed_paths, K_fixed if fixed_paths is not None else 0, n_sc, n_sym)

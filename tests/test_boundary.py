@@ -108,6 +108,26 @@ def _host_demap():
     return run
 
 
+def test_demap_exact_ties_follow_canonical_order():
+    """Centres on a grid of eighths give exact distance ties (also at
+    half-integers, where two offsets of one axis are equally far): every rank
+    of every tier must follow the (distance, j) order exactly."""
+    run = _host_demap()
+    g = np.arange(-20, 21) / 8.0
+    gx, gy = np.meshgrid(g, g)
+    cx, cy = gx.ravel().astype(np.float32), gy.ravel().astype(np.float32)
+    c = cx.astype(np.float64) + 1j * cy.astype(np.float64)
+    order = np.argsort(O.sqabs(c[:, None] - O.BOX[None, :]), axis=1, kind="stable")
+    for r in range(9):
+        ref = O.BOX[order[:, r]]
+        for tier in (0, 1, 2):
+            if (tier == 0 and r > 0) or (tier == 1 and r > 1):
+                continue
+            a, b = run(cx, cy, np.full(len(cx), r), tier)
+            bad = np.nonzero((a != ref.real) | (b != ref.imag))[0]
+            assert bad.size == 0, (r, tier, [(cx[i], cy[i]) for i in bad[:4]])
+
+
 def test_demap_matches_oracle_order():
     """The GPU's DEMAP (host build) picks the same box point as the oracle's
     (distance, j) order for every rank, except where two distances are within
@@ -121,7 +141,7 @@ def test_demap_matches_oracle_order():
     cx = np.concatenate([cx, gx.ravel(), cx[:5000]])
     cy = np.concatenate([cy, gy.ravel(), -cx[:5000]])
     c = cx.astype(np.float64) + 1j * cy.astype(np.float64)
-    d = np.abs(c[:, None] - O.BOX[None, :]) ** 2
+    d = O.sqabs(c[:, None] - O.BOX[None, :])
     order = np.argsort(d, axis=1, kind="stable")
     ds = np.take_along_axis(d, order, 1)
     for r in range(9):
@@ -163,10 +183,11 @@ def test_learned_argument_validation():
     from paper_2602_12098_amd._lib import VP_EINVAL, VP_EUNSUPPORTED, VP_OK
     lib = learn._load()
     P = ctypes.c_void_p(16)   # never dereferenced: validation fails or returns before any launch
-    assert lib.vp_mlp_features(None, None, None, 8.0, 1, 14, 4, None, None) == VP_EINVAL
-    assert lib.vp_mlp_features(P, P, P, 0.0, 1, 14, 4, P, None) == VP_EINVAL
-    assert lib.vp_mlp_features(P, P, P, 8.0, 1, 14, 17, P, None) == VP_EUNSUPPORTED
-    assert lib.vp_mlp_features(None, None, None, 8.0, 0, 14, 4, None, None) == VP_OK
+    assert lib.vp_mlp_features(None, None, None, 8.0, 1, 14, 4, 1, None, None) == VP_EINVAL
+    assert lib.vp_mlp_features(P, P, P, 0.0, 1, 14, 4, 1, P, None) == VP_EINVAL
+    assert lib.vp_mlp_features(P, P, P, 8.0, 1, 14, 4, 2, P, None) == VP_EINVAL   # unknown kind
+    assert lib.vp_mlp_features(P, P, P, 8.0, 1, 14, 17, 0, P, None) == VP_EUNSUPPORTED
+    assert lib.vp_mlp_features(None, None, None, 8.0, 0, 14, 4, 0, None, None) == VP_OK
     assert lib.vp_path_ranks(P, P, P, 8.0, None, 1, 14, 4, P, None) == VP_EINVAL
     assert lib.vp_path_ranks(P, P, P, 8.0, P, 1, 0, 4, P, None) == VP_EINVAL
     # gemm: bad sizes, leading dimensions, flags, no output

@@ -95,6 +95,35 @@ def test_features_scale_invariant():
     np.testing.assert_allclose(f1, f2, rtol=1e-12, atol=1e-14)
 
 
+def test_features_walk_reproduce_rank0_path():
+    # sum_i tau^2 W_ii^2 |c_i - b_i|^2 along the walk is the cost of the rank-0
+    # path; the level-i gap is the extra PED of taking rank 1 at level i alone
+    p, s, tau = _subcarrier(n=6, nsym=7, seed=21, Q=64)
+    f, gap = L.features_walk(p.W, p.perm, s, tau)
+    n = 6
+    off = f[:, 16:16 + n] + 1j * f[:, 32:32 + n]
+    cost0 = tau ** 2 * np.sum(p.w2[None, :] * np.abs(off) ** 2, axis=1)
+    zero = np.zeros((1, n), int)
+    res = O.search_paths(p.W, p.perm, s, tau, zero, include_zero=False)
+    np.testing.assert_allclose(cost0, res.path_cost[:, 0], rtol=1e-11)
+    w2m = np.mean(p.w2)
+    for i in range(n):
+        path = np.zeros((1, n), int)
+        path[0, i] = 1
+        r1 = O.search_paths(p.W, p.perm, s, tau, path, include_zero=False)
+        # PED of levels <= i: prefix of the rank-0 path, then rank 1 at level i
+        pre = tau ** 2 * np.sum(p.w2[None, :i] * np.abs(off[:, :i]) ** 2, axis=1)
+        ped_i = tau ** 2 * p.w2[i] * np.abs(off[:, i]) ** 2
+        l1 = r1.path_l[:, 0, i]
+        c_i = -((p.W @ s[p.perm, :]).T[:, i] + tau * np.sum(p.W[i, :i][None, :] * res.path_l[:, 0, :i], axis=1)) \
+            / (tau * p.W[i, i])
+        extra = tau ** 2 * p.w2[i] * (np.abs(c_i - l1) ** 2) - ped_i
+        np.testing.assert_allclose(f[:, 48 + i] * w2m * tau ** 2, extra, rtol=1e-9, atol=1e-9)
+        np.testing.assert_allclose(pre + ped_i + extra, pre + tau ** 2 * p.w2[i] * np.abs(c_i - l1) ** 2,
+                                   rtol=1e-12)
+    assert np.all(gap >= 0)
+
+
 def test_path_ranks_inverts_rank_walk():
     p, s, tau = _subcarrier(n=8, nsym=12, seed=8)
     rng = np.random.default_rng(2)

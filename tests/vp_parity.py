@@ -54,7 +54,7 @@ def relaxed_walks(W, st, tau, ranks, eps=TIE_EPS, limit=64):
             out.append((l.copy(), cost))
             return
         c = -resid[i] / (tau * W[i, i])
-        d = np.abs(c - O.BOX) ** 2
+        d = O.sqabs(c - O.BOX)
         order = np.argsort(d, kind="stable")
         dr = d[order[ranks[i]]]
         for p in range(9):

@@ -152,11 +152,14 @@ class BatchedWorkload:
     seed: int
 
 
-def cfg4(n_rbg: int = 2048, seed: int = 4) -> BatchedWorkload:
-    """2048 RBGs x 12 subcarriers x 14 symbols, U ~ Unif{4..16}, Q ~ Unif{4,16,64,256}, M=16."""
+def cfg4(n_rbg: int = 2048, seed: int = 4, users=None) -> BatchedWorkload:
+    """2048 RBGs x 12 subcarriers x 14 symbols, U ~ Unif{4..16}, Q ~ Unif{4,16,64,256}, M=16.
+    `users` (optional) replaces the first len(users) user counts."""
     rng = np.random.default_rng(seed)
     M, spr, n_sym = 16, 12, 14
     U = rng.integers(4, 17, size=n_rbg).astype(np.int32)
+    if users is not None:
+        U[:len(users)] = np.asarray(users, dtype=np.int32)
     Q = np.array([4, 16, 64, 256], dtype=np.int32)[rng.integers(0, 4, size=n_rbg)]
     alpha = (U / 100.0).astype(np.float32)
     H = [draw_rayleigh(rng, spr, int(u), M) for u in U]
