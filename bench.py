@@ -7,11 +7,16 @@ per-subcarrier preprocessing, MoP path selection, the per-vector search over
 the 512 paths with its argmin, and the precoding x = G (s + tau l).  Inputs
 are resident in HBM before the timed region; outputs are preallocated.
 
-Prints one JSON line (rank 0).  Extra fields: per-stage times, the roofline of
-the dominant kernel (the path search, VALU-bound), and the FP64 CPU oracle
-timed on a bounded sample of the same workload on the host cores.
+Prints one JSON line (rank 0).  Extra fields: per-stage times, the power gap
+to exact VP (GPU sphere encoder, outside the timed region), the roofline of
+the dominant kernel (the path search, VALU-bound) with its HBM traffic from
+committed counter profiles, the FP64 CPU oracle timed on a bounded sample of
+the same workload on the host cores, and two further measured forms of the
+path: the batched uneven RBG slot (one graph, autotuned, against per-size
+launches) and the learned per-vector path proposal.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -34,6 +39,146 @@ FLOP_PER_CM = 6   # one complex multiplication: 4 real multiplies + 2 adds
 def search_cm_per_vector(n_t, K):
     """Path-search part of the paper's per-vector count (Sec. III-B): K N_t (1 + (N_t+1)/2)."""
     return K * n_t * (n_t + 3) // 2
+
+
+SEARCH_SOURCES = ["paper_2602_12098_amd/csrc/vp_search.hip", "paper_2602_12098_amd/csrc/vp_walk.hpp",
+                  "paper_2602_12098_amd/csrc/vp_device.hpp", "paper_2602_12098_amd/csrc/demap_lut.h"]
+TRAFFIC_FILE = "profiles/k_search_trie_16x16_256qam_K512.traffic.json"
+
+
+def search_traffic():
+    """HBM bytes per launch of the search kernel from the committed counter
+    profile, or None when it is missing or the kernel sources changed since."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None, "no traffic profile"
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for f in rec.get("source_files", SEARCH_SOURCES):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest() != rec.get("source_sha256"):
+        return None, "kernel changed since the counters were taken"
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], TRAFFIC_FILE
+
+
+def gap_to_exact(vp, prep, s, tau, n_sym, cost):
+    """Power gap (dB) of the selected perturbations to exact VP over the box:
+    the sphere encoder seeded with each vector's own cost as radius."""
+    import torch
+    se = vp.sphere_encode(prep.W, prep.perm, s, tau, n_sym, radius=cost * (1 + 1e-6))
+    exact = torch.where(torch.isfinite(se.cost), se.cost, cost).double()
+    return 10 * math.log10(float(cost.double().sum()) / float(exact.sum())), exact
+
+
+def bench_batched(vp, steps, warmup):
+    """The 2048-RBG uneven slot (U ~ 4..16, mixed QAM, M = 16) with K(U) from the
+    calibration table: one captured graph (default and autotuned tile shapes)
+    against per-size launches of the per-call API, and its power gap."""
+    import torch
+    import vpgen
+    from paper_2602_12098_amd import batch as B
+    kcal = json.load(open(os.path.join(ROOT, "paper_2602_12098_amd", "kcal_rbg_m16.json")))["K_by_U"]
+    wl = vpgen.cfg4()
+    groups = [B.GroupSpec(int(u), wl.sc_per_rbg, int(kcal[str(int(u))]), float(vpgen.qam_tau(int(q))), float(a))
+              for u, q, a in zip(wl.U, wl.Q, wl.alpha)]
+    b = B.Batch(groups, wl.M, wl.n_sym, P_T=1.0)
+    b.set_inputs(wl.H, wl.s)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    ms_default = timed(b.run)
+    info = b.tune(reps=3)
+    ms_tuned = timed(b.run)
+    # per-size launches: RBGs grouped by (U, QAM order), each group one call per stage
+    keys = sorted(set(zip(wl.U.tolist(), wl.Q.tolist())))
+    per = []
+    for (u, q) in keys:
+        idx = [i for i in range(wl.n_rbg) if wl.U[i] == u and wl.Q[i] == q]
+        H = torch.from_numpy(np.concatenate([wl.H[i] for i in idx])).to("cuda:0")
+        sg = torch.from_numpy(np.concatenate([wl.s[i] for i in idx], axis=1)).to("cuda:0")
+        per.append((H, sg, float(vpgen.qam_tau(q)), float(u) / 100.0, int(kcal[str(u)])))
+
+    def per_size():
+        outs = []
+        for H, sg, tau, alpha, K in per:
+            prep = vp.preprocess(H, alpha)
+            paths = vp.paths_mop(prep.w2, K)
+            o = vp.search(prep.W, prep.perm, sg, tau, paths, wl.n_sym)
+            vp.precode(prep.G, sg, o.l, tau, o.cost, wl.n_sym, P_T=1.0)
+            outs.append((prep, o))
+        return outs
+
+    ms_per_size = timed(per_size)
+    num = den = 0.0
+    for (H, sg, tau, alpha, K), (prep, o) in zip(per, per_size()):
+        g, exact = gap_to_exact(vp, prep, sg, tau, wl.n_sym, o.cost)
+        num += float(o.cost.double().sum())
+        den += float(exact.sum())
+    n_vec = b.n_vec
+    res = {"workload": f"{wl.n_rbg} RBGs x {wl.sc_per_rbg} sc x {wl.n_sym} sym, U 4..16, QAM 4..256, M {wl.M}",
+           "n_vec": n_vec, "K_by_U": kcal, "value": n_vec / (ms_tuned * 1e-3), "unit": "vectors/s",
+           "ms_graph_default": ms_default, "ms_graph_tuned": ms_tuned, "ms_per_size_launches": ms_per_size,
+           "per_size_launch_groups": len(per), "speedup_vs_per_size": ms_per_size / ms_tuned,
+           "gap_db": 10 * math.log10(num / den), "tuning": info}
+    b.close()
+    return res
+
+
+def bench_learned(vp, steps, warmup, wl, H, s, K_mop=64):
+    """The learned per-vector proposal on the same slot: features, network and
+    top-64 (bf16 MFMA), table of 64 proposed + first K_mop MoP paths, search,
+    precode; timed per stage, with its power gap."""
+    import torch
+    from paper_2602_12098_amd import learn
+    path = os.path.join(ROOT, "paper_2602_12098_amd", "weights", "proposer_16x16_256qam_res64.safetensors")
+    if not os.path.exists(path):
+        return None
+    prop = learn.load_proposer(path)
+    n_sym = wl.n_sym
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
+    out = {}
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        prep = vp.preprocess(H, wl.alpha)
+        if ev: ev[1].record()
+        paths = vp.paths_mop(prep.w2, K_mop)
+        if ev: ev[2].record()
+        table, mass = prop.propose(prep.W, prep.perm, s, wl.tau, n_sym, fixed_paths=paths, K_fixed=K_mop)
+        if ev: ev[3].record()
+        o = vp.search(prep.W, prep.perm, s, wl.tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
+        if ev: ev[4].record()
+        vp.precode(prep.G, s, o.l, wl.tau, o.cost, n_sym, P_T=1.0)
+        if ev: ev[5].record()
+        out["prep"], out["o"] = prep, o
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    names = ["preprocess", "paths_mop", "propose", "search", "precode"]
+    stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+              for i, n in enumerate(names)}
+    ms = float(np.mean([evs[k][0].elapsed_time(evs[k][5]) for k in range(steps)]))
+    g, _ = gap_to_exact(vp, out["prep"], s, wl.tau, n_sym, out["o"].cost)
+    return {"paths_per_vector": 64 + K_mop, "value": wl.n_vec / (ms * 1e-3), "unit": "vectors/s",
+            "ms_per_step": ms, "stages_ms": stages, "gap_db": g,
+            "model": "64 -> 256 -> 256 -> 4096 (ReLU), bf16 MFMA; vocabulary of 4096 exact position vectors; "
+                     "trained on vectors the first 64 MoP paths miss",
+            "train_meta": getattr(prop, "meta", {})}
 
 
 def _cpu_worker(args):
@@ -84,6 +229,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--K", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip the gap, batched and learned measurements")
+    ap.add_argument("--only", choices=("batched", "learned"), default=None,
+                    help="run one further form alone (for profiling) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by "
@@ -95,6 +243,9 @@ def main():
     import vpgen
 
     dev = "cuda:0"
+    if args.only == "batched":
+        print(json.dumps({"batched": bench_batched(vp, args.steps, args.warmup)}), flush=True)
+        return
     wl = vpgen.cfg3(args.K)
     N, M, n_sc, n_sym, K = wl.N, wl.M, wl.n_sc, wl.n_sym, args.K
     n_vec = n_sc * n_sym
@@ -111,6 +262,9 @@ def main():
                         torch.empty((n_vec,), dtype=torch.float32, device=dev),
                         torch.empty((n_vec,), dtype=torch.int32, device=dev))
     x = torch.empty((n_vec, M), dtype=torch.complex64, device=dev)
+    if args.only == "learned":
+        print(json.dumps({"learned": bench_learned(vp, args.steps, args.warmup, wl, H, s)}), flush=True)
+        return
 
     def step(ev=None):
         if ev: ev[0].record()
@@ -144,8 +298,9 @@ def main():
 
     flops = search_cm_per_vector(M, K) * FLOP_PER_CM * n_vec
     achieved = flops / (stage["search"] * 1e-3) / 1e12
+    traffic, traffic_src = search_traffic()
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+            "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic, "traffic_source": traffic_src,
             "kernel": "vp_search (k_search_trie + k_search_finalize)",
             "work": f"{search_cm_per_vector(M, K)} complex mult/vector x {FLOP_PER_CM} flop x {n_vec} vectors"}
 
@@ -158,6 +313,13 @@ def main():
         "event_ms_per_step": ms_step, "stages_ms": stage, "roofline": roof,
         "gap_db": None,
     }
+    if not args.no_extras:
+        print("gap to exact VP ...", file=sys.stderr, flush=True)
+        line["gap_db"], _ = gap_to_exact(vp, prep, s, wl.tau, n_sym, sout.cost)
+        print("batched slot ...", file=sys.stderr, flush=True)
+        line["batched"] = bench_batched(vp, args.steps, args.warmup)
+        print("learned proposal ...", file=sys.stderr, flush=True)
+        line["learned"] = bench_learned(vp, args.steps, args.warmup, wl, H, s)
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(K)

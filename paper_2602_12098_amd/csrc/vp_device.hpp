@@ -9,6 +9,7 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <string.h>
 
 #if defined(__HIPCC__)
 #include <hip/hip_runtime.h>
@@ -67,26 +68,46 @@ VP_HD void vp_demap1(float cx, float cy, int rank, float &a, float &b) {
 
 // Any rank 0..8: eight cell comparisons form the signature of the box order,
 // a 256 x 9 table gives the cell (p, q) of the requested rank.
+// Bit pattern of a non-negative float: increasing in the value, so that
+// a < b  <=>  bits(a) < bits(b), and "a <= b" is bits(a) < bits(b) + 1.
+VP_HD int32_t vp_fbits(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __float_as_int(x);
+#else
+    int32_t i;
+    memcpy(&i, &x, sizeof i);
+    return i;
+#endif
+}
+
 VP_HD int vp_demap_signature(const vp_axis &X, const vp_axis &Y) {
     // each bit: the first cell comes first in the (distance, j) order; the two
-    // cells always differ in x offset, which decides equal distances
+    // cells always differ in x offset, which decides equal distances -- the
+    // first cell then wins when its x offset is the smaller one, i.e. the
+    // comparison is "<=" instead of "<".  All gaps are >= +0, so the
+    // comparisons run on their bit patterns and the tie rule is a +1.
     const float A = X.A, B = X.B, C = Y.A, D = Y.B;
-    const float AC = A + C, BC = B + C, AD = A + D;
-    const bool x01 = X.o0 < X.o1, x02 = X.o0 < X.o2, x12 = X.o1 < X.o2;
-    int sig = (int)((C < A) | ((C == A) & x01));               // (0,1) before (1,0)
-    sig |= (int)((C < B) | ((C == B) & x02)) << 1;             // (0,1) before (2,0)
-    sig |= (int)((D < A) | ((D == A) & x01)) << 2;             // (0,2) before (1,0)
-    sig |= (int)((D < AC) | ((D == AC) & x01)) << 3;           // (0,2) before (1,1)
-    sig |= (int)((D < B) | ((D == B) & x02)) << 4;             // (0,2) before (2,0)
-    sig |= (int)((D < BC) | ((D == BC) & x02)) << 5;           // (0,2) before (2,1)
-    sig |= (int)((AC < B) | ((AC == B) & x12)) << 6;           // (1,1) before (2,0)
-    sig |= (int)((AD < B) | ((AD == B) & x12)) << 7;           // (1,2) before (2,0)
+    const int32_t a = vp_fbits(A), b = vp_fbits(B), c = vp_fbits(C), d = vp_fbits(D);
+    const int32_t ac = vp_fbits(A + C), bc = vp_fbits(B + C), ad = vp_fbits(A + D);
+    const int32_t x01 = X.o0 < X.o1, x02 = X.o0 < X.o2, x12 = X.o1 < X.o2;
+    const int32_t a1 = a + x01, b2 = b + x02, b12 = b + x12;
+    int sig = (int)(c < a1);                      // (0,1) before (1,0)
+    sig |= (int)(c < b2) << 1;                    // (0,1) before (2,0)
+    sig |= (int)(d < a1) << 2;                    // (0,2) before (1,0)
+    sig |= (int)(d < ac + x01) << 3;              // (0,2) before (1,1)
+    sig |= (int)(d < b2) << 4;                    // (0,2) before (2,0)
+    sig |= (int)(d < bc + x02) << 5;              // (0,2) before (2,1)
+    sig |= (int)(ac < b12) << 6;                  // (1,1) before (2,0)
+    sig |= (int)(ad < b12) << 7;                  // (1,2) before (2,0)
     return sig;
 }
 
-VP_HD float vp_pick_offset(const vp_axis &X, int p) {
-    float v = (p == 1) ? X.o1 : X.o0;
-    v = (p == 2) ? X.o2 : v;
+// Offset of per-axis rank p.  The three offsets are taken by value: a select
+// over fields of one struct lets the compiler turn the choice into an
+// indexed load from a stack copy (private memory).
+VP_HD float vp_pick_offset(float o0, float o1, float o2, int p) {
+    float v = (p == 1) ? o1 : o0;
+    v = (p == 2) ? o2 : v;
     return v;
 }
 
@@ -95,8 +116,8 @@ VP_HD void vp_demapN(float cx, float cy, int rank, const uint8_t *lut, float &a,
     const vp_axis Y = vp_axis_order(cy);
     const int sig = vp_demap_signature(X, Y);
     const int cell = lut[sig * 9 + rank];
-    a = vp_pick_offset(X, cell & 3);
-    b = vp_pick_offset(Y, cell >> 2);
+    a = vp_pick_offset(X.o0, X.o1, X.o2, cell & 3);
+    b = vp_pick_offset(Y.o0, Y.o1, Y.o2, cell >> 2);
 }
 
 // Box code of a perturbation symbol: j = 3 (a + 1) + (b + 1).

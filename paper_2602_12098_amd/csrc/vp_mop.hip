@@ -98,7 +98,7 @@ __device__ __forceinline__ void list_elem(const MopSmem &S, double wl, int r, in
 
 // One subcarrier: w2 its N weights, out its [K][N] table, order its [2][K]
 // orders or NULL.  With only_marked, a table not marked for redoing is left.
-__device__ void mop_kbest_one(MopSmem &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
+__device__ __forceinline__ void mop_kbest_one(MopSmem &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
                               uint16_t *__restrict__ order, int only_marked) {
     const int t = threadIdx.x;
     if (only_marked && out[0] != 0xFF) return;
@@ -328,7 +328,7 @@ struct ThrSmem {
 // One subcarrier (pointers as for mop_kbest_one).  Marks the table for the
 // K-best kernel when the threshold enumeration does not fit.
 template <int CAP>
-__device__ void mop_thr_one(ThrSmem<CAP> &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
+__device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
                             uint16_t *__restrict__ order) {
     constexpr int PER = CAP / kT;   // frontier entries held per thread
     const int t = threadIdx.x;

@@ -18,7 +18,7 @@ constexpr int kT = 256;
 
 // One subcarrier: Hs its [N][M] channel; Wsc, w2sc, permsc, Gsc (or NULL),
 // status_sc its outputs.
-__device__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha, float2 *__restrict__ Wsc,
+__device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha, float2 *__restrict__ Wsc,
                                float *__restrict__ w2sc, uint8_t *__restrict__ permsc, float2 *__restrict__ Gsc,
                                int32_t *__restrict__ status_sc) {
     __shared__ float2 sH[kMaxN * kMaxM];

@@ -37,7 +37,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
     __shared__ unsigned long long s_red[kT / 64];
 
     constexpr int NP = VP_PACKED(N);
-    const size_t v = blockIdx.x;            // one vector per workgroup
+    const size_t v = xcd_contiguous(blockIdx.x, gridDim.x);   // one vector per workgroup
     const int sc = (int)(v / n_sym);
     const int t = threadIdx.x;
     const size_t n_vec = (size_t)gridDim.x;
@@ -126,7 +126,7 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
     __shared__ unsigned long long s_red[kTT / 64];
 
     constexpr int NP = VP_PACKED(N);
-    const size_t v = blockIdx.x;
+    const size_t v = xcd_contiguous(blockIdx.x, gridDim.x);
     const int sc = (int)(v / n_sym);
     const int t = threadIdx.x;
     const size_t n_vec = (size_t)gridDim.x;
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     constexpr int NP = VP_PACKED(N);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = threadIdx.x & 63;
-    const size_t v0 = (size_t)blockIdx.x * kWV + wv;
+    const size_t v0 = (size_t)xcd_contiguous(blockIdx.x, gridDim.x) * kWV + wv;
     const bool live = v0 < n_vec;   // the last workgroup may hold fewer vectors
     const size_t v = live ? v0 : n_vec - 1;
     const int sc = (int)(v / n_sym);

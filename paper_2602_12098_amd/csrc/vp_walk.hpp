@@ -135,4 +135,16 @@ __device__ __forceinline__ unsigned long long load_word(const uint8_t *__restric
 }
 
 
+// Workgroups are dispatched to the 8 XCDs of the chip in turn (workgroup b to
+// XCD b mod 8), and every XCD has its own L2.  This bijection of [0, n) gives
+// each XCD one contiguous range of indices, so that consecutive vectors --
+// the symbols of one subcarrier, which read the same W, path table and path
+// orders -- meet in one L2 instead of being fetched by up to eight.
+__device__ __forceinline__ uint32_t xcd_contiguous(uint32_t b, uint32_t n) {
+    constexpr uint32_t kXcd = 8;
+    const uint32_t per = n / kXcd, rem = n % kXcd;
+    const uint32_t x = b % kXcd, i = b / kXcd;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
 }  // namespace vp

@@ -26,7 +26,7 @@ from .vp import _req, _stream, packed_size
 
 __all__ = ["VP_EPI_RELU", "VP_PATHS_PER_VECTOR", "N_FEATURES", "TOPK", "mlp_features", "path_ranks", "gemm_bf16",
            "topk64", "softmax_xent", "colsum_bf16", "learned_paths", "MLPParams", "MLPFunction", "mlp_logits",
-           "pack_ranks", "Proposer"]
+           "pack_ranks", "Proposer", "load_proposer"]
 
 VP_EPI_RELU = 1
 VP_PATHS_PER_VECTOR = 2
@@ -289,6 +289,20 @@ class Proposer:
         top, mass = topk64(z)
         table = learned_paths(self.vocab, top, fixed_paths, K_fixed if fixed_paths is not None else 0, n_sc, n_sym)
         return table, mass
+
+
+def load_proposer(path: str, device: str = "cuda:0") -> Proposer:
+    """A Proposer from a safetensors file written by the training script
+    (weights W1..b3, vocabulary; metadata: feature kind).  Safe loader only."""
+    from safetensors import safe_open
+    from safetensors.torch import load_file
+    t = load_file(path, device=device)
+    with safe_open(path, framework="pt") as fh:
+        meta = fh.metadata() or {}
+    p = MLPParams(t["W1"], t["b1"], t["W2"], t["b2"], t["W3"], t["b3"])
+    prop = Proposer(p, t["vocab"], feature_kind=int(meta.get("feature_kind", VP_FEAT_RANK0_WALK)))
+    prop.meta = meta
+    return prop
 
 
 class _NoCtx:

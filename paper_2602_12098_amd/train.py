@@ -182,13 +182,7 @@ def save(path: str, params: learn.MLPParams, vocab: torch.Tensor, meta: dict):
 
 
 def load(path: str, device: str = DEV) -> learn.Proposer:
-    from safetensors import safe_open
-    from safetensors.torch import load_file
-    t = load_file(path, device=device)
-    with safe_open(path, framework="pt") as fh:
-        meta = fh.metadata() or {}
-    p = learn.MLPParams(t["W1"], t["b1"], t["W2"], t["b2"], t["W3"], t["b3"])
-    return learn.Proposer(p, t["vocab"], feature_kind=int(meta.get("feature_kind", learn.VP_FEAT_RANK0_WALK)))
+    return learn.load_proposer(path, device)
 
 
 # ---------------------------------------------------------------------------

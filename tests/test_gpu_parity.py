@@ -395,3 +395,29 @@ def test_prefix_sharing_is_bit_identical(vp, N, K):
     a = run_pipeline(vp, wl, shared_prefix=True)
     b = run_pipeline(vp, wl, shared_prefix=False)
     assert torch.equal(a[2].cost, b[2].cost) and torch.equal(a[2].kidx, b[2].kidx) and torch.equal(a[2].l, b[2].l)
+
+
+@pytest.mark.parametrize("N,K,hi", [(16, 512, 9), (16, 300, 9), (8, 512, 3), (5, 200, 9), (16, 512, 2)])
+def test_trie_search_any_table_is_bit_identical(vp, N, K, hi):
+    # arbitrary per-subcarrier tables (random ranks, duplicates allowed) with
+    # their two orders: the prefix-sharing search must equal the plain
+    # per-path search bit for bit, also with many distinct prefixes (done in
+    # chunks) and with repeated paths
+    rng = np.random.default_rng(N * 1000 + K + hi)
+    n_sc, n_sym = 6, 5
+    H = vpgen.draw_rayleigh(rng, n_sc, N, N)
+    s = vpgen.draw_symbols(rng, N, n_sc * n_sym, 64)
+    tau = vpgen.qam_tau(64)
+    prep = vp.preprocess(_to_dev(H), 0.1)
+    paths = rng.integers(0, hi, size=(n_sc, K, N)).astype(np.uint8)
+    order = np.zeros((n_sc, 2, K), np.int16)
+    for sc in range(n_sc):
+        lex = np.lexsort(tuple(paths[sc][:, i] for i in reversed(range(N))))   # level 0 most significant
+        order[sc, 0] = lex
+        order[sc, 1] = np.lexsort(tuple(paths[sc][:, i] for i in range(N)))    # deepest level most significant
+    sd = _to_dev(s)
+    pd = _to_dev(paths)
+    a = vp.search(prep.W, prep.perm, sd, tau, pd, n_sym, order=_to_dev(order))
+    b = vp.search(prep.W, prep.perm, sd, tau, pd, n_sym)
+    torch.cuda.synchronize()
+    assert torch.equal(a.cost, b.cost) and torch.equal(a.kidx, b.kidx) and torch.equal(a.l, b.l)
