@@ -86,6 +86,13 @@ __device__ void write_suffix_order(WordFn word, int K, unsigned long long *key, 
     __syncthreads();
 }
 
+// The N rank nibbles of a path word in reverse level order (nibble i <-> N-1-i):
+// swap the nibbles of every byte, reverse the bytes, drop the unused levels.
+__device__ __forceinline__ unsigned long long nibble_reverse(unsigned long long x, int N) {
+    x = ((x & 0x0F0F0F0F0F0F0F0Full) << 4) | ((x >> 4) & 0x0F0F0F0F0F0F0F0Full);
+    return __builtin_bswap64(x) >> (4 * (16 - N));
+}
+
 __device__ __forceinline__ bool key_less(double ma, uint32_t ta, double mb, uint32_t tb) {
     return ma < mb || (ma == mb && (ta & 0x3fffu) < (tb & 0x3fffu));
 }
@@ -272,38 +279,53 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratc
 // Smallest grid index b with count(b) >= K of the rounded-up metric, on a
 // grid of step h with NB points (-1 if none); dp is [2][NB] scratch.  The
 // rounding up makes the count a lower bound of the true count at b * h.
+// Counting recursion on a grid of NB = 2 kT bins of width h: after levels
+// l..N-1, count[b] = number of rank suffixes whose metric, with every term
+// w_i r_i rounded up to whole bins, is at most b bins (an under-count of the
+// true |S(b h)|).  Returns the smallest b with count >= K, or -1.  Each
+// thread owns two adjacent bins; the two buffers (cur, next) carry NB zero
+// bins on their left so that shifted reads need no bounds test; counts
+// saturate at 2^20 (>= K, all that is compared).  buf: 2 x 2 NB uint32 of
+// LDS; dtab: kMaxN x 9 ints of LDS.
 template <int NB>
-__device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t (*dp)[NB], int *sbest) {
+__device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *buf, int *sbest, int (*dtab)[9]) {
+    static_assert(NB == 2 * kT, "two bins per thread");
+    constexpr uint32_t kSat = 1u << 20;
     const int t = threadIdx.x;
     const double inv_h = (1.0 + 0x1p-40) / h;   // the tiny excess keeps every term rounded up
-    for (int b = t; b < NB; b += kT) dp[0][b] = 1u;
+    uint32_t *b0 = buf, *b1 = buf + 2 * NB;
+    b0[2 * t] = 0u;
+    b0[2 * t + 1] = 0u;
+    b1[2 * t] = 0u;
+    b1[2 * t + 1] = 0u;
+    b0[NB + 2 * t] = 1u;
+    b0[NB + 2 * t + 1] = 1u;
     if (t == 0) *sbest = NB;
+    // the shifts ceil(w_l r / h) depend only on the level: one thread each
+    for (int q = t; q < N * 9; q += kT) {
+        const int l = q / 9, r = q % 9;
+        const double x = ceil((w[l] * inv_h) * (double)r);
+        dtab[l][r] = x < (double)NB ? (int)x : NB;
+    }
     __syncthreads();
-    int cur = 0;
+    uint32_t *cur = b0, *nxt = b1;
     for (int l = N - 1; l >= 0; --l) {
-        int d[9];
-        const double wl = w[l] * inv_h;
+        const uint32_t *src = cur + NB + 2 * t;
+        uint32_t a0 = 0u, a1 = 0u;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const double x = ceil(wl * (double)r);
-            d[r] = x < (double)NB ? (int)x : NB;
+            const int d = dtab[l][r];
+            a0 += src[-d];
+            a1 += src[1 - d];
         }
-        for (int b = t; b < NB; b += kT) {
-            unsigned long long acc = 0;
-#pragma unroll
-            for (int r = 0; r < 9; ++r)
-                if (d[r] <= b) acc += dp[cur][b - d[r]];
-            dp[cur ^ 1][b] = acc > 0x7fffffffull ? 0x7fffffffu : (uint32_t)acc;
-        }
+        nxt[NB + 2 * t] = min(a0, kSat);
+        nxt[NB + 2 * t + 1] = min(a1, kSat);
         __syncthreads();
-        cur ^= 1;
+        uint32_t *tmp = cur;
+        cur = nxt;
+        nxt = tmp;
     }
-    int mine = NB;
-    for (int b = t; b < NB; b += kT)
-        if (dp[cur][b] >= (uint32_t)K) {
-            mine = b;
-            break;
-        }
+    const int mine = cur[NB + 2 * t] >= (uint32_t)K ? 2 * t : (cur[NB + 2 * t + 1] >= (uint32_t)K ? 2 * t + 1 : NB);
     atomicMin(sbest, mine);
     __syncthreads();
     const int r = *sbest;
@@ -315,12 +337,13 @@ constexpr int kNB = 512;   // grid points of the counting recursion
 
 template <int CAP>
 struct ThrSmem {
-    double fm[CAP];               // S(T) members / frontier: metric
+    double fm[CAP];               // S(T) members / frontier: metric (first the counting buffers)
     unsigned long long fw[CAP];   // rank nibbles (level i at bits 4i), later the lexicographic key
     uint16_t fe[CAP];             // enumeration (= lexicographic) position, carried through the sort
     uint16_t rank_of[CAP];        // enumeration position -> MoP rank (or 0xffff beyond K)
-    uint32_t dp[2][kNB];          // counting recursion; later bucket starts / cursors
+    uint32_t dp[2][kNB];          // bucket starts / cursors
     double w[kMaxN];
+    int dtab[kMaxN][9];           // bin shifts of the counting recursion
     uint32_t scan[kT / 64];
     int best;
 };
@@ -349,11 +372,11 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     }
     // (1) threshold on a coarse grid over the whole range, then a finer one
     const double h0 = 8.0 * wsum / (double)(kNB - 1);
-    const int b0 = dp_threshold<kNB>(S.w, N, K, h0, S.dp, &S.best);
+    const int b0 = dp_threshold<kNB>(S.w, N, K, h0, reinterpret_cast<uint32_t *>(S.fm), &S.best, S.dtab);
     double T = (b0 < 0 ? (double)(kNB - 1) : (double)b0) * h0;
     if (b0 > 0) {
         const double h1 = 1.25 * T / (double)(kNB - 1);
-        const int b1 = dp_threshold<kNB>(S.w, N, K, h1, S.dp, &S.best);
+        const int b1 = dp_threshold<kNB>(S.w, N, K, h1, reinterpret_cast<uint32_t *>(S.fm), &S.best, S.dtab);
         if (b1 >= 0) T = (double)b1 * h1;
     }
     // (2) enumerate S(T) level by level, in place: every thread first takes its
@@ -367,6 +390,9 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     __syncthreads();
     for (int l = 0; l < N; ++l) {
         const double wl = S.w[l];
+        double wr[9];   // the level's metric steps w_l r, formed once
+#pragma unroll
+        for (int r = 0; r < 9; ++r) wr[r] = wl * (double)r;
         const uint32_t chunk = (n + kT - 1) / kT;
         const uint32_t j0 = t * chunk;
         double m[PER];
@@ -379,8 +405,9 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             if ((uint32_t)q < chunk && j0 + q < n) {
                 m[q] = S.fm[j0 + q];
                 wd[q] = S.fw[j0 + q];
-                int r = 1;
-                while (r < 9 && m[q] + wl * (double)r <= T) ++r;
+                int r = 1;   // children r = 0 .. R-1 stay within T (the steps increase with r)
+#pragma unroll
+                for (int rr = 1; rr < 9; ++rr) r += (m[q] + wr[rr] <= T) ? 1 : 0;
                 R[q] = r;
                 cnt += r;
             }
@@ -393,11 +420,13 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         }
 #pragma unroll
         for (int q = 0; q < PER; ++q)
-            for (int r = 0; r < R[q]; ++r) {
-                S.fm[off] = m[q] + wl * (double)r;
-                S.fw[off] = wd[q] | ((unsigned long long)r << (4 * l));
-                ++off;
-            }
+#pragma unroll
+            for (int r = 0; r < 9; ++r)
+                if (r < R[q]) {
+                    S.fm[off] = m[q] + wr[r];
+                    S.fw[off] = wd[q] | ((unsigned long long)r << (4 * l));
+                    ++off;
+                }
         __syncthreads();
         n = total;
     }
@@ -419,9 +448,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             S.rank_of[j] = 0xffff;
             m[q] = S.fm[j];
             const unsigned long long wd = S.fw[j];
-            unsigned long long x = 0;   // level 0 in the most significant nibble
-            for (int i = 0; i < N; ++i) x |= ((wd >> (4 * i)) & 15ull) << (4 * (N - 1 - i));
-            lex[q] = x;
+            lex[q] = nibble_reverse(wd, N);   // level 0 in the most significant nibble
             bk[q] = min(kNB - 1, (int)(m[q] * scale));
         }
     }
@@ -498,12 +525,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         // suffix-major order: the nibble reversal of the lexicographic key
         const int NN = N;
         write_suffix_order(
-            [&](int k) {
-                const unsigned long long x = S.fw[k];
-                unsigned long long wd = 0;
-                for (int i = 0; i < NN; ++i) wd |= ((x >> (4 * (NN - 1 - i))) & 15ull) << (4 * i);
-                return wd;
-            },
+            [&](int k) { return nibble_reverse(S.fw[k], NN); },
             K, reinterpret_cast<unsigned long long *>(S.fm), S.fe, lexorder + K);
     }
 }
