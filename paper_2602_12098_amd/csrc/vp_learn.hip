@@ -328,120 +328,189 @@ __device__ __forceinline__ uint32_t okey(float f) {   // larger float -> larger 
     return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
 }
 
-__global__ __launch_bounds__(64) void k_topk64(const float *__restrict__ S, int rows, int C,
-                                               int32_t *__restrict__ idx_out, float *__restrict__ mass_out) {
+__device__ __forceinline__ float key_value(uint32_t k) {   // inverse of okey
+    return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+
+constexpr int kTopT = 256;              // threads per row
+constexpr int kTopPer = 4096 / kTopT;   // columns per thread
+
+// Block-wide exclusive prefix of x over threads (thread order); *total gets the sum.
+__device__ __forceinline__ uint32_t topk_scan(uint32_t x, uint32_t *tmp, uint32_t *total) {
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+    uint32_t incl = x;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) tmp[wv] = incl;
+    __syncthreads();
+    uint32_t base = 0, tot = 0;
+#pragma unroll
+    for (int q = 0; q < kTopT / 64; ++q) {
+        base += (q < wv) ? tmp[q] : 0u;
+        tot += tmp[q];
+    }
+    __syncthreads();
+    *total = tot;
+    return base + incl - x;
+}
+
+__global__ __launch_bounds__(kTopT) void k_topk64(const float *__restrict__ S, int rows, int C,
+                                                  int32_t *__restrict__ idx_out, float *__restrict__ mass_out) {
     __shared__ uint32_t hist[256];
     __shared__ uint32_t sel_key[64];
     __shared__ uint32_t sel_idx[64];
+    __shared__ uint32_t tmp[kTopT / 64];
+    __shared__ float redf[kTopT / 64];
+    __shared__ uint32_t s_bin, s_before, s_ngt;
     const int row = blockIdx.x;
-    const int lane = threadIdx.x;
-    if (row >= rows) return;
+    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const float *x = S + (size_t)row * C;
-    constexpr int PER = 4096 / 64;
-    uint32_t key[PER];
+    uint32_t key[kTopPer];
+    uint32_t tmax = 0u;
     float mx = -INFINITY;
 #pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int c = q * 64 + lane;
+    for (int q = 0; q < kTopPer; ++q) {   // column q * 256 + t
+        const int c = q * kTopT + t;
         const float f = c < C ? x[c] : -INFINITY;
         key[q] = c < C ? okey(f) : 0u;
+        if (c < C) tmax = max(tmax, key[q]);
         mx = fmaxf(mx, f);
     }
-    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-    // radix select: find the key of rank 63 in descending order
-    uint32_t prefix = 0, pmask = 0;
-    int need = 64;   // how many still to take at or below the current prefix
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        for (int b = lane; b < 256; b += 64) hist[b] = 0;
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; ++q)
-            if (q * 64 + lane < C && (key[q] & pmask) == prefix) atomicAdd(&hist[(key[q] >> shift) & 255u], 1u);
-        __syncthreads();
-        // from the top bin down, find the bin where the cumulative count reaches need
-        uint32_t h[4];
-        for (int j = 0; j < 4; ++j) h[j] = hist[255 - (lane * 4 + j)];
-        uint32_t local = h[0] + h[1] + h[2] + h[3];
-        uint32_t incl = local;
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off);
-            if (lane >= off) incl += y;
-        }
-        const uint32_t excl = incl - local;
-        int found_bin = -1, taken_before = 0;
-        uint32_t run = excl;
-        for (int j = 0; j < 4; ++j) {
-            if (found_bin < 0 && run + h[j] >= (uint32_t)need && run < (uint32_t)need) {
-                found_bin = 255 - (lane * 4 + j);
-                taken_before = (int)run;
-            }
-            run += h[j];
-        }
-        const unsigned long long bal = __ballot(found_bin >= 0);
-        const int src = __ffsll((long long)bal) - 1;
-        const int fb = __shfl(found_bin, src);
-        const int tb = __shfl(taken_before, src);
-        prefix |= (uint32_t)fb << shift;
-        pmask |= 255u << shift;
-        need -= tb;
-        __syncthreads();
-    }
-    // prefix is the key of the 64th largest; take every key above it and the
-    // `need` equal ones of smallest column
-    const uint32_t T = prefix;
-    int nsel = 0, eq_taken = 0;
-    float se = 0.f, sall = 0.f;
-#pragma unroll
-    for (int q = 0; q < PER; ++q) {
-        const int c = q * 64 + lane;
-        const bool in = c < C;
-        const float f = in ? x[c] : 0.f;
-        const float e = in ? __expf(f - mx) : 0.f;
-        sall += e;
-        const bool gt = in && key[q] > T;
-        const bool eq = in && key[q] == T;
-        const unsigned long long bg = __ballot(gt);
-        if (gt) {
-            const int pos = min(nsel + __popcll(bg & ((1ull << lane) - 1ull)), 63);
-            sel_key[pos] = key[q];
-            sel_idx[pos] = (uint32_t)c;
-            se += e;
-        }
-        nsel += __popcll(bg);
-        const unsigned long long be = __ballot(eq);
-        const int before = __popcll(be & ((1ull << lane) - 1ull));
-        if (eq && eq_taken + before < need && nsel + before < 64) {
-            sel_key[nsel + before] = key[q];
-            sel_idx[nsel + before] = (uint32_t)c;
-            se += e;
-        }
-        const int took = min(__popcll(be), need - eq_taken);
-        nsel += took;
-        eq_taken += took;
-    }
+    // bounds: the row maximum (for the softmax mass) and, per wave, the smallest
+    // of its 64 lanes' maxima -- 64 distinct entries reach it, so it bounds the
+    // 64th largest key from below (C >= 64: lanes 0..63 of wave 0 hold one each;
+    // a lane of another wave without columns holds 0 and yields the bound 0)
+    uint32_t wfloor = tmax;
     for (int off = 32; off > 0; off >>= 1) {
-        se += __shfl_xor(se, off);
-        sall += __shfl_xor(sall, off);
+        mx = fmaxf(mx, __shfl_xor(mx, off));
+        wfloor = min(wfloor, (uint32_t)__shfl_xor((int)wfloor, off));
+    }
+    if (lane == 0) {
+        redf[wv] = mx;
+        tmp[wv] = wfloor;
     }
     __syncthreads();
-    // bitonic sort of 64 (key desc, index asc) across the wave
-    uint32_t k = sel_key[lane], id = sel_idx[lane];
-    for (int size = 2; size <= 64; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t ok_ = __shfl_xor(k, stride), oi = __shfl_xor(id, stride);
-            const bool lower = (lane & stride) == 0;
-            const bool desc = (lane & size) == 0;   // this block sorts descending
-            // "a before b" in the final order: larger key, or equal key and smaller index
-            const bool mine_first = (k > ok_) || (k == ok_ && id < oi);
-            const bool keep = (lower == desc) ? mine_first : !mine_first;
-            if (!keep) {
-                k = ok_;
-                id = oi;
+    uint32_t floor_key = 0u;
+#pragma unroll
+    for (int q = 0; q < kTopT / 64; ++q) {
+        mx = fmaxf(mx, redf[q]);
+        floor_key = max(floor_key, tmp[q]);
+    }
+    __syncthreads();
+    // radix select over the keys >= floor_key: the key of rank 63 (descending)
+    uint32_t prefix = 0, pmask = 0;
+    int need = 64;
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        hist[t] = 0u;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < kTopPer; ++q)
+            if (q * kTopT + t < C && key[q] >= floor_key && (key[q] & pmask) == prefix)
+                atomicAdd(&hist[(key[q] >> shift) & 255u], 1u);
+        __syncthreads();
+        const uint32_t h = hist[255 - t];   // thread t: the t-th bin from the top
+        uint32_t tot;
+        const uint32_t before = topk_scan(h, tmp, &tot);
+        if (before < (uint32_t)need && before + h >= (uint32_t)need) {
+            s_bin = 255u - (uint32_t)t;
+            s_before = before;
+        }
+        __syncthreads();
+        prefix |= s_bin << shift;
+        pmask |= 255u << shift;
+        need -= (int)s_before;
+        __syncthreads();
+    }
+    const uint32_t T = prefix;   // the 64th largest key; take every key above it
+    // and the `need` entries equal to it of smallest column
+    if (t == 0) {
+        s_ngt = 0u;
+        s_bin = 0u;   // count of keys equal to T
+    }
+    __syncthreads();
+    uint32_t my_eq = 0;
+#pragma unroll
+    for (int q = 0; q < kTopPer; ++q) {
+        const int c = q * kTopT + t;
+        if (c < C && key[q] > T) {
+            const uint32_t pos = atomicAdd(&s_ngt, 1u);
+            if (pos < 64u) {
+                sel_key[pos] = key[q];
+                sel_idx[pos] = (uint32_t)c;
             }
         }
+        my_eq += (c < C && key[q] == T) ? 1u : 0u;
     }
-    idx_out[(size_t)row * 64 + lane] = (int32_t)id;
-    if (lane == 0 && mass_out) mass_out[row] = sall > 0.f ? se / sall : 0.f;
+    if (my_eq) atomicAdd(&s_bin, my_eq);
+    __syncthreads();
+    if (s_bin == (uint32_t)need) {   // every equal key is selected: no order needed
+#pragma unroll
+        for (int q = 0; q < kTopPer; ++q) {
+            const int c = q * kTopT + t;
+            if (c < C && key[q] == T) {
+                const uint32_t pos = atomicAdd(&s_ngt, 1u);
+                if (pos < 64u) {
+                    sel_key[pos] = key[q];
+                    sel_idx[pos] = (uint32_t)c;
+                }
+            }
+        }
+    } else {   // ties at the boundary: the equal keys of smallest column, block by block
+        uint32_t eq_run = 0;
+#pragma unroll
+        for (int q = 0; q < kTopPer; ++q) {
+            const int c = q * kTopT + t;
+            const bool eq = c < C && key[q] == T;
+            uint32_t tot;
+            const uint32_t rank = topk_scan(eq ? 1u : 0u, tmp, &tot);
+            if (eq && eq_run + rank < (uint32_t)need) {
+                const uint32_t pos = (uint32_t)(64 - need) + eq_run + rank;
+                sel_key[pos] = key[q];
+                sel_idx[pos] = (uint32_t)c;
+            }
+            eq_run += tot;
+        }
+    }
+    // softmax denominator from the registers: per thread around its own maximum
+    float tmx = -INFINITY;
+#pragma unroll
+    for (int q = 0; q < kTopPer; ++q)
+        if (q * kTopT + t < C) tmx = fmaxf(tmx, key_value(key[q]));
+    float se = 0.f;
+#pragma unroll
+    for (int q = 0; q < kTopPer; ++q)
+        if (q * kTopT + t < C) se += __expf(key_value(key[q]) - tmx);
+    se = (tmx > -INFINITY) ? se * __expf(tmx - mx) : 0.f;
+    for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
+    if (lane == 0) redf[wv] = se;
+    __syncthreads();
+    if (wv == 0) {
+        float sall = 0.f;
+#pragma unroll
+        for (int q = 0; q < kTopT / 64; ++q) sall += redf[q];
+        // bitonic sort of the 64 selected entries (key desc, column asc) in wave 0
+        uint32_t k = sel_key[lane], id = sel_idx[lane];
+        float ssel = __expf(key_value(k) - mx);
+        for (int size = 2; size <= 64; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const uint32_t ok_ = __shfl_xor(k, stride), oi = __shfl_xor(id, stride);
+                const bool lower = (lane & stride) == 0;
+                const bool desc = (lane & size) == 0;
+                const bool mine_first = (k > ok_) || (k == ok_ && id < oi);
+                const bool keep = (lower == desc) ? mine_first : !mine_first;
+                if (!keep) {
+                    k = ok_;
+                    id = oi;
+                }
+            }
+        }
+        for (int off = 32; off > 0; off >>= 1) ssel += __shfl_xor(ssel, off);
+        idx_out[(size_t)row * 64 + lane] = (int32_t)id;
+        if (lane == 0 && mass_out) mass_out[row] = sall > 0.f ? ssel / sall : 0.f;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -489,28 +558,33 @@ __global__ __launch_bounds__(256) void k_colsum(const uint16_t *__restrict__ X, 
 }
 
 // per-vector path table: the Kl proposed vocabulary entries, then the first
-// Kf paths of the subcarrier's fixed (MoP) table.
+// Kf paths of the subcarrier's fixed (MoP) table.  One thread per table row;
+// 16-level rows move as one 16-byte load and store.
 __global__ __launch_bounds__(256) void k_learned_table(const uint8_t *__restrict__ vocab, int V, int N,
                                                        const int32_t *__restrict__ top, int Kl,
                                                        const uint8_t *__restrict__ fixed, int Kfix_stride,
                                                        int Kf, int n_sc, int n_sym, uint8_t *__restrict__ table) {
     const size_t n_vec = (size_t)n_sc * n_sym;
     const int Kt = Kl + Kf;
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= n_vec * Kt * N) return;
-    const size_t v = e / ((size_t)Kt * N);
-    const int rem = (int)(e % ((size_t)Kt * N));
-    const int k = rem / N, i = rem % N;
-    uint8_t r;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;   // row (vector, path)
+    if (e >= n_vec * Kt) return;
+    const size_t v = e / Kt;
+    const int k = (int)(e % Kt);
+    const uint8_t *src;
     if (k < Kl) {
         int id = top[v * Kl + k];
         id = id < 0 ? 0 : (id >= V ? V - 1 : id);
-        r = vocab[(size_t)id * N + i];
+        src = vocab + (size_t)id * N;
     } else {
         const int sc = (int)(v / n_sym);
-        r = fixed[(size_t)sc * Kfix_stride * N + (size_t)(k - Kl) * N + i];
+        src = fixed + (size_t)sc * Kfix_stride * N + (size_t)(k - Kl) * N;
     }
-    table[e] = r;
+    uint8_t *dst = table + e * N;
+    if (N == 16 && ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0) {
+        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+    } else {
+        for (int i = 0; i < N; ++i) dst[i] = src[i];
+    }
 }
 
 }  // namespace
@@ -573,7 +647,7 @@ int launch_ranks(const float2 *W, const uint8_t *perm, const float2 *s, float ta
 
 int launch_topk64(const float *S, int rows, int C, int32_t *idx, float *mass, hipStream_t st) {
     if (rows == 0) return VP_OK;
-    hipLaunchKernelGGL(k_topk64, dim3(rows), dim3(64), 0, st, S, rows, C, idx, mass);
+    hipLaunchKernelGGL(k_topk64, dim3(rows), dim3(kTopT), 0, st, S, rows, C, idx, mass);
     return launch_status();
 }
 
@@ -592,7 +666,7 @@ int launch_colsum(const uint16_t *X, int rows, int cols, float *out, hipStream_t
 
 int launch_learned_table(const uint8_t *vocab, int V, int N, const int32_t *top, int Kl, const uint8_t *fixed,
                          int Kfix, int Kf, int n_sc, int n_sym, uint8_t *table, hipStream_t st) {
-    const size_t total = (size_t)n_sc * n_sym * (Kl + Kf) * N;
+    const size_t total = (size_t)n_sc * n_sym * (Kl + Kf);   // table rows
     if (total == 0) return VP_OK;
     hipLaunchKernelGGL(k_learned_table, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, vocab, V, N, top,
                        Kl, fixed, Kfix, Kf, n_sc, n_sym, table);
