@@ -103,12 +103,15 @@ constexpr int kMaxPrefix = kTT;   // stage-1 prefixes held in LDS at a time
 template <int N>
 constexpr int prefix_levels() { return N >= 4 ? N / 4 : 1; }
 
+constexpr int kVPB = 2;                 // vectors of one subcarrier per workgroup (they share its table)
+constexpr int kTB = kTT * kVPB;         // threads of the prefix-sharing search
+
 template <int N>
-__global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+__global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
                                                      const float2 *__restrict__ s, float tau,
                                                      const uint8_t *__restrict__ paths,
                                                      const uint16_t *__restrict__ order, int K,
-                                                     long long pstride, int n_sym, unsigned flags,
+                                                     long long pstride, int n_sym, size_t n_vec, unsigned flags,
                                                      float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
     constexpr int P1 = prefix_levels<N>();
     constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
@@ -117,23 +120,28 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
     uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of lex position
     uint16_t *s_lexpos = s_node + K;                                // [K] lex position of path k
     uint16_t *s_first = s_lexpos + K;                               // [K + 1] first lex position of a prefix
-    __shared__ float s_state[kMaxPrefix * SW];
-    __shared__ float2 s_r0[N];
+    __shared__ float s_state[kVPB][kMaxPrefix * SW];
+    __shared__ float2 s_r0[kVPB][N];
     __shared__ float s_linv[N];
     __shared__ float s_wdiag[N];
     __shared__ uint8_t s_perm[N];
-    __shared__ uint32_t s_scan[kTT / 64];
-    __shared__ unsigned long long s_red[kTT / 64];
+    __shared__ uint32_t s_scan[kTB / 64];
+    __shared__ unsigned long long s_red[kTB / 64];
 
     constexpr int NP = VP_PACKED(N);
-    const size_t v = xcd_contiguous(blockIdx.x, gridDim.x);
-    const int sc = (int)(v / n_sym);
+    const int slots = (n_sym + kVPB - 1) / kVPB;
+    const uint32_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int sc = (int)(blk / slots);
     const int t = threadIdx.x;
-    const size_t n_vec = (size_t)gridDim.x;
+    const int h = __builtin_amdgcn_readfirstlane(t / kTT);   // this thread's vector in the workgroup
+    const int tl = t % kTT;
+    const int sym = (int)(blk % slots) * kVPB + h;
+    const bool live = sym < n_sym;
+    const size_t v = (size_t)sc * n_sym + (live ? sym : 0);
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
-    if (!(w00 > 0.f) || !isfinite(w00)) {
-        if (t == 0) {
+    if (!(w00 > 0.f) || !isfinite(w00)) {   // failed preprocessing (the whole subcarrier)
+        if (tl == 0 && live) {
             cost_out[v] = __int_as_float(0x7fc00000);
             kidx_out[v] = -1;
         }
@@ -147,7 +155,7 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         s_linv[t] = 1.0f / s_wdiag[t];
         s_perm[t] = perm[(size_t)sc * N + t];
     }
-    for (int j = t; j < K; j += kTT) {
+    for (int j = t; j < K; j += kTB) {
         int k = LX[j];
         k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
         s_k[j] = (uint16_t)k;
@@ -155,10 +163,10 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         s_words[j] = load_word<N>(P, k);
     }
     __syncthreads();
-    if (t < N) s_r0[t] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, t, 1.0f / tau);
+    if (tl < N && live) s_r0[h][tl] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, tl, 1.0f / tau);
     // prefix boundaries: contiguous chunk of lex positions per thread, then a block scan
     constexpr unsigned long long PMASK = P1 >= 16 ? ~0ull : ((1ull << (4 * P1)) - 1ull);
-    const int chunk = (K + kTT - 1) / kTT;
+    const int chunk = (K + kTB - 1) / kTB;
     const int j0 = t * chunk, j1 = min(K, j0 + chunk);
     uint32_t cnt = 0;
     for (int j = j0; j < j1; ++j)
@@ -176,7 +184,7 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         for (int q = 0; q < wv; ++q) incl += s_scan[q];
     }
     uint32_t n1 = 0;
-    for (int q = 0; q < kTT / 64; ++q) n1 += s_scan[q];
+    for (int q = 0; q < kTB / 64; ++q) n1 += s_scan[q];
     uint32_t node = incl - cnt;
     for (int j = j0; j < j1; ++j) {
         if (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull) s_first[node++] = (uint16_t)j;
@@ -186,15 +194,16 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
     __syncthreads();
     const float tau2 = tau * tau;
     unsigned long long best = ~0ull;
+    float *state = s_state[h];
     for (uint32_t base = 0; base < n1; base += kMaxPrefix) {
         const uint32_t nc = min(n1 - base, (uint32_t)kMaxPrefix);
-        if (t < (int)nc) {   // stage 1: one lane per distinct prefix
+        if (live && tl < (int)nc) {   // stage 1: one lane per distinct prefix
             float2 r[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) r[i] = s_r0[i];
-            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_first[base + t]],
+            for (int i = 0; i < N; ++i) r[i] = s_r0[h][i];
+            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_first[base + tl]],
                                                            VP_DEMAP_LUT, nullptr, nullptr);
-            float *st = s_state + t * SW;
+            float *st = state + tl * SW;
 #pragma unroll
             for (int i = P1; i < N; ++i) {
                 st[2 * (i - P1)] = r[i].x;
@@ -207,8 +216,8 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         // case) the contiguous lexicographic range of this chunk's prefixes
         const bool whole = (n1 <= (uint32_t)kMaxPrefix);
         const int q0 = whole ? 0 : s_first[base];
-        const int q1 = whole ? K : s_first[base + nc];
-        for (int q = q0 + t; q < q1; q += kTT) {
+        const int q1 = live ? (whole ? K : s_first[base + nc]) : q0;
+        for (int q = q0 + tl; q < q1; q += kTT) {
             int j;
             if (whole) {
                 int kk = SX[q];
@@ -217,7 +226,7 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
             } else {
                 j = q;
             }
-            const float *st = s_state + (s_node[j] - base) * SW;
+            const float *st = state + (s_node[j] - base) * SW;
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
@@ -229,20 +238,21 @@ __global__ __launch_bounds__(kTT) void k_search_trie(const float2 *__restrict__ 
         }
         __syncthreads();
     }
-    if ((flags & VP_INCLUDE_ZERO) && t == 0) {
+    if ((flags & VP_INCLUDE_ZERO) && tl == 0 && live) {
         float z = 0.f;
         for (int i = 0; i < N; ++i) {
-            z = fmaf(s_r0[i].x, s_r0[i].x, z);
-            z = fmaf(s_r0[i].y, s_r0[i].y, z);
+            z = fmaf(s_r0[h][i].x, s_r0[h][i].x, z);
+            z = fmaf(s_r0[h][i].y, s_r0[h][i].y, z);
         }
         best = umin64(best, ((unsigned long long)__float_as_uint(z * tau2) << 32) | (unsigned)K);
     }
     best = wave_min(best);
     if ((t & 63) == 0) s_red[t >> 6] = best;
     __syncthreads();
-    if (t == 0) {
-        unsigned long long b = s_red[0];
-        for (int w = 1; w < kTT / 64; ++w) b = umin64(b, s_red[w]);
+    if (tl == 0 && live) {
+        constexpr int WPV = kTT / 64;   // waves per vector
+        unsigned long long b = s_red[h * WPV];
+        for (int w = 1; w < WPV; ++w) b = umin64(b, s_red[h * WPV + w]);
         cost_out[v] = __uint_as_float((unsigned)(b >> 32));
         kidx_out[v] = (int32_t)(b & 0xffffffffull);
     }
@@ -374,8 +384,9 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024),
                                       0);
         (void)attr_once;
-        hipLaunchKernelGGL(k_search_trie<N>, dim3((unsigned)n_vec), dim3(kTT), smem, st, W, perm, s, tau, paths,
-                           order, K, (long long)pstride, n_sym, flags, cost, kidx);
+        const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);
+        hipLaunchKernelGGL(k_search_trie<N>, dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths, order, K,
+                           (long long)pstride, n_sym, n_vec, flags, cost, kidx);
     } else if (K <= kWaveMaxK) {
         hipLaunchKernelGGL(k_search_wave<N>, dim3((unsigned)((n_vec + kWV - 1) / kWV)), dim3(64 * kWV), 0, st, W,
                            perm, s, tau, paths, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx);
