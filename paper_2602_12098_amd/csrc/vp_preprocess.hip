@@ -16,6 +16,31 @@ namespace {
 
 constexpr int kT = 256;
 
+// Column c of W = Lbar^{-1}: W_rc = (delta_rc - sum_{c<=k<r} Lbar_rk W_kc) / Lbar_rr,
+// row r of Lbar being user perm[r]'s factor row Lc[perm[r]][.].
+template <int NN>
+__device__ __forceinline__ void forward_column(int c, const int *sperm, const float2 (*Lc)[kMaxN + 1],
+                                               float2 (*Wl)[kMaxN + 1]) {
+    float2 w[NN];
+#pragma unroll
+    for (int r = 0; r < NN; ++r) {
+        const int ur = sperm[r];
+        float re = (r == c) ? 1.f : 0.f, im = 0.f;
+#pragma unroll
+        for (int k = 0; k < r; ++k) {   // - Lbar_rk W_kc, k >= c
+            if (k >= c) {
+                const float2 a = Lc[ur][k], b = w[k];
+                re = fmaf(-a.x, b.x, fmaf(a.y, b.y, re));
+                im = fmaf(-a.x, b.y, fmaf(-a.y, b.x, im));
+            }
+        }
+        const float d = Lc[ur][r].x;
+        w[r] = (r < c) ? make_float2(0.f, 0.f) : make_float2(re / d, im / d);
+    }
+#pragma unroll
+    for (int r = 0; r < NN; ++r) Wl[r][c] = w[r];
+}
+
 // One subcarrier: Hs its [N][M] channel; Wsc, w2sc, permsc, Gsc (or NULL),
 // status_sc its outputs.
 __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha, float2 *__restrict__ Wsc,
@@ -66,21 +91,27 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     floor_ *= (float)N * 1.1920929e-7f;
 
     for (int step = 0; step < N; ++step) {
-        if (t == 0) {
-            int p = -1;
-            float best = 0.f;
-            for (int u = 0; u < N; ++u) {   // ascending u: ties keep the smaller user
-                if (!srem[u]) continue;
-                const float d = S[u][u].x;
-                if (p < 0 || d < best) {
-                    p = u;
-                    best = d;
-                }
+        if (t < 64) {   // wave 0: smallest remaining Schur diagonal, ties to the smaller user
+            const bool cand = (t < N) && srem[t];
+            float d = cand ? S[t][t].x : 0.f;
+            int u = cand ? t : 0x7fffffff;
+            // order by (value, user); a NaN diagonal (only from non-finite input,
+            // which fails the subcarrier anyway) never beats a number
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                const float od = __shfl_xor(d, off);
+                const int ou = __shfl_xor(u, off);
+                const bool ovalid = ou != 0x7fffffff, valid = u != 0x7fffffff;
+                const bool take = ovalid & ((!valid) | (od < d) | ((od == d) & (ou < u)));
+                d = take ? od : d;
+                u = take ? ou : u;
             }
-            if (!(best > floor_) && sstatus == VP_STATUS_OK) sstatus = VP_STATUS_NOT_PD;
-            sperm[step] = p;
-            srem[p] = 0;
-            spiv = sqrtf(fmaxf(best, 0.f));
+            if (t == 0) {
+                if (!(d > floor_) && sstatus == VP_STATUS_OK) sstatus = VP_STATUS_NOT_PD;
+                sperm[step] = u;
+                srem[u] = 0;
+                spiv = sqrtf(fmaxf(d, 0.f));
+            }
         }
         __syncthreads();
         const int p = sperm[step];
@@ -119,20 +150,16 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         return;
     }
 
-    // W = Lbar^{-1}: thread c solves Lbar x = e_c by forward substitution.
+    // W = Lbar^{-1}: thread c solves Lbar x = e_c by forward substitution,
+    // its column held in registers.
     if (t < N) {
-        const int c = t;
-        for (int r = 0; r < c; ++r) Wl[r][c] = make_float2(0.f, 0.f);
-        for (int r = c; r < N; ++r) {
-            const int ur = sperm[r];
-            float re = (r == c) ? 1.f : 0.f, im = 0.f;
-            for (int k = c; k < r; ++k) {   // - Lbar_rk W_kc
-                const float2 a = Lc[ur][k], b = Wl[k][c];
-                re = fmaf(-a.x, b.x, fmaf(a.y, b.y, re));
-                im = fmaf(-a.x, b.y, fmaf(-a.y, b.x, im));
-            }
-            const float d = Lc[ur][r].x;
-            Wl[r][c] = make_float2(re / d, im / d);
+        switch (N) {
+#define VP_CASE(n) \
+    case n: forward_column<n>(t, sperm, Lc, Wl); break;
+            VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
+            VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
+#undef VP_CASE
+            default: break;
         }
     }
     __syncthreads();
