@@ -499,9 +499,20 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         }
     }
     __syncthreads();
-    for (int idx = t; idx < K * N; idx += kT) {
-        const int k = idx / N, i = idx % N;
-        out[idx] = (uint8_t)((S.fw[k] >> (4 * (N - 1 - i))) & 15ull);
+    for (int k = t; k < K; k += kT) {   // one path per thread: its N rank bytes
+        const unsigned long long w = nibble_reverse(S.fw[k], N);   // level i at bits 4i
+        uint8_t *o = out + (size_t)k * N;
+        if (N == 16 && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+            uint32_t d[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t n4 = (uint32_t)(w >> (16 * q));   // levels 4q .. 4q+3
+                d[q] = (n4 & 15u) | ((n4 >> 4) & 15u) << 8 | ((n4 >> 8) & 15u) << 16 | ((n4 >> 12) & 15u) << 24;
+            }
+            *reinterpret_cast<uint4 *>(o) = make_uint4(d[0], d[1], d[2], d[3]);
+        } else {
+            for (int i = 0; i < N; ++i) o[i] = (uint8_t)((w >> (4 * i)) & 15ull);
+        }
     }
     if (order) {
         uint16_t *lexorder = order;
