@@ -111,6 +111,30 @@ VP_HD float vp_pick_offset(float o0, float o1, float o2, int p) {
     return v;
 }
 
+// Children of rank 0, 1 or 2.  In the box order a cell follows every cell
+// that is nearer on both axes, so the rank-2 cell is, after a rank-1 cell
+// (0,1), the first of (1,0) and (0,2), and after a rank-1 cell (1,0), the
+// first of (0,1) and (2,0).  The three comparisons are bits 0, 2 and 1 of the
+// signature above, with the same tie rule, so the result is that of the
+// table for every rank up to 2.
+VP_HD void vp_demap2(float cx, float cy, int rank, float &a, float &b) {
+    const vp_axis X = vp_axis_order(cx);
+    const vp_axis Y = vp_axis_order(cy);
+    const int32_t ia = vp_fbits(X.A), ib = vp_fbits(X.B), ic = vp_fbits(Y.A), id = vp_fbits(Y.B);
+    const int32_t a1 = ia + (int32_t)(X.o0 < X.o1);
+    const bool q1 = ic < a1;                                  // (0,1) before (1,0)
+    const bool y2 = id < a1;                                  // (0,2) before (1,0)
+    const bool y1 = ic < ib + (int32_t)(X.o0 < X.o2);         // (0,1) before (2,0)
+    const bool r1 = (rank == 1), r2 = (rank == 2);
+    // cell (p, q) of the requested rank, as per-axis ranks
+    const bool p1 = (r1 & !q1) | (r2 & q1 & !y2);
+    const bool p2 = r2 & !q1 & !y1;
+    const bool s1 = (r1 & q1) | (r2 & !q1 & y1);
+    const bool s2 = r2 & q1 & y2;
+    a = p2 ? X.o2 : (p1 ? X.o1 : X.o0);
+    b = s2 ? Y.o2 : (s1 ? Y.o1 : Y.o0);
+}
+
 VP_HD void vp_demapN(float cx, float cy, int rank, const uint8_t *lut, float &a, float &b) {
     const vp_axis X = vp_axis_order(cx);
     const vp_axis Y = vp_axis_order(cy);

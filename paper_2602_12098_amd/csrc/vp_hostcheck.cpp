@@ -4,7 +4,8 @@
 
 extern "C" {
 
-// tier 0: rank 0 only; tier 1: ranks 0..1; tier 2: any rank (table lookup).
+// tier 0: rank 0 only; tier 1: ranks 0..1; tier 2: ranks 0..2; tier 3: any
+// rank (table lookup).
 int vp_host_demap(const float *cx, const float *cy, const int32_t *rank, int n, int tier, float *a,
                   float *b) {
     for (int k = 0; k < n; ++k) {
@@ -15,6 +16,9 @@ int vp_host_demap(const float *cx, const float *cy, const int32_t *rank, int n, 
         } else if (tier == 1) {
             if (rank[k] > 1) return -1;
             vp_demap1(cx[k], cy[k], rank[k], aa, bb);
+        } else if (tier == 2) {
+            if (rank[k] > 2) return -1;
+            vp_demap2(cx[k], cy[k], rank[k], aa, bb);
         } else {
             vp_demapN(cx[k], cy[k], rank[k], VP_DEMAP_LUT, aa, bb);
         }

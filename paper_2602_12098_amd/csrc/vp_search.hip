@@ -97,8 +97,14 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
 // DEMAP work.  A table with more than kMaxPrefix distinct prefixes is done in
 // chunks of kMaxPrefix prefixes (their paths are contiguous in lexicographic
 // order).  Every path sees exactly the arithmetic of a direct walk.
-constexpr int kTT = 128;          // threads of the prefix-sharing search
-constexpr int kMaxPrefix = kTT;   // stage-1 prefixes held in LDS at a time
+//
+// Occupancy: the walk is a long chain of dependent VALU work, so it runs best
+// with five waves per SIMD (at most 96 VGPRs, and at most a fifth of the
+// CU's 160 KiB LDS per workgroup: 120 stage-1 states of two vectors and the
+// K = 512 tables come to 31 KiB).
+constexpr int kTT = 128;          // threads of the prefix-sharing search, per vector
+constexpr int kMaxPrefix = 120;   // stage-1 prefixes held in LDS at a time
+constexpr int kTrieWaves = 5;     // waves per SIMD the register budget is set for
 
 template <int N>
 constexpr int prefix_levels() { return N >= 4 ? N / 4 : 1; }
@@ -107,7 +113,7 @@ constexpr int kVPB = 2;                 // vectors of one subcarrier per workgro
 constexpr int kTB = kTT * kVPB;         // threads of the prefix-sharing search
 
 template <int N>
-__global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
                                                      const float2 *__restrict__ s, float tau,
                                                      const uint8_t *__restrict__ paths,
                                                      const uint16_t *__restrict__ order, int K,
@@ -115,11 +121,10 @@ __global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ 
                                                      float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
     constexpr int P1 = prefix_levels<N>();
     constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
-    extern __shared__ unsigned long long s_words[];   // [K] rank nibbles, lexicographic order
+    extern __shared__ unsigned long long s_words[];   // [K] rank nibbles of path k
     uint16_t *s_k = reinterpret_cast<uint16_t *>(s_words + K);     // [K] path index of lex position
-    uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of lex position
-    uint16_t *s_lexpos = s_node + K;                                // [K] lex position of path k
-    uint16_t *s_first = s_lexpos + K;                               // [K + 1] first lex position of a prefix
+    uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of path k
+    uint16_t *s_first = s_node + K;                                 // [K + 1] first lex position of a prefix
     __shared__ float s_state[kVPB][kMaxPrefix * SW];
     __shared__ float2 s_r0[kVPB][N];
     __shared__ float s_linv[N];
@@ -159,8 +164,7 @@ __global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ 
         int k = LX[j];
         k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
         s_k[j] = (uint16_t)k;
-        s_lexpos[k] = (uint16_t)j;
-        s_words[j] = load_word<N>(P, k);
+        s_words[j] = load_word<N>(P, j);
     }
     __syncthreads();
     if (tl < N && live) s_r0[h][tl] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, tl, 1.0f / tau);
@@ -169,8 +173,13 @@ __global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ 
     const int chunk = (K + kTB - 1) / kTB;
     const int j0 = t * chunk, j1 = min(K, j0 + chunk);
     uint32_t cnt = 0;
-    for (int j = j0; j < j1; ++j)
-        cnt += (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull) ? 1u : 0u;
+    // the word of lex position j is s_words[s_k[j]]
+    unsigned long long prev = j0 > 0 && j0 < j1 ? s_words[s_k[j0 - 1]] : 0ull;
+    for (int j = j0; j < j1; ++j) {
+        const unsigned long long wj = s_words[s_k[j]];
+        cnt += (j == 0 || ((wj ^ prev) & PMASK) != 0ull) ? 1u : 0u;
+        prev = wj;
+    }
     uint32_t incl = cnt;
     {
         const int lane = t & 63, wv = t >> 6;
@@ -186,9 +195,12 @@ __global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ 
     uint32_t n1 = 0;
     for (int q = 0; q < kTB / 64; ++q) n1 += s_scan[q];
     uint32_t node = incl - cnt;
+    prev = j0 > 0 && j0 < j1 ? s_words[s_k[j0 - 1]] : 0ull;
     for (int j = j0; j < j1; ++j) {
-        if (j == 0 || ((s_words[j] ^ s_words[j - 1]) & PMASK) != 0ull) s_first[node++] = (uint16_t)j;
-        s_node[j] = (uint16_t)(node - 1);
+        const unsigned long long wj = s_words[s_k[j]];
+        if (j == 0 || ((wj ^ prev) & PMASK) != 0ull) s_first[node++] = (uint16_t)j;
+        s_node[s_k[j]] = (uint16_t)(node - 1);
+        prev = wj;
     }
     if (t == 0) s_first[n1] = (uint16_t)K;
     __syncthreads();
@@ -201,7 +213,7 @@ __global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ 
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) r[i] = s_r0[h][i];
-            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_first[base + tl]],
+            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_k[s_first[base + tl]]],
                                                            VP_DEMAP_LUT, nullptr, nullptr);
             float *st = state + tl * SW;
 #pragma unroll
@@ -218,23 +230,24 @@ __global__ __launch_bounds__(kTB) void k_search_trie(const float2 *__restrict__ 
         const int q0 = whole ? 0 : s_first[base];
         const int q1 = live ? (whole ? K : s_first[base + nc]) : q0;
         for (int q = q0 + tl; q < q1; q += kTT) {
-            int j;
+            int k;
             if (whole) {
-                int kk = SX[q];
-                kk = kk < K ? kk : K - 1;
-                j = s_lexpos[kk];
+                k = SX[q];
+                k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
             } else {
-                j = q;
+                k = s_k[q];
             }
-            const float *st = state + (s_node[j] - base) * SW;
+            int nd = (int)s_node[k] - (int)base;   // in [0, nc) unless the order is corrupt
+            nd = nd < 0 ? 0 : (nd < (int)nc ? nd : (int)nc - 1);
+            const float *st = state + nd * SW;
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
 #pragma unroll
             for (int i = P1; i < N; ++i) r[i] = make_float2(st[2 * (i - P1)], st[2 * (i - P1) + 1]);
-            const float ped = walk<N, true, false, P1, N>(Wc, s_linv, s_wdiag, r, s_words[j], VP_DEMAP_LUT,
+            const float ped = walk<N, true, false, P1, N>(Wc, s_linv, s_wdiag, r, s_words[k], VP_DEMAP_LUT,
                                                            nullptr, nullptr, st[SW - 1]);
-            best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)s_k[j]);
+            best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
         }
         __syncthreads();
     }
@@ -379,7 +392,7 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
                     float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
     if (order) {
-        const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(4 * K + 1) * sizeof(uint16_t);
+        const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(3 * K + 1) * sizeof(uint16_t);
         static const int attr_once = (hipFuncSetAttribute((const void *)k_search_trie<N>,
                                                           hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024),
                                       0);

@@ -61,10 +61,11 @@ __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float
         const float cx = -(r[i].x * li);
         const float cy = -(r[i].y * li);
         float a, b;
-        if (UNIFORM_TIERS) {
-            if (__any(rank > 1)) vp_demapN(cx, cy, rank, lut, a, b);
-            else if (__any(rank != 0)) vp_demap1(cx, cy, rank, a, b);
-            else vp_demap0(cx, cy, a, b);
+        if (UNIFORM_TIERS) {   // the cheapest variant that serves every lane of the wave
+            if (!__any(rank != 0)) vp_demap0(cx, cy, a, b);
+            else if (!__any(rank > 1)) vp_demap1(cx, cy, rank, a, b);
+            else if (!__any(rank > 2)) vp_demap2(cx, cy, rank, a, b);
+            else vp_demapN(cx, cy, rank, lut, a, b);
         } else {
             vp_demapN(cx, cy, rank, lut, a, b);
         }

@@ -120,8 +120,8 @@ def test_demap_exact_ties_follow_canonical_order():
     order = np.argsort(O.sqabs(c[:, None] - O.BOX[None, :]), axis=1, kind="stable")
     for r in range(9):
         ref = O.BOX[order[:, r]]
-        for tier in (0, 1, 2):
-            if (tier == 0 and r > 0) or (tier == 1 and r > 1):
+        for tier in (0, 1, 2, 3):
+            if r > tier and tier < 3:
                 continue
             a, b = run(cx, cy, np.full(len(cx), r), tier)
             bad = np.nonzero((a != ref.real) | (b != ref.imag))[0]
@@ -145,12 +145,15 @@ def test_demap_matches_oracle_order():
     order = np.argsort(d, axis=1, kind="stable")
     ds = np.take_along_axis(d, order, 1)
     for r in range(9):
-        a, b = run(cx, cy, np.full(len(cx), r), 2)
+        a, b = run(cx, cy, np.full(len(cx), r), 3)
         ref = O.BOX[order[:, r]]
         mism = (a != ref.real) | (b != ref.imag)
         lo = ds[:, r] - ds[:, max(r - 1, 0)] if r > 0 else np.full(len(cx), np.inf)
         hi = ds[:, min(r + 1, 8)] - ds[:, r] if r < 8 else np.full(len(cx), np.inf)
         assert not np.any(mism & (np.minimum(lo, hi) > 1e-5)), r
+        if r <= 2:
+            a2, b2 = run(cx, cy, np.full(len(cx), r), 2)
+            assert np.array_equal(a2, a) and np.array_equal(b2, b)
         if r <= 1:
             a1, b1 = run(cx, cy, np.full(len(cx), r), 1)
             assert np.array_equal(a1, a) and np.array_equal(b1, b)
@@ -158,10 +161,12 @@ def test_demap_matches_oracle_order():
             a0, b0 = run(cx, cy, np.full(len(cx), r), 0)
             assert np.array_equal(a0, a) and np.array_equal(b0, b)
     # the exact diagonal ties of QAM centres are resolved by the canonical index
-    a, b = run(np.array([-3 / 32.0]), np.array([-3 / 32.0]), np.array([1]), 2)
-    assert (a[0], b[0]) == (-1.0, 0.0)
-    a, b = run(np.array([-3 / 32.0]), np.array([-3 / 32.0]), np.array([2]), 2)
-    assert (a[0], b[0]) == (0.0, -1.0)
+    for tier in (1, 2, 3):
+        a, b = run(np.array([-3 / 32.0]), np.array([-3 / 32.0]), np.array([1]), tier)
+        assert (a[0], b[0]) == (-1.0, 0.0)
+    for tier in (2, 3):
+        a, b = run(np.array([-3 / 32.0]), np.array([-3 / 32.0]), np.array([2]), tier)
+        assert (a[0], b[0]) == (0.0, -1.0)
 
 
 def test_demap_table_is_generated():
