@@ -337,7 +337,8 @@ constexpr int kNB = 512;   // grid points of the counting recursion
 
 template <int CAP>
 struct ThrSmem {
-    double fm[CAP];               // S(T) members / frontier: metric (first the counting buffers)
+    // fm and fw, adjacent, first hold the counting recursion's two buffers
+    double fm[CAP];               // S(T) members / frontier: metric
     unsigned long long fw[CAP];   // rank nibbles (level i at bits 4i), later the lexicographic key
     uint16_t fe[CAP];             // enumeration (= lexicographic) position, carried through the sort
     uint16_t rank_of[CAP];        // enumeration position -> MoP rank (or 0xffff beyond K)
@@ -346,7 +347,18 @@ struct ThrSmem {
     int dtab[kMaxN][9];           // bin shifts of the counting recursion
     uint32_t scan[kT / 64];
     int best;
+
+    __device__ uint32_t *count_buffers() {
+        static_assert(2 * CAP * sizeof(double) >= 4 * kNB * sizeof(uint32_t), "fm and fw hold the counting buffers");
+        return reinterpret_cast<uint32_t *>(fm);
+    }
 };
+
+// Frontier capacity of the threshold pass for tables of up to 512 paths: the
+// enumerated set exceeds K by a few members for spread weights (513 to 522
+// for K = 512 on 16 x 16 Rayleigh channels); a larger set sends the table to
+// the K-best kernel.  20 KiB of LDS, eight workgroups per CU.
+constexpr int kCap512 = 768;
 
 // One subcarrier (pointers as for mop_kbest_one).  Marks the table for the
 // K-best kernel when the threshold enumeration does not fit.
@@ -372,11 +384,11 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     }
     // (1) threshold on a coarse grid over the whole range, then a finer one
     const double h0 = 8.0 * wsum / (double)(kNB - 1);
-    const int b0 = dp_threshold<kNB>(S.w, N, K, h0, reinterpret_cast<uint32_t *>(S.fm), &S.best, S.dtab);
+    const int b0 = dp_threshold<kNB>(S.w, N, K, h0, S.count_buffers(), &S.best, S.dtab);
     double T = (b0 < 0 ? (double)(kNB - 1) : (double)b0) * h0;
     if (b0 > 0) {
         const double h1 = 1.25 * T / (double)(kNB - 1);
-        const int b1 = dp_threshold<kNB>(S.w, N, K, h1, reinterpret_cast<uint32_t *>(S.fm), &S.best, S.dtab);
+        const int b1 = dp_threshold<kNB>(S.w, N, K, h1, S.count_buffers(), &S.best, S.dtab);
         if (b1 >= 0) T = (double)b1 * h1;
     }
     // (2) enumerate S(T) level by level, in place: every thread first takes its
@@ -557,11 +569,11 @@ __global__ __launch_bounds__(kT) void k_batch_mop_thr(const BatchGroup *__restri
                                                       const int32_t *__restrict__ sc_group,
                                                       const float *__restrict__ w2, uint8_t *__restrict__ paths) {
     extern __shared__ unsigned char smem_raw[];
-    ThrSmem<1024> &S = *reinterpret_cast<ThrSmem<1024> *>(smem_raw);
+    ThrSmem<kCap512> &S = *reinterpret_cast<ThrSmem<kCap512> *>(smem_raw);
     const int sc = blockIdx.x;
     const BatchGroup g = groups[sc_group[sc]];
     const long long j = sc - g.sc0;
-    mop_thr_one<1024>(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr);
+    mop_thr_one<kCap512>(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr);
 }
 
 __global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__restrict__ groups,
@@ -579,7 +591,7 @@ __global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__rest
 
 void prepare_batch_kernels() {
     (void)hipFuncSetAttribute((const void *)k_batch_mop_thr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(ThrSmem<1024>));
+                              (int)sizeof(ThrSmem<kCap512>));
     (void)hipFuncSetAttribute((const void *)k_batch_mop_kbest, hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)sizeof(MopSmem));
 }
@@ -587,7 +599,7 @@ void prepare_batch_kernels() {
 int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, const float *w2,
                      uint8_t *paths, hipStream_t st) {
     if (n_sc_total == 0) return VP_OK;
-    hipLaunchKernelGGL(k_batch_mop_thr, dim3(n_sc_total), dim3(kT), sizeof(ThrSmem<1024>), st, groups, sc_group, w2,
+    hipLaunchKernelGGL(k_batch_mop_thr, dim3(n_sc_total), dim3(kT), sizeof(ThrSmem<kCap512>), st, groups, sc_group, w2,
                        paths);
     hipLaunchKernelGGL(k_batch_mop_kbest, dim3(n_sc_total), dim3(kT), sizeof(MopSmem), st, groups, sc_group, w2,
                        paths);
@@ -598,14 +610,14 @@ int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t
     if (n_sc == 0) return VP_OK;
     static const int attr_once = (
         hipFuncSetAttribute((const void *)k_mop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(MopSmem)),
-        hipFuncSetAttribute((const void *)k_mop_thr<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sizeof(ThrSmem<1024>)),
+        hipFuncSetAttribute((const void *)k_mop_thr<kCap512>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sizeof(ThrSmem<kCap512>)),
         hipFuncSetAttribute((const void *)k_mop_thr<2048>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)sizeof(ThrSmem<2048>)),
         0);
     (void)attr_once;
     if (K <= 512)
-        hipLaunchKernelGGL(k_mop_thr<1024>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<1024>), st, w2, N, K, paths,
+        hipLaunchKernelGGL(k_mop_thr<kCap512>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<kCap512>), st, w2, N, K, paths,
                            order);
     else
         hipLaunchKernelGGL(k_mop_thr<2048>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<2048>), st, w2, N, K, paths,
