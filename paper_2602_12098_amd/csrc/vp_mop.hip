@@ -335,6 +335,79 @@ __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *b
 
 constexpr int kNB = 512;   // grid points of the counting recursion
 
+// An upper bound on the K-th smallest M: for per-level rank limits a_i the
+// box {r : r_i <= a_i} holds prod (a_i + 1) position vectors, each with
+// M <= sum a_i w_i.  The limits are raised greedily, each time at the level
+// with the smallest cost per gained log-count, w_i / ln((a_i + 2) / (a_i + 1)),
+// until the box holds K vectors (K <= 9^N).  0 for K = 1.  Run by the whole
+// of wave 0, lane i holding level i: each step is a 16-lane argmin by DPP
+// moves (xor 1, xor 2, half-row mirror, row mirror).
+__device__ __forceinline__ float dpp_f(float x, int ctrl_sel) {
+    const int v = __float_as_int(x);
+    int r;
+    switch (ctrl_sel) {
+        case 0: r = __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false); break;    // quad_perm [1,0,3,2]
+        case 1: r = __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false); break;    // quad_perm [2,3,0,1]
+        case 2: r = __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false); break;   // row_half_mirror
+        default: r = __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false); break; // row_mirror
+    }
+    return __int_as_float(r);
+}
+
+__device__ __forceinline__ int dpp_i(int v, int ctrl_sel) {
+    switch (ctrl_sel) {
+        case 0: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);
+        case 1: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);
+        case 2: return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);
+        default: return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);
+    }
+}
+
+constexpr int kRankMax = 8;   // ranks 0..8 per level (the 3 x 3 box)
+
+// Wave 0 only (all 64 lanes active); returns the bound in every lane.
+__device__ double product_set_bound(const double *w, int N, int K) {
+    const int lane = threadIdx.x & 63;
+    const bool mine = lane < N;
+    const double wl = mine ? w[lane] : 0.0;
+    int a = 0;   // this level's limit
+    // 1 / ln((a + 2) / (a + 1)) for a = 0..7
+    auto inv_gain = [](int a) {
+        const float g[kRankMax] = {1.4426950f, 2.4663035f, 3.4760595f, 4.4814201f,
+                                   5.4848149f, 6.4871592f, 7.4888757f, 8.4901870f};
+        float v = g[0];
+#pragma unroll
+        for (int q = 1; q < kRankMax; ++q) v = a == q ? g[q] : v;
+        return v;
+    };
+    const float kInf = __int_as_float(0x7f800000);
+    float c = mine ? (float)wl * inv_gain(0) : kInf;
+    long long count = 1;
+    double U = 0.0;
+    while (count < (long long)K) {
+        float m = c;
+        int mi = lane;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {   // (cost, level) minimum over the 16 lanes of each row
+            const float om = dpp_f(m, s);
+            const int oi = dpp_i(mi, s);
+            const bool take = (om < m) | ((om == m) & (oi < mi));
+            m = take ? om : m;
+            mi = take ? oi : mi;
+        }
+        const int best = __builtin_amdgcn_readfirstlane(mi);
+        if (!(__int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(m))) < kInf)) break;
+        const int ab = __builtin_amdgcn_readlane(a, best);
+        count = count / (ab + 1) * (ab + 2);
+        U += w[best];
+        if (lane == best) {
+            ++a;
+            c = a < kRankMax ? (float)wl * inv_gain(a) : kInf;
+        }
+    }
+    return U;
+}
+
 template <int CAP>
 struct ThrSmem {
     // fm and fw, adjacent, first hold the counting recursion's two buffers
@@ -347,6 +420,7 @@ struct ThrSmem {
     int dtab[kMaxN][9];           // bin shifts of the counting recursion
     uint32_t scan[kT / 64];
     int best;
+    double ubound;
 
     __device__ uint32_t *count_buffers() {
         static_assert(2 * CAP * sizeof(double) >= 4 * kNB * sizeof(uint32_t), "fm and fw hold the counting buffers");
@@ -371,10 +445,8 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     if (t < N) S.w[t] = (double)w2[t];
     __syncthreads();
     bool valid = true;
-    double wsum = 0.0;
     for (int i = 0; i < N; ++i) {
         valid &= (S.w[i] > 0.0) && isfinite(S.w[i]);
-        wsum += S.w[i];
     }
     if (!valid) {   // failed preprocessing: a deterministic all-zero table
         for (int idx = t; idx < K * N; idx += kT) out[idx] = 0;
@@ -382,14 +454,25 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             for (int k = t; k < 2 * K; k += kT) order[k] = (uint16_t)(k % K);
         return;
     }
-    // (1) threshold on a coarse grid over the whole range, then a finer one
-    const double h0 = 8.0 * wsum / (double)(kNB - 1);
-    const int b0 = dp_threshold<kNB>(S.w, N, K, h0, S.count_buffers(), &S.best, S.dtab);
-    double T = (b0 < 0 ? (double)(kNB - 1) : (double)b0) * h0;
-    if (b0 > 0) {
-        const double h1 = 1.25 * T / (double)(kNB - 1);
-        const int b1 = dp_threshold<kNB>(S.w, N, K, h1, S.count_buffers(), &S.best, S.dtab);
-        if (b1 >= 0) T = (double)b1 * h1;
+    // (1) threshold: the smallest grid point whose count reaches K.  U bounds
+    // the K-th smallest M from above; the grid first spans [0, 0.625 U] (the
+    // K-th smallest is typically U / 2.5), and the guaranteed [0, 1.25 U] only
+    // when that one never reaches K.
+    if (t < 64) {
+        const double U0 = product_set_bound(S.w, N, K);
+        if (t == 0) S.ubound = U0;
+    }
+    __syncthreads();
+    const double U = S.ubound;
+    double T = 0.0;   // K = 1: the zero path alone
+    if (U > 0.0) {
+        double h = 0.625 * U / (double)(kNB - 1);
+        int b = dp_threshold<kNB>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
+        if (b < 0) {
+            h = 1.25 * U / (double)(kNB - 1);
+            b = dp_threshold<kNB>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
+        }
+        T = (b < 0 ? (double)(kNB - 1) : (double)b) * h;
     }
     // (2) enumerate S(T) level by level, in place: every thread first takes its
     // contiguous share of the frontier into registers, then writes the children
