@@ -16,6 +16,22 @@ namespace {
 
 constexpr int kT = 256;
 
+// Value of the partner lane within a row of 16 lanes, for the four steps of a
+// row reduction: xor 1, xor 2 (quad permutations), then the half-row and the
+// row mirror (each pairs the two halves reduced so far).
+__device__ __forceinline__ int row_xchg_i(int v, int step) {
+    switch (step) {
+        case 0: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+        case 1: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+        case 2: return __builtin_amdgcn_update_dpp(v, v, 0x141, 0xF, 0xF, false);   // row_half_mirror
+        default: return __builtin_amdgcn_update_dpp(v, v, 0x140, 0xF, 0xF, false);  // row_mirror
+    }
+}
+
+__device__ __forceinline__ float row_xchg_f(float v, int step) {
+    return __int_as_float(row_xchg_i(__float_as_int(v), step));
+}
+
 // Column c of W = Lbar^{-1}: W_rc = (delta_rc - sum_{c<=k<r} Lbar_rk W_kc) / Lbar_rr,
 // row r of Lbar being user perm[r]'s factor row Lc[perm[r]][.].
 template <int NN>
@@ -53,7 +69,7 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     __shared__ float2 Ai[kMaxN][kMaxN + 1];   // A^{-1}, user indices
     __shared__ int sperm[kMaxN];
     __shared__ int srem[kMaxN];               // 1 while user not yet pivoted
-    __shared__ float spiv;
+    __shared__ float spiv, sinv;              // L_pp and 1 / L_pp of the current step
     __shared__ int sstatus;
 
     const int t = threadIdx.x;
@@ -90,17 +106,22 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     for (int u = 0; u < N; ++u) floor_ = fmaxf(floor_, S[u][u].x);
     floor_ *= (float)N * 1.1920929e-7f;
 
+    // Two barriers per pivot step: wave 0 picks the pivot, then every thread
+    // scales the entries of column p it needs (column p is only read in step
+    // p: the update touches remaining users only).
     for (int step = 0; step < N; ++step) {
         if (t < 64) {   // wave 0: smallest remaining Schur diagonal, ties to the smaller user
             const bool cand = (t < N) && srem[t];
             float d = cand ? S[t][t].x : 0.f;
             int u = cand ? t : 0x7fffffff;
-            // order by (value, user); a NaN diagonal (only from non-finite input,
-            // which fails the subcarrier anyway) never beats a number
+            // order by (value, user) over the 16 lanes of each row (N <= 16:
+            // row 0 holds every candidate); a NaN diagonal (only from
+            // non-finite or overflowing input, which fails the subcarrier)
+            // never beats a number
 #pragma unroll
-            for (int off = 1; off < 64; off <<= 1) {
-                const float od = __shfl_xor(d, off);
-                const int ou = __shfl_xor(u, off);
+            for (int s = 0; s < 4; ++s) {
+                const float od = row_xchg_f(d, s);
+                const int ou = row_xchg_i(u, s);
                 const bool ovalid = ou != 0x7fffffff, valid = u != 0x7fffffff;
                 const bool take = ovalid & ((!valid) | (od < d) | ((od == d) & (ou < u)));
                 d = take ? od : d;
@@ -110,23 +131,25 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
                 if (!(d > floor_) && sstatus == VP_STATUS_OK) sstatus = VP_STATUS_NOT_PD;
                 sperm[step] = u;
                 srem[u] = 0;
-                spiv = sqrtf(fmaxf(d, 0.f));
+                const float lpp = sqrtf(fmaxf(d, 0.f));
+                spiv = lpp;
+                sinv = lpp > 0.f ? 1.0f / lpp : 0.f;
             }
         }
         __syncthreads();
         const int p = sperm[step];
-        const float lpp = spiv;
+        const float lpp = spiv, inv = sinv;   // L_up = S_up / L_pp
         if (t < N) {
             if (t == p) {
                 Lc[t][step] = make_float2(lpp, 0.f);
             } else if (srem[t]) {
                 const float2 a = S[t][p];
-                Lc[t][step] = lpp > 0.f ? make_float2(a.x / lpp, a.y / lpp) : make_float2(0.f, 0.f);
+                Lc[t][step] = make_float2(a.x * inv, a.y * inv);
             }
         }
-        __syncthreads();
         if (i < N && j < N && srem[i] && srem[j]) {   // S_ij -= L_i conj(L_j)
-            const float2 a = Lc[i][step], b = Lc[j][step];
+            const float2 si = S[i][p], sj = S[j][p];
+            const float2 a = make_float2(si.x * inv, si.y * inv), b = make_float2(sj.x * inv, sj.y * inv);
             float2 v = S[i][j];
             v.x = fmaf(-a.x, b.x, fmaf(-a.y, b.y, v.x));
             v.y = fmaf(-a.y, b.x, fmaf(a.x, b.y, v.y));
