@@ -1,8 +1,11 @@
 // Per-subcarrier regularised sorted factorisation (Sec. III-A-1, Alg. 1,
 // eq:invr) and the RZF precoder G = H^H (H H^H + alpha I)^{-1} (Sec. II-A).
 //
-// One 256-thread workgroup per subcarrier; the N x N Gram matrix lives in LDS
-// with one thread per entry.  Alg. 1's sorted Gram-Schmidt on the rows of
+// One wave (a 64-thread workgroup) per subcarrier, so that no step needs a
+// workgroup barrier: the N x N Gram matrix lives in LDS, each lane updating
+// up to four entries, and the channel rows are staged in dynamically sized
+// LDS (N x M), which keeps a workgroup at about 9 KiB for 16 x 16 and lets a
+// CU hold all its subcarriers at once.  Alg. 1's sorted Gram-Schmidt on the rows of
 // [H, lambda I] is carried out in its equivalent Cholesky form: the squared
 // row norms that Alg. 1 downdates are exactly the Schur-complement diagonals
 // of A = H H^H + lambda^2 I, so the pivot is the smallest remaining one and the
@@ -14,7 +17,8 @@
 namespace vp {
 namespace {
 
-constexpr int kT = 256;
+constexpr int kT = 64;                          // one wave per subcarrier
+constexpr int kPer = kMaxN * kMaxN / kT;        // Gram entries per lane
 
 // Value of the partner lane within a row of 16 lanes, for the four steps of a
 // row reduction: xor 1, xor 2 (quad permutations), then the half-row and the
@@ -58,47 +62,55 @@ __device__ __forceinline__ void forward_column(int c, const int *sperm, const fl
 }
 
 // One subcarrier: Hs its [N][M] channel; Wsc, w2sc, permsc, Gsc (or NULL),
-// status_sc its outputs.
-__device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha, float2 *__restrict__ Wsc,
-                               float *__restrict__ w2sc, uint8_t *__restrict__ permsc, float2 *__restrict__ Gsc,
-                               int32_t *__restrict__ status_sc) {
-    __shared__ float2 sH[kMaxN * kMaxM];
-    __shared__ float2 S[kMaxN][kMaxN + 1];    // Schur complement, user indices
+// status_sc its outputs; sH: LDS for N * M channel entries.
+__device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha,
+                                               float2 *__restrict__ Wsc, float *__restrict__ w2sc,
+                                               uint8_t *__restrict__ permsc, float2 *__restrict__ Gsc,
+                                               int32_t *__restrict__ status_sc, float2 *sH) {
+    __shared__ float2 S[kMaxN][kMaxN + 1];    // Schur complement, user indices; later A^{-1}
     __shared__ float2 Lc[kMaxN][kMaxN + 1];   // Lc[u][k]: user u's entry of factor column k
     __shared__ float2 Wl[kMaxN][kMaxN + 1];   // W = Lbar^{-1}, search order
-    __shared__ float2 Ai[kMaxN][kMaxN + 1];   // A^{-1}, user indices
     __shared__ int sperm[kMaxN];
-    __shared__ int srem[kMaxN];               // 1 while user not yet pivoted
-    __shared__ float spiv, sinv;              // L_pp and 1 / L_pp of the current step
-    __shared__ int sstatus;
 
     const int t = threadIdx.x;
     const int NM = N * M;
+    const int NN = N * N;
 
     int bad = 0;
     for (int idx = t; idx < NM; idx += kT) {
-        float2 h = Hs[idx];
+        const float2 h = Hs[idx];
         sH[idx] = h;
         bad |= !(isfinite(h.x) && isfinite(h.y));
     }
-    bad = __syncthreads_or(bad);
-    if (t == 0) sstatus = bad ? VP_STATUS_NONFINITE : VP_STATUS_OK;
+    int st = __any(bad) ? VP_STATUS_NONFINITE : VP_STATUS_OK;   // the same in every lane
+    __syncthreads();
 
-    const int i = t >> 4, j = t & 15;
-    if (i < N && j < N) {
-        float re = 0.f, im = 0.f;
-        for (int k = 0; k < M; ++k) {   // A_ij = sum_k H_ik conj(H_jk)
-            const float2 a = sH[i * M + k], b = sH[j * M + k];
-            re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
-            im = fmaf(a.y, b.x, fmaf(-a.x, b.y, im));
-        }
-        if (i == j) {
-            re += alpha;
-            im = 0.f;
-        }
-        S[i][j] = make_float2(re, im);
+    // this lane's Gram entries e = t + q kT, (i, j) = (e / N, e % N)
+    int ei[kPer], ej[kPer];
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int e = t + q * kT;
+        ei[q] = e < NN ? e / N : kMaxN;
+        ej[q] = e < NN ? e % N : 0;
     }
-    if (t < N) srem[t] = 1;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = ei[q], j = ej[q];
+        if (i < N) {
+            float re = 0.f, im = 0.f;
+#pragma unroll 8
+            for (int k = 0; k < M; ++k) {   // A_ij = sum_k H_ik conj(H_jk)
+                const float2 a = sH[i * M + k], b = sH[j * M + k];
+                re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
+                im = fmaf(a.y, b.x, fmaf(-a.x, b.y, im));
+            }
+            if (i == j) {
+                re += alpha;
+                im = 0.f;
+            }
+            S[i][j] = make_float2(re, im);
+        }
+    }
     __syncthreads();
 
     // Pivot floor: N * eps32 * max_u A_uu.
@@ -106,59 +118,61 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     for (int u = 0; u < N; ++u) floor_ = fmaxf(floor_, S[u][u].x);
     floor_ *= (float)N * 1.1920929e-7f;
 
-    // Two barriers per pivot step: wave 0 picks the pivot, then every thread
-    // scales the entries of column p it needs (column p is only read in step
-    // p: the update touches remaining users only).
+    // Column p of S is only read during step p: the update touches remaining
+    // users only.  The workgroup is one wave, so the barrier that ends a step
+    // costs only the wait for its LDS writes.
+    uint32_t rem = (N >= 32) ? ~0u : (1u << N) - 1u;   // users not yet pivoted (the same in every lane)
     for (int step = 0; step < N; ++step) {
-        if (t < 64) {   // wave 0: smallest remaining Schur diagonal, ties to the smaller user
-            const bool cand = (t < N) && srem[t];
-            float d = cand ? S[t][t].x : 0.f;
-            int u = cand ? t : 0x7fffffff;
-            // order by (value, user) over the 16 lanes of each row (N <= 16:
-            // row 0 holds every candidate); a NaN diagonal (only from
-            // non-finite or overflowing input, which fails the subcarrier)
-            // never beats a number
+        // smallest remaining Schur diagonal, ties to the smaller user, over the
+        // 16 lanes of row 0 (N <= 16); a NaN diagonal (only from non-finite or
+        // overflowing input, which fails the subcarrier) never beats a number
+        const bool cand = (t < N) && ((rem >> t) & 1u);
+        float d = cand ? S[t][t].x : 0.f;
+        int u = cand ? t : 0x7fffffff;
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const float od = row_xchg_f(d, s);
-                const int ou = row_xchg_i(u, s);
-                const bool ovalid = ou != 0x7fffffff, valid = u != 0x7fffffff;
-                const bool take = ovalid & ((!valid) | (od < d) | ((od == d) & (ou < u)));
-                d = take ? od : d;
-                u = take ? ou : u;
-            }
-            if (t == 0) {
-                if (!(d > floor_) && sstatus == VP_STATUS_OK) sstatus = VP_STATUS_NOT_PD;
-                sperm[step] = u;
-                srem[u] = 0;
-                const float lpp = sqrtf(fmaxf(d, 0.f));
-                spiv = lpp;
-                sinv = lpp > 0.f ? 1.0f / lpp : 0.f;
-            }
+        for (int s = 0; s < 4; ++s) {
+            const float od = row_xchg_f(d, s);
+            const int ou = row_xchg_i(u, s);
+            const bool ovalid = ou != 0x7fffffff, valid = u != 0x7fffffff;
+            const bool take = ovalid & ((!valid) | (od < d) | ((od == d) & (ou < u)));
+            d = take ? od : d;
+            u = take ? ou : u;
         }
-        __syncthreads();
-        const int p = sperm[step];
-        const float lpp = spiv, inv = sinv;   // L_up = S_up / L_pp
+        const int p = __builtin_amdgcn_readfirstlane(u);
+        d = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(d)));
+        if (!(d > floor_) && st == VP_STATUS_OK) st = VP_STATUS_NOT_PD;
+        if (t == 0) sperm[step] = p;
+        rem &= ~(1u << p);
+        const float lpp = sqrtf(fmaxf(d, 0.f));
+        const float inv = lpp > 0.f ? 1.0f / lpp : 0.f;   // L_up = S_up / L_pp
+        // every read of the step first (rows beyond N read row 0: discarded),
+        // so that they overlap, then the arithmetic, then the writes
+        const int tr = t < N ? t : 0;
+        const float2 st_ = S[tr][p];
+        float2 si[kPer], sj[kPer], sv[kPer];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int i = ei[q] < N ? ei[q] : 0, j = ej[q];
+            si[q] = S[i][p];
+            sj[q] = S[j][p];
+            sv[q] = S[i][j];
+        }
         if (t < N) {
-            if (t == p) {
-                Lc[t][step] = make_float2(lpp, 0.f);
-            } else if (srem[t]) {
-                const float2 a = S[t][p];
-                Lc[t][step] = make_float2(a.x * inv, a.y * inv);
-            }
+            if (t == p) Lc[t][step] = make_float2(lpp, 0.f);
+            else if ((rem >> t) & 1u) Lc[t][step] = make_float2(st_.x * inv, st_.y * inv);
         }
-        if (i < N && j < N && srem[i] && srem[j]) {   // S_ij -= L_i conj(L_j)
-            const float2 si = S[i][p], sj = S[j][p];
-            const float2 a = make_float2(si.x * inv, si.y * inv), b = make_float2(sj.x * inv, sj.y * inv);
-            float2 v = S[i][j];
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {   // S_ij -= L_i conj(L_j)
+            const int i = ei[q], j = ej[q];
+            const float2 a = make_float2(si[q].x * inv, si[q].y * inv), b = make_float2(sj[q].x * inv, sj[q].y * inv);
+            float2 v = sv[q];
             v.x = fmaf(-a.x, b.x, fmaf(-a.y, b.y, v.x));
             v.y = fmaf(-a.y, b.x, fmaf(a.x, b.y, v.y));
-            S[i][j] = v;
+            if (i < N && ((rem >> i) & 1u) && ((rem >> j) & 1u)) S[i][j] = v;
         }
         __syncthreads();
     }
 
-    const int st = sstatus;
     const int NP = VP_PACKED(N);
     if (st != VP_STATUS_OK) {
         const float qnan = __int_as_float(0x7fc00000);
@@ -173,7 +187,7 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         return;
     }
 
-    // W = Lbar^{-1}: thread c solves Lbar x = e_c by forward substitution,
+    // W = Lbar^{-1}: lane c solves Lbar x = e_c by forward substitution,
     // its column held in registers.
     if (t < N) {
         switch (N) {
@@ -187,40 +201,46 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     }
     __syncthreads();
 
-    // A^{-1} = P^T W^H W P:  (W^H W)_kl = sum_{r >= max(k,l)} conj(W_rk) W_rl
-    if (i < N && j < N) {
-        float re = 0.f, im = 0.f;
-        for (int r = (i > j ? i : j); r < N; ++r) {
-            const float2 a = Wl[r][i], b = Wl[r][j];
-            re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
-            im = fmaf(a.x, b.y, fmaf(-a.y, b.x, im));
+    // A^{-1} = P^T W^H W P:  (W^H W)_kl = sum_{r >= max(k,l)} conj(W_rk) W_rl, into S
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+        const int i = ei[q], j = ej[q];
+        if (i < N) {
+            float re = 0.f, im = 0.f;
+#pragma unroll 4
+            for (int r = (i > j ? i : j); r < N; ++r) {
+                const float2 a = Wl[r][i], b = Wl[r][j];
+                re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
+                im = fmaf(a.x, b.y, fmaf(-a.y, b.x, im));
+            }
+            S[sperm[i]][sperm[j]] = make_float2(re, im);
         }
-        Ai[sperm[i]][sperm[j]] = make_float2(re, im);
     }
     __syncthreads();
 
     for (int idx = t; idx < NP; idx += kT) {   // packed column-major lower
-        int c = 0, rem = idx;
-        while (rem >= N - c) {
-            rem -= N - c;
+        int c = 0, rem_ = idx;
+        while (rem_ >= N - c) {
+            rem_ -= N - c;
             ++c;
         }
-        const int r = c + rem;
+        const int r = c + rem_;
         float2 v = Wl[r][c];
         if (r == c) v.y = 0.f;
         Wsc[idx] = v;
     }
     if (t < N) {
-        const float d = Wl[t][t].x;
-        w2sc[t] = d * d;
+        const float dg = Wl[t][t].x;
+        w2sc[t] = dg * dg;
         permsc[t] = (uint8_t)sperm[t];
     }
     if (Gsc) {   // G[m][u] = sum_v conj(H_vm) Ainv_vu
         for (int idx = t; idx < NM; idx += kT) {
             const int m = idx / N, u = idx % N;
             float re = 0.f, im = 0.f;
+#pragma unroll 8
             for (int v = 0; v < N; ++v) {
-                const float2 h = sH[v * M + m], a = Ai[v][u];
+                const float2 h = sH[v * M + m], a = S[v][u];
                 re = fmaf(h.x, a.x, fmaf(h.y, a.y, re));
                 im = fmaf(h.x, a.y, fmaf(-h.y, a.x, im));
             }
@@ -234,24 +254,26 @@ __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H,
                                                    float2 *__restrict__ Wout, float *__restrict__ w2out,
                                                    uint8_t *__restrict__ perm_out, float2 *__restrict__ Gout,
                                                    int32_t *__restrict__ status_out) {
+    extern __shared__ float2 sH[];   // [N * M]
     const size_t sc = blockIdx.x;
     const size_t NM = (size_t)N * M;
     preprocess_one(H + sc * NM, N, M, alpha, Wout + sc * VP_PACKED(N), w2out + sc * N, perm_out + sc * N,
-                   Gout ? Gout + sc * NM : nullptr, status_out + sc);
+                   Gout ? Gout + sc * NM : nullptr, status_out + sc, sH);
 }
 
-// Batched: one workgroup per subcarrier of any group.
+// Batched: one wave per subcarrier of any group.
 __global__ __launch_bounds__(kT) void k_batch_preprocess(const BatchGroup *__restrict__ groups,
                                                          const int32_t *__restrict__ sc_group, int M,
                                                          const float2 *__restrict__ H, float2 *__restrict__ W,
                                                          float *__restrict__ w2, uint8_t *__restrict__ perm,
                                                          float2 *__restrict__ G, int32_t *__restrict__ status) {
+    extern __shared__ float2 sH[];   // [kMaxN * M]
     const int sc = blockIdx.x;
     const BatchGroup g = groups[sc_group[sc]];
     const long long j = sc - g.sc0;
     const long long UM = (long long)g.U * M;
     preprocess_one(H + g.offH + j * UM, g.U, M, g.alpha, W + g.offW + j * VP_PACKED(g.U), w2 + g.offN + j * g.U,
-                   perm + g.offN + j * g.U, G + g.offG + j * UM, status + sc);
+                   perm + g.offN + j * g.U, G + g.offG + j * UM, status + sc, sH);
 }
 
 }  // namespace
@@ -260,15 +282,16 @@ int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, i
                             const float2 *H, float2 *W, float *w2, uint8_t *perm, float2 *G, int32_t *status,
                             hipStream_t st) {
     if (n_sc_total == 0) return VP_OK;
-    hipLaunchKernelGGL(k_batch_preprocess, dim3(n_sc_total), dim3(kT), 0, st, groups, sc_group, M, H, W, w2, perm, G,
-                       status);
+    hipLaunchKernelGGL(k_batch_preprocess, dim3(n_sc_total), dim3(kT), (size_t)kMaxN * M * sizeof(float2), st, groups,
+                       sc_group, M, H, W, w2, perm, G, status);
     return launch_status();
 }
 
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
                       uint8_t *perm, float2 *G, int32_t *status, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
-    hipLaunchKernelGGL(k_preprocess, dim3(n_sc), dim3(kT), 0, st, H, N, M, alpha, W, w2, perm, G, status);
+    hipLaunchKernelGGL(k_preprocess, dim3(n_sc), dim3(kT), (size_t)N * M * sizeof(float2), st, H, N, M, alpha, W, w2,
+                       perm, G, status);
     return launch_status();
 }
 
