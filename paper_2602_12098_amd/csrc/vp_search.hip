@@ -111,6 +111,7 @@ constexpr int prefix_levels() { return N >= 4 ? N / 4 : 1; }
 
 constexpr int kVPB = 2;                 // vectors of one subcarrier per workgroup (they share its table)
 constexpr int kTB = kTT * kVPB;         // threads of the prefix-sharing search
+static_assert(kVPB == 2 && 2 * kMaxPrefix <= kTB, "stage 1 packs both vectors' prefixes over the workgroup");
 
 template <int N>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
@@ -207,15 +208,19 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const float tau2 = tau * tau;
     unsigned long long best = ~0ull;
     float *state = s_state[h];
+    const int nlive = min(kVPB, n_sym - (int)(blk % slots) * kVPB);   // live vectors of this workgroup
     for (uint32_t base = 0; base < n1; base += kMaxPrefix) {
         const uint32_t nc = min(n1 - base, (uint32_t)kMaxPrefix);
-        if (live && tl < (int)nc) {   // stage 1: one lane per distinct prefix
+        // stage 1: one lane per (vector, distinct prefix), the vectors' prefixes
+        // packed one after the other over the workgroup (2 nc <= kTB)
+        const int hh = t >= (int)nc ? 1 : 0, pp = t - hh * (int)nc;
+        if (hh < nlive && pp < (int)nc) {
             float2 r[N];
 #pragma unroll
-            for (int i = 0; i < N; ++i) r[i] = s_r0[h][i];
-            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_k[s_first[base + tl]]],
+            for (int i = 0; i < N; ++i) r[i] = s_r0[hh][i];
+            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_k[s_first[base + pp]]],
                                                            VP_DEMAP_LUT, nullptr, nullptr);
-            float *st = state + tl * SW;
+            float *st = s_state[hh] + pp * SW;
 #pragma unroll
             for (int i = P1; i < N; ++i) {
                 st[2 * (i - P1)] = r[i].x;
