@@ -541,7 +541,10 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         return;
     }
     // (3) bucket sort by M over [0, T], then exact (M, lexicographic r) inside buckets
-    const double scale = T > 0.0 ? (double)kNB / T : 0.0;
+    // bucket of M: kNB (M / T)^4, monotone in M.  The members of S(T) grow
+    // steeply towards T (|S(x)| rises like a power of x), and the fourth power
+    // spreads them nearly evenly, which keeps every bucket's insertion sort short.
+    const double invT = T > 0.0 ? 1.0 / T : 0.0;
     for (int b = t; b < kNB; b += kT) S.dp[0][b] = 0u;
     double m[PER];
     unsigned long long lex[PER];
@@ -555,7 +558,8 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             m[q] = S.fm[j];
             const unsigned long long wd = S.fw[j];
             lex[q] = nibble_reverse(wd, N);   // level 0 in the most significant nibble
-            bk[q] = min(kNB - 1, (int)(m[q] * scale));
+            const double x = m[q] * invT, x2 = x * x;
+            bk[q] = min(kNB - 1, (int)(x2 * x2 * (double)kNB));
         }
     }
     __syncthreads();
