@@ -70,12 +70,74 @@ __device__ void block_bitonic_sort(unsigned long long *key, uint16_t *val, int n
 // Writes order[1]: the path indices sorted with the deepest level most
 // significant.  word(k) must return path k's rank nibbles (level i at bits 4i),
 // which is exactly that key.  key/val are LDS scratch of >= pow2(K) entries.
+// Compare-exchange with the partner element: keep the smaller (take_min) or
+// the larger of the two (key, value) pairs.
+__device__ __forceinline__ void bitonic_keep(unsigned long long &k, uint32_t &v, unsigned long long ok, uint32_t ov,
+                                             bool take_min) {
+    const bool take = take_min ? (ok < k) : (k < ok);
+    k = take ? ok : k;
+    v = take ? ov : v;
+}
+
 template <class WordFn>
 __device__ void write_suffix_order(WordFn word, int K, unsigned long long *key, uint16_t *val,
                                    uint16_t *__restrict__ out) {
     const int t = threadIdx.x;
     int n = 1;
     while (n < K) n <<= 1;
+    if (n <= 2 * kT) {
+        // Bitonic sort with elements 2t and 2t + 1 in thread t's registers:
+        // partners at distance 1 are in the same thread, at 2..64 in lane
+        // t ^ (stride / 2) of the same wave, further ones are exchanged
+        // through LDS.  Positions n..2 kT - 1 hold sentinels sorted among
+        // themselves.
+        const int e0 = 2 * t;
+        unsigned long long k0 = e0 < K ? word(e0) : ~0ull, k1 = e0 + 1 < K ? word(e0 + 1) : ~0ull;
+        uint32_t v0 = (uint32_t)e0, v1 = (uint32_t)e0 + 1;
+        for (int size = 2; size <= n; size <<= 1) {
+            for (int stride = size >> 1; stride > 0; stride >>= 1) {
+                const bool asc = (e0 & size) == 0;
+                if (stride == 1) {
+                    if (asc ? (k1 < k0) : (k0 < k1)) {
+                        const unsigned long long tk = k0;
+                        k0 = k1;
+                        k1 = tk;
+                        const uint32_t tv = v0;
+                        v0 = v1;
+                        v1 = tv;
+                    }
+                    continue;
+                }
+                const bool take_min = ((e0 & stride) == 0) == asc;   // e0 and e0 + 1 share both bits
+                unsigned long long o0, o1;
+                uint32_t w0, w1;
+                if (stride <= 64) {
+                    const int j = stride >> 1;
+                    o0 = __shfl_xor(k0, j);
+                    o1 = __shfl_xor(k1, j);
+                    w0 = __shfl_xor(v0, j);
+                    w1 = __shfl_xor(v1, j);
+                } else {
+                    key[e0] = k0;
+                    key[e0 + 1] = k1;
+                    val[e0] = (uint16_t)v0;
+                    val[e0 + 1] = (uint16_t)v1;
+                    __syncthreads();
+                    o0 = key[e0 ^ stride];
+                    o1 = key[(e0 + 1) ^ stride];
+                    w0 = val[e0 ^ stride];
+                    w1 = val[(e0 + 1) ^ stride];
+                    __syncthreads();
+                }
+                bitonic_keep(k0, v0, o0, w0, take_min);
+                bitonic_keep(k1, v1, o1, w1, take_min);
+            }
+        }
+        if (e0 < K) out[e0] = (uint16_t)v0;
+        if (e0 + 1 < K) out[e0 + 1] = (uint16_t)v1;
+        __syncthreads();
+        return;
+    }
     for (int k = t; k < n; k += kT) {
         key[k] = k < K ? word(k) : ~0ull;
         val[k] = (uint16_t)k;
