@@ -17,6 +17,22 @@ constexpr int kMaxM = 64;
 constexpr int kMaxKSearch = 4096;
 constexpr int kMaxKMop = 1024;
 
+// Inclusive scan over the 64 lanes of a wave by DPP moves: shifts by 1 and 2
+// within each row of 16 lanes, by 4 and 8 into the upper banks of a row, then
+// the last lane of row 0 (of rows 0-1) added to row 1 (to rows 2-3) and that
+// of row 2 to row 3.  Lanes without a source add 0.
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
+    const int v = (int)x;
+    int s = v;
+    s += __builtin_amdgcn_update_dpp(0, s, 0x111, 0xF, 0xF, true);   // row_shr:1
+    s += __builtin_amdgcn_update_dpp(0, s, 0x112, 0xF, 0xF, true);   // row_shr:2
+    s += __builtin_amdgcn_update_dpp(0, s, 0x114, 0xF, 0xE, true);   // row_shr:4, banks 1-3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x118, 0xF, 0xC, true);   // row_shr:8, banks 2-3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x142, 0xA, 0xF, true);   // row_bcast:15 into rows 1, 3
+    s += __builtin_amdgcn_update_dpp(0, s, 0x143, 0xC, 0xF, true);   // row_bcast:31 into rows 2, 3
+    return (uint32_t)s;
+}
+
 // Launchers, one per kernel family (defined next to their kernels).
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
                       uint8_t *perm, float2 *G, int32_t *status, hipStream_t st);

@@ -181,14 +181,9 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
         cnt += (j == 0 || ((wj ^ prev) & PMASK) != 0ull) ? 1u : 0u;
         prev = wj;
     }
-    uint32_t incl = cnt;
+    uint32_t incl = wave_scan_incl(cnt);
     {
         const int lane = t & 63, wv = t >> 6;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            const uint32_t y = __shfl_up(incl, off);
-            if (lane >= off) incl += y;
-        }
         if (lane == 63) s_scan[wv] = incl;
         __syncthreads();
         for (int q = 0; q < wv; ++q) incl += s_scan[q];

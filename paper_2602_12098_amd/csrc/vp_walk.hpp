@@ -20,12 +20,17 @@ __device__ __forceinline__ float2 stilde_over_tau(const float2 *__restrict__ Wc,
                                                   const float2 *__restrict__ s, size_t v, size_t n_vec, int i,
                                                   float inv_tau) {
     float re = 0.f, im = 0.f;
-    for (int j = 0; j <= i; ++j) {
+    // every load is issued up front (vp_pidx(N, i, j) stays inside the packed
+    // triangle for all j < N); the terms j > i are skipped
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
         const float2 w = Wc[vp_pidx(N, i, j)];
         const int u = pm[j] < N ? pm[j] : N - 1;   // a corrupt permutation must not index out of bounds
         const float2 x = s[(size_t)u * n_vec + v];
-        re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
-        im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+        if (j <= i) {
+            re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
+            im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+        }
     }
     return make_float2(re * inv_tau, im * inv_tau);
 }
