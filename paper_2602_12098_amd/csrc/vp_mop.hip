@@ -571,14 +571,15 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             break;
         }
 #pragma unroll
-        for (int q = 0; q < PER; ++q)
-#pragma unroll
-            for (int r = 0; r < 9; ++r)
-                if (r < R[q]) {
-                    S.fm[off] = m[q] + wr[r];
-                    S.fw[off] = wd[q] | ((unsigned long long)r << (4 * l));
-                    ++off;
-                }
+        for (int q = 0; q < PER; ++q) {   // children r = 0 .. R-1 (R = 0 past the frontier)
+            const double mq = m[q];
+            const unsigned long long wq = wd[q];
+            for (int r = 0; r < R[q]; ++r) {
+                S.fm[off] = mq + wl * (double)r;   // the step w_l r formed as above
+                S.fw[off] = wq | ((unsigned long long)r << (4 * l));
+                ++off;
+            }
+        }
         __syncthreads();
         n = total;
     }
