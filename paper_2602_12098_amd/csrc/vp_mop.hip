@@ -366,12 +366,15 @@ __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *b
     }
     __syncthreads();
     uint32_t *cur = b0, *nxt = b1;
+    const int lane = t & 63;
     for (int l = N - 1; l >= 0; --l) {
         const uint32_t *src = cur + NB + 2 * t;
+        // the level's nine shifts: one LDS read by lanes 0..8, then scalar copies
+        const int dl = dtab[l][lane < 9 ? lane : 0];
         uint32_t a0 = 0u, a1 = 0u;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
-            const int d = dtab[l][r];
+            const int d = __builtin_amdgcn_readlane(dl, r);
             a0 += src[-d];
             a1 += src[1 - d];
         }
