@@ -85,8 +85,11 @@ __device__ __forceinline__ void stage(uint16_t (*S)[LDK], const uint16_t *__rest
     }
 }
 
+// Four waves per SIMD: the accumulators then sit in ordinary VGPRs (114 in
+// all) instead of 144 VGPRs + 64 accumulation registers at two waves, which
+// hides more of each K step's load latency.
 template <bool TA, bool TB>
-__global__ __launch_bounds__(GT) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, long long lda,
+__global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, long long lda,
                                              const uint16_t *__restrict__ B, long long ldb, int vec_a, int vec_b,
                                              float *__restrict__ Cf, uint16_t *__restrict__ Cb, long long ldc,
                                              const float *__restrict__ bias, int relu,
