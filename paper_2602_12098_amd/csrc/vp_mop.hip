@@ -333,30 +333,28 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratc
     return base + incl - v;
 }
 
-// Smallest grid index b with count(b) >= K of the rounded-up metric, on a
-// grid of step h with NB points (-1 if none); dp is [2][NB] scratch.  The
-// rounding up makes the count a lower bound of the true count at b * h.
-// Counting recursion on a grid of NB = 2 kT bins of width h: after levels
-// l..N-1, count[b] = number of rank suffixes whose metric, with every term
-// w_i r_i rounded up to whole bins, is at most b bins (an under-count of the
-// true |S(b h)|).  Returns the smallest b with count >= K, or -1.  Each
-// thread owns two adjacent bins; the two buffers (cur, next) carry NB zero
-// bins on their left so that shifted reads need no bounds test; counts
+// Counting recursion on a grid of NB bins of width h (NB = kT or 2 kT: one
+// or two adjacent bins per thread): after levels l..N-1, count[b] = number of
+// rank suffixes whose metric, with every term w_i r_i rounded up to whole
+// bins, is at most b bins (an under-count of the true |S(b h)|).  Returns the
+// smallest b with count >= K, or -1.  The two buffers (cur, next) carry NB
+// zero bins on their left so that shifted reads need no bounds test; counts
 // saturate at 2^20 (>= K, all that is compared).  buf: 2 x 2 NB uint32 of
 // LDS; dtab: kMaxN x 9 ints of LDS.
 template <int NB>
 __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *buf, int *sbest, int (*dtab)[9]) {
-    static_assert(NB == 2 * kT, "two bins per thread");
+    constexpr int BPT = NB / kT;   // bins per thread
+    static_assert(BPT * kT == NB && (BPT == 1 || BPT == 2), "one or two bins per thread");
     constexpr uint32_t kSat = 1u << 20;
     const int t = threadIdx.x;
     const double inv_h = (1.0 + 0x1p-40) / h;   // the tiny excess keeps every term rounded up
     uint32_t *b0 = buf, *b1 = buf + 2 * NB;
-    b0[2 * t] = 0u;
-    b0[2 * t + 1] = 0u;
-    b1[2 * t] = 0u;
-    b1[2 * t + 1] = 0u;
-    b0[NB + 2 * t] = 1u;
-    b0[NB + 2 * t + 1] = 1u;
+#pragma unroll
+    for (int e = 0; e < BPT; ++e) {
+        b0[BPT * t + e] = 0u;
+        b1[BPT * t + e] = 0u;
+        b0[NB + BPT * t + e] = 1u;
+    }
     if (t == 0) *sbest = NB;
     // the shifts ceil(w_l r / h) depend only on the level: one thread each
     for (int q = t; q < N * 9; q += kT) {
@@ -368,24 +366,29 @@ __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *b
     uint32_t *cur = b0, *nxt = b1;
     const int lane = t & 63;
     for (int l = N - 1; l >= 0; --l) {
-        const uint32_t *src = cur + NB + 2 * t;
+        const uint32_t *src = cur + NB + BPT * t;
         // the level's nine shifts: one LDS read by lanes 0..8, then scalar copies
         const int dl = dtab[l][lane < 9 ? lane : 0];
-        uint32_t a0 = 0u, a1 = 0u;
+        uint32_t a[BPT];
+#pragma unroll
+        for (int e = 0; e < BPT; ++e) a[e] = 0u;
 #pragma unroll
         for (int r = 0; r < 9; ++r) {
             const int d = __builtin_amdgcn_readlane(dl, r);
-            a0 += src[-d];
-            a1 += src[1 - d];
+#pragma unroll
+            for (int e = 0; e < BPT; ++e) a[e] += src[e - d];
         }
-        nxt[NB + 2 * t] = min(a0, kSat);
-        nxt[NB + 2 * t + 1] = min(a1, kSat);
+#pragma unroll
+        for (int e = 0; e < BPT; ++e) nxt[NB + BPT * t + e] = min(a[e], kSat);
         __syncthreads();
         uint32_t *tmp = cur;
         cur = nxt;
         nxt = tmp;
     }
-    const int mine = cur[NB + 2 * t] >= (uint32_t)K ? 2 * t : (cur[NB + 2 * t + 1] >= (uint32_t)K ? 2 * t + 1 : NB);
+    int mine = NB;
+#pragma unroll
+    for (int e = BPT - 1; e >= 0; --e)
+        if (cur[NB + BPT * t + e] >= (uint32_t)K) mine = BPT * t + e;
     atomicMin(sbest, mine);
     __syncthreads();
     const int r = *sbest;
@@ -393,7 +396,8 @@ __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *b
     return r < NB ? r : -1;
 }
 
-constexpr int kNB = 512;   // grid points of the counting recursion
+constexpr int kNBCount = 256;   // grid points of the counting recursion (one per thread)
+constexpr int kNB = 512;   // buckets of the sort by metric
 
 // An upper bound on the K-th smallest M: for per-level rank limits a_i the
 // box {r : r_i <= a_i} holds prod (a_i + 1) position vectors, each with
@@ -526,13 +530,13 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     const double U = S.ubound;
     double T = 0.0;   // K = 1: the zero path alone
     if (U > 0.0) {
-        double h = 0.625 * U / (double)(kNB - 1);
-        int b = dp_threshold<kNB>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
+        double h = 0.625 * U / (double)(kNBCount - 1);
+        int b = dp_threshold<kNBCount>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
         if (b < 0) {
-            h = 1.25 * U / (double)(kNB - 1);
-            b = dp_threshold<kNB>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
+            h = 1.25 * U / (double)(kNBCount - 1);
+            b = dp_threshold<kNBCount>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
         }
-        T = (b < 0 ? (double)(kNB - 1) : (double)b) * h;
+        T = (b < 0 ? (double)(kNBCount - 1) : (double)b) * h;
     }
     // (2) enumerate S(T) level by level, in place: every thread first takes its
     // contiguous share of the frontier into registers, then writes the children
