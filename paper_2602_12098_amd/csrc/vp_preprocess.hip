@@ -93,9 +93,11 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         ei[q] = e < NN ? e / N : kMaxN;
         ej[q] = e < NN ? e % N : 0;
     }
+    float2 sv[kPer];   // this lane's entries of S, kept in registers (only this lane writes them)
 #pragma unroll
     for (int q = 0; q < kPer; ++q) {
         const int i = ei[q], j = ej[q];
+        sv[q] = make_float2(0.f, 0.f);
         if (i < N) {
             float re = 0.f, im = 0.f;
 #pragma unroll 8
@@ -108,10 +110,12 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
                 re += alpha;
                 im = 0.f;
             }
-            S[i][j] = make_float2(re, im);
+            sv[q] = make_float2(re, im);
+            S[i][j] = sv[q];
         }
     }
     __syncthreads();
+    const bool same_j = (kT % N) == 0;   // then all of a lane's entries share their column j
 
     // Pivot floor: N * eps32 * max_u A_uu.
     float floor_ = 0.f;
@@ -149,13 +153,16 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         // so that they overlap, then the arithmetic, then the writes
         const int tr = t < N ? t : 0;
         const float2 st_ = S[tr][p];
-        float2 si[kPer], sj[kPer], sv[kPer];
+        float2 si[kPer], sj[kPer];
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int i = ei[q] < N ? ei[q] : 0, j = ej[q];
-            si[q] = S[i][p];
-            sj[q] = S[j][p];
-            sv[q] = S[i][j];
+        for (int q = 0; q < kPer; ++q) si[q] = S[ei[q] < N ? ei[q] : 0][p];
+        if (same_j) {
+            const float2 x = S[ej[0]][p];
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) sj[q] = x;
+        } else {
+#pragma unroll
+            for (int q = 0; q < kPer; ++q) sj[q] = S[ej[q]][p];
         }
         if (t < N) {
             if (t == p) Lc[t][step] = make_float2(lpp, 0.f);
@@ -168,7 +175,10 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
             float2 v = sv[q];
             v.x = fmaf(-a.x, b.x, fmaf(-a.y, b.y, v.x));
             v.y = fmaf(-a.y, b.x, fmaf(a.x, b.y, v.y));
-            if (i < N && ((rem >> i) & 1u) && ((rem >> j) & 1u)) S[i][j] = v;
+            if (i < N && ((rem >> i) & 1u) && ((rem >> j) & 1u)) {
+                sv[q] = v;
+                S[i][j] = v;
+            }
         }
         __syncthreads();
     }
