@@ -234,8 +234,8 @@ def main():
                     help="run one further form alone (for profiling) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by "
-              "subcarrier with no exchange, see the design notes", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); on several GPUs each would "
+              "take a contiguous range of subcarriers, with no exchange between them", file=sys.stderr)
         sys.exit(2)
 
     import torch
