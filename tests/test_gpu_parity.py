@@ -397,14 +397,16 @@ def test_prefix_sharing_is_bit_identical(vp, N, K):
     assert torch.equal(a[2].cost, b[2].cost) and torch.equal(a[2].kidx, b[2].kidx) and torch.equal(a[2].l, b[2].l)
 
 
-@pytest.mark.parametrize("N,K,hi", [(16, 512, 9), (16, 300, 9), (8, 512, 3), (5, 200, 9), (16, 512, 2)])
-def test_trie_search_any_table_is_bit_identical(vp, N, K, hi):
+@pytest.mark.parametrize("N,K,hi,n_sym", [(16, 512, 9, 5), (16, 300, 9, 5), (8, 512, 3, 5), (5, 200, 9, 5),
+                                           (16, 512, 2, 5), (16, 512, 9, 1), (16, 512, 2, 2), (7, 64, 9, 1)])
+def test_trie_search_any_table_is_bit_identical(vp, N, K, hi, n_sym):
     # arbitrary per-subcarrier tables (random ranks, duplicates allowed) with
     # their two orders: the prefix-sharing search must equal the plain
     # per-path search bit for bit, also with many distinct prefixes (done in
-    # chunks) and with repeated paths
-    rng = np.random.default_rng(N * 1000 + K + hi)
-    n_sc, n_sym = 6, 5
+    # chunks), with repeated paths, and with one or two symbols per subcarrier
+    # (a workgroup takes two vectors of a subcarrier)
+    rng = np.random.default_rng(N * 1000 + K + hi + 17 * n_sym)
+    n_sc = 6
     H = vpgen.draw_rayleigh(rng, n_sc, N, N)
     s = vpgen.draw_symbols(rng, N, n_sc * n_sym, 64)
     tau = vpgen.qam_tau(64)
