@@ -298,13 +298,16 @@ __device__ __forceinline__ void mop_kbest_one(MopSmem &S, const float *__restric
     }
 }
 
-__global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ paths,
-                                            uint16_t *__restrict__ order, int only_marked) {
+__global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int n_sc, int N, int K,
+                                            uint8_t *__restrict__ paths, uint16_t *__restrict__ order,
+                                            int only_marked) {
     extern __shared__ unsigned char smem_raw[];
     MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
-    const int sc = blockIdx.x;
-    mop_kbest_one(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
-                  order ? order + (size_t)sc * 2 * K : nullptr, only_marked);
+    // with only_marked, a few workgroups stride over the subcarriers (most
+    // need nothing); otherwise one workgroup per subcarrier
+    for (int sc = blockIdx.x; sc < n_sc; sc += gridDim.x)
+        mop_kbest_one(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
+                      order ? order + (size_t)sc * 2 * K : nullptr, only_marked);
 }
 
 
@@ -774,13 +777,14 @@ int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t
     else
         hipLaunchKernelGGL(k_mop_thr<2048>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<2048>), st, w2, N, K, paths,
                            order);
-    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, order, 1);
+    hipLaunchKernelGGL(k_mop, dim3((unsigned)min(n_sc, 512)), dim3(kT), sizeof(MopSmem), st, w2, n_sc, N, K, paths,
+                       order, 1);
     return launch_status();
 }
 
 int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
-    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, N, K, paths, order, 0);
+    hipLaunchKernelGGL(k_mop, dim3(n_sc), dim3(kT), sizeof(MopSmem), st, w2, n_sc, N, K, paths, order, 0);
     return launch_status();
 }
 
