@@ -34,6 +34,8 @@ namespace {
 
 constexpr int kT = 256;
 
+constexpr uint8_t kRedo = 0xFF;   // first byte of a subcarrier's table: K-best must redo it
+
 struct MopSmem {
     double pm[kMaxKMop];                 // survivors: metric
     uint16_t plex[kMaxKMop];             // survivors: lexicographic rank among survivors
@@ -170,7 +172,7 @@ __device__ __forceinline__ void list_elem(const MopSmem &S, double wl, int r, in
 __device__ __forceinline__ void mop_kbest_one(MopSmem &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
                               uint16_t *__restrict__ order, int only_marked) {
     const int t = threadIdx.x;
-    if (only_marked && out[0] != 0xFF) return;
+    if (only_marked && out[0] != kRedo) return;
     __syncthreads();   // every thread has read the marker before it is overwritten
 
     if (t == 0) {
@@ -298,16 +300,39 @@ __device__ __forceinline__ void mop_kbest_one(MopSmem &S, const float *__restric
     }
 }
 
+// Collects the indices `idx` of the threads with `mark` into s_list[0..*s_cnt).
+__device__ __forceinline__ void marked_list(bool mark, int idx, int *s_list, int *s_cnt) {
+    if (threadIdx.x == 0) *s_cnt = 0;
+    __syncthreads();
+    if (mark) s_list[atomicAdd(s_cnt, 1)] = idx;
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int n_sc, int N, int K,
                                             uint8_t *__restrict__ paths, uint16_t *__restrict__ order,
                                             int only_marked) {
     extern __shared__ unsigned char smem_raw[];
     MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
-    // with only_marked, a few workgroups stride over the subcarriers (most
-    // need nothing); otherwise one workgroup per subcarrier
-    for (int sc = blockIdx.x; sc < n_sc; sc += gridDim.x)
+    if (!only_marked) {
+        const int sc = blockIdx.x;
         mop_kbest_one(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
-                      order ? order + (size_t)sc * 2 * K : nullptr, only_marked);
+                      order ? order + (size_t)sc * 2 * K : nullptr, 0);
+        return;
+    }
+    // marked tables only: each pass checks kT markers at once, then redoes
+    // the marked subcarriers one after the other
+    __shared__ int s_list[kT];
+    __shared__ int s_cnt;
+    for (int base = blockIdx.x * kT; base < n_sc; base += gridDim.x * kT) {
+        marked_list(base + threadIdx.x < n_sc && paths[(size_t)(base + threadIdx.x) * K * N] == kRedo,
+                    base + threadIdx.x, s_list, &s_cnt);
+        for (int q = 0; q < s_cnt; ++q) {
+            const int sc = s_list[q];
+            mop_kbest_one(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
+                          order ? order + (size_t)sc * 2 * K : nullptr, 1);
+        }
+        __syncthreads();   // s_list and s_cnt are rewritten by the next pass
+    }
 }
 
 
@@ -315,7 +340,6 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int n_
 // threshold + enumeration + bucket sort
 // ---------------------------------------------------------------------------
 
-constexpr uint8_t kRedo = 0xFF;   // first byte of a subcarrier's table: K-best must redo it
 
 // Exclusive scan of one value per thread across the workgroup; returns the
 // prefix and writes the total to *total.
@@ -732,14 +756,28 @@ __global__ __launch_bounds__(kT) void k_batch_mop_thr(const BatchGroup *__restri
 }
 
 __global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__restrict__ groups,
-                                                        const int32_t *__restrict__ sc_group,
+                                                        const int32_t *__restrict__ sc_group, int n_sc_total,
                                                         const float *__restrict__ w2, uint8_t *__restrict__ paths) {
     extern __shared__ unsigned char smem_raw[];
     MopSmem &S = *reinterpret_cast<MopSmem *>(smem_raw);
-    const int sc = blockIdx.x;
-    const BatchGroup g = groups[sc_group[sc]];
-    const long long j = sc - g.sc0;
-    mop_kbest_one(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr, 1);
+    __shared__ int s_list[kT];
+    __shared__ int s_cnt;
+    for (int base = blockIdx.x * kT; base < n_sc_total; base += gridDim.x * kT) {
+        const int sc = base + threadIdx.x;
+        bool mark = false;
+        if (sc < n_sc_total) {
+            const BatchGroup g = groups[sc_group[sc]];
+            mark = paths[g.offP + (sc - g.sc0) * g.K * g.U] == kRedo;
+        }
+        marked_list(mark, sc, s_list, &s_cnt);
+        for (int q = 0; q < s_cnt; ++q) {
+            const int sm = s_list[q];
+            const BatchGroup g = groups[sc_group[sm]];
+            const long long j = sm - g.sc0;
+            mop_kbest_one(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr, 1);
+        }
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -756,8 +794,8 @@ int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc
     if (n_sc_total == 0) return VP_OK;
     hipLaunchKernelGGL(k_batch_mop_thr, dim3(n_sc_total), dim3(kT), sizeof(ThrSmem<kCap512>), st, groups, sc_group, w2,
                        paths);
-    hipLaunchKernelGGL(k_batch_mop_kbest, dim3(n_sc_total), dim3(kT), sizeof(MopSmem), st, groups, sc_group, w2,
-                       paths);
+    hipLaunchKernelGGL(k_batch_mop_kbest, dim3((unsigned)((n_sc_total + kT - 1) / kT)), dim3(kT), sizeof(MopSmem), st,
+                       groups, sc_group, n_sc_total, w2, paths);
     return launch_status();
 }
 
@@ -777,8 +815,8 @@ int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t
     else
         hipLaunchKernelGGL(k_mop_thr<2048>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<2048>), st, w2, N, K, paths,
                            order);
-    hipLaunchKernelGGL(k_mop, dim3((unsigned)min(n_sc, 512)), dim3(kT), sizeof(MopSmem), st, w2, n_sc, N, K, paths,
-                       order, 1);
+    hipLaunchKernelGGL(k_mop, dim3((unsigned)((n_sc + kT - 1) / kT)), dim3(kT), sizeof(MopSmem), st, w2, n_sc, N, K,
+                       paths, order, 1);
     return launch_status();
 }
 

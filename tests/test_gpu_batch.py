@@ -14,6 +14,7 @@ import numpy as np
 import pytest
 
 import vpgen
+from oracle import vp_oracle as O
 from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W
 
 torch = pytest.importorskip("torch")
@@ -182,3 +183,30 @@ def test_batch_rejects_bad_groups(mods):
         bm.Batch([G(4, 5000, 8, 8.0, 0.04)], 16, 14)            # n_sc * n_sym > 65535
     with pytest.raises(VPError):
         bm.Batch([G(4, 1, k, 8.0, 0.04) for k in range(1, 10)], 16, 14)   # 9 distinct K
+
+
+def test_batch_kbest_fallback(mods):
+    # orthogonal users of equal gain give equal MoP weights: the threshold
+    # pass overflows its frontier and the K-best kernel redoes those tables
+    vp, bm = mods
+    wl = vpgen.cfg4(n_rbg=5, seed=21, users=[16, 9, 16, 5, 13])
+    for gi in (0, 2):
+        U = int(wl.U[gi])
+        H = np.zeros((wl.sc_per_rbg, U, wl.M), np.complex64)
+        for sc in range(wl.sc_per_rbg):
+            H[sc, :, :U] = np.eye(U, dtype=np.complex64) * (1.0 + 0.25 * sc)
+        wl.H[gi] = H
+    b = make_batch(bm, wl)
+    b.run()
+    torch.cuda.synchronize()
+    bufs = check_against_per_call(vp, b, wl, 1.0)
+    # the redone tables are the exact K smallest (MoP, lexicographic) of the oracle
+    for gi in (0, 2):
+        gb = b.group_buffers(gi, bufs)
+        w2 = host(gb["w2"])
+        P = host(gb["paths"])
+        assert np.all(w2 == w2[:, :1])   # equal weights within each subcarrier
+        for sc in (0, wl.sc_per_rbg - 1):
+            ref = O.mop_paths_kbest(w2[sc].astype(np.float64), b.groups[gi].K)
+            assert np.array_equal(P[sc].astype(np.int64), ref), (gi, sc)
+    b.close()
