@@ -33,6 +33,14 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
     return (uint32_t)s;
 }
 
+// Raises a kernel's dynamic LDS limit (once per process at the call site); a
+// failure surfaces as that kernel's launch error.
+template <class K>
+inline bool allow_dynamic_lds(K *kernel, size_t bytes) {
+    return hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes) ==
+           hipSuccess;
+}
+
 // Launchers, one per kernel family (defined next to their kernels).
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
                       uint8_t *perm, float2 *G, int32_t *status, hipStream_t st);

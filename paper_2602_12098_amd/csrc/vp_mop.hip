@@ -783,10 +783,8 @@ __global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__rest
 }  // namespace
 
 void prepare_batch_kernels() {
-    (void)hipFuncSetAttribute((const void *)k_batch_mop_thr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(ThrSmem<kCap512>));
-    (void)hipFuncSetAttribute((const void *)k_batch_mop_kbest, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              (int)sizeof(MopSmem));
+    (void)allow_dynamic_lds(k_batch_mop_thr, sizeof(ThrSmem<kCap512>));
+    (void)allow_dynamic_lds(k_batch_mop_kbest, sizeof(MopSmem));
 }
 
 int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, const float *w2,
@@ -801,14 +799,10 @@ int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc
 
 int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
-    static const int attr_once = (
-        hipFuncSetAttribute((const void *)k_mop, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(MopSmem)),
-        hipFuncSetAttribute((const void *)k_mop_thr<kCap512>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sizeof(ThrSmem<kCap512>)),
-        hipFuncSetAttribute((const void *)k_mop_thr<2048>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sizeof(ThrSmem<2048>)),
-        0);
-    (void)attr_once;
+    static const int lds_ok = (int)allow_dynamic_lds(k_mop, sizeof(MopSmem)) +
+                              (int)allow_dynamic_lds(k_mop_thr<kCap512>, sizeof(ThrSmem<kCap512>)) +
+                              (int)allow_dynamic_lds(k_mop_thr<2048>, sizeof(ThrSmem<2048>));
+    (void)lds_ok;
     if (K <= 512)
         hipLaunchKernelGGL(k_mop_thr<kCap512>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<kCap512>), st, w2, N, K, paths,
                            order);

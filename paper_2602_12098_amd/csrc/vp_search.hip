@@ -393,10 +393,8 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
     const size_t n_vec = (size_t)n_sc * n_sym;
     if (order) {
         const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(3 * K + 1) * sizeof(uint16_t);
-        static const int attr_once = (hipFuncSetAttribute((const void *)k_search_trie<N>,
-                                                          hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024),
-                                      0);
-        (void)attr_once;
+        static const bool lds_ok = allow_dynamic_lds(k_search_trie<N>, 64 * 1024);
+        (void)lds_ok;
         const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);
         hipLaunchKernelGGL(k_search_trie<N>, dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths, order, K,
                            (long long)pstride, n_sym, n_vec, flags, cost, kidx);
