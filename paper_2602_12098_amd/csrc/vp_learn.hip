@@ -341,12 +341,7 @@ constexpr int kTopPer = 4096 / kTopT;   // columns per thread
 // Block-wide exclusive prefix of x over threads (thread order); *total gets the sum.
 __device__ __forceinline__ uint32_t topk_scan(uint32_t x, uint32_t *tmp, uint32_t *total) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    uint32_t incl = x;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        const uint32_t y = __shfl_up(incl, off);
-        if (lane >= off) incl += y;
-    }
+    const uint32_t incl = wave_scan_incl(x);
     if (lane == 63) tmp[wv] = incl;
     __syncthreads();
     uint32_t base = 0, tot = 0;
