@@ -33,6 +33,36 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t x) {
     return (uint32_t)s;
 }
 
+// Reductions over the 64 lanes of a wave by the same DPP pattern (lanes
+// without a source contribute the identity); every lane gets the result.
+template <int CTRL, int ROWS, int BANKS, class T, class Op>
+__device__ __forceinline__ T dpp_combine(T x, int ident, Op op) {
+    return op(x, __builtin_bit_cast(T, __builtin_amdgcn_update_dpp(ident, __builtin_bit_cast(int, x), CTRL, ROWS,
+                                                                   BANKS, false)));
+}
+
+template <class T, class Op>
+__device__ __forceinline__ T wave_reduce(T x, T ident, Op op) {
+    const int id = __builtin_bit_cast(int, ident);
+    x = dpp_combine<0x111, 0xF, 0xF>(x, id, op);   // row_shr:1
+    x = dpp_combine<0x112, 0xF, 0xF>(x, id, op);   // row_shr:2
+    x = dpp_combine<0x114, 0xF, 0xE>(x, id, op);   // row_shr:4, banks 1-3
+    x = dpp_combine<0x118, 0xF, 0xC>(x, id, op);   // row_shr:8, banks 2-3
+    x = dpp_combine<0x142, 0xA, 0xF>(x, id, op);   // row_bcast:15 into rows 1, 3
+    x = dpp_combine<0x143, 0xC, 0xF>(x, id, op);   // row_bcast:31 into rows 2, 3
+    return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, x), 63));
+}
+
+__device__ __forceinline__ float wave_max_f(float x) {
+    return wave_reduce(x, -INFINITY, [](float a, float b) { return fmaxf(a, b); });
+}
+__device__ __forceinline__ float wave_sum_f(float x) {
+    return wave_reduce(x, 0.0f, [](float a, float b) { return a + b; });
+}
+__device__ __forceinline__ uint32_t wave_min_u(uint32_t x) {
+    return wave_reduce(x, 0xffffffffu, [](uint32_t a, uint32_t b) { return a < b ? a : b; });
+}
+
 // Raises a kernel's dynamic LDS limit (once per process at the call site); a
 // failure surfaces as that kernel's launch error.
 template <class K>

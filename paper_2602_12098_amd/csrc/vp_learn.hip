@@ -381,11 +381,8 @@ __global__ __launch_bounds__(kTopT) void k_topk64(const float *__restrict__ S, i
     // of its 64 lanes' maxima -- 64 distinct entries reach it, so it bounds the
     // 64th largest key from below (C >= 64: lanes 0..63 of wave 0 hold one each;
     // a lane of another wave without columns holds 0 and yields the bound 0)
-    uint32_t wfloor = tmax;
-    for (int off = 32; off > 0; off >>= 1) {
-        mx = fmaxf(mx, __shfl_xor(mx, off));
-        wfloor = min(wfloor, (uint32_t)__shfl_xor((int)wfloor, off));
-    }
+    mx = wave_max_f(mx);
+    const uint32_t wfloor = wave_min_u(tmax);
     if (lane == 0) {
         redf[wv] = mx;
         tmp[wv] = wfloor;
@@ -482,7 +479,7 @@ __global__ __launch_bounds__(kTopT) void k_topk64(const float *__restrict__ S, i
     for (int q = 0; q < kTopPer; ++q)
         if (q * kTopT + t < C) se += __expf(key_value(key[q]) - tmx);
     se = (tmx > -INFINITY) ? se * __expf(tmx - mx) : 0.f;
-    for (int off = 32; off > 0; off >>= 1) se += __shfl_xor(se, off);
+    se = wave_sum_f(se);
     if (lane == 0) redf[wv] = se;
     __syncthreads();
     if (wv == 0) {

@@ -90,8 +90,9 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
 
 // Prefix-sharing search (path orders from vp_paths_mop: lexicographic, and
 // deepest level most significant).
-// Stage 1: each distinct prefix of levels [0, P1) is walked once, one lane per
-// prefix, and its residuals below P1 and its PED are kept in LDS.  Stage 2:
+// Stage 1: each distinct prefix of levels [0, P1) is walked once per vector,
+// one lane per (vector, prefix), and its residuals below P1 and its PED are
+// kept in LDS.  Stage 2:
 // each path continues from its prefix's state over levels [P1, N), taken in
 // deepest-level-first order so that the lanes of a wave mostly need the same
 // DEMAP work.  A table with more than kMaxPrefix distinct prefixes is done in
@@ -114,12 +115,10 @@ constexpr int kTB = kTT * kVPB;         // threads of the prefix-sharing search
 static_assert(kVPB == 2 && 2 * kMaxPrefix <= kTB, "stage 1 packs both vectors' prefixes over the workgroup");
 
 template <int N>
-__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
-                                                     const float2 *__restrict__ s, float tau,
-                                                     const uint8_t *__restrict__ paths,
-                                                     const uint16_t *__restrict__ order, int K,
-                                                     long long pstride, int n_sym, size_t n_vec, unsigned flags,
-                                                     float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(
+    const float2 *__restrict__ W, const uint8_t *__restrict__ perm, const float2 *__restrict__ s, float tau,
+    const uint8_t *__restrict__ paths, const uint16_t *__restrict__ order, int K, long long pstride, int n_sym,
+    size_t n_vec, unsigned flags, float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
     constexpr int P1 = prefix_levels<N>();
     constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
     extern __shared__ unsigned long long s_words[];   // [K] rank nibbles of path k
