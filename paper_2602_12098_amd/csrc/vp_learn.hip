@@ -360,6 +360,8 @@ __global__ __launch_bounds__(kTopT) void k_topk64(const float *__restrict__ S, i
     __shared__ uint32_t hist[256];
     __shared__ uint32_t sel_key[64];
     __shared__ uint32_t sel_idx[64];
+    __shared__ uint32_t cand_key[kTopT];
+    __shared__ uint32_t cand_col[kTopT];
     __shared__ uint32_t tmp[kTopT / 64];
     __shared__ float redf[kTopT / 64];
     __shared__ uint32_t s_bin, s_before, s_ngt;
@@ -377,96 +379,140 @@ __global__ __launch_bounds__(kTopT) void k_topk64(const float *__restrict__ S, i
         if (c < C) tmax = max(tmax, key[q]);
         mx = fmaxf(mx, f);
     }
-    // bounds: the row maximum (for the softmax mass) and, per wave, the smallest
-    // of its 64 lanes' maxima -- 64 distinct entries reach it, so it bounds the
-    // 64th largest key from below (C >= 64: lanes 0..63 of wave 0 hold one each;
-    // a lane of another wave without columns holds 0 and yields the bound 0)
+    // bounds: the row maximum (for the softmax mass) and a lower bound of the
+    // 64th largest key: in each wave the 16 largest lane maxima are 16
+    // distinct entries, so the four waves hold 64 distinct entries at or above
+    // the smallest of the waves' 16th largest lane maxima (a lane without
+    // columns holds 0, which only weakens the bound)
     mx = wave_max_f(mx);
-    const uint32_t wfloor = wave_min_u(tmax);
+    uint32_t srt = tmax;   // bitonic sort of the wave's lane maxima, descending
+    for (int size = 2; size <= 64; size <<= 1)
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            const uint32_t o = (uint32_t)__shfl_xor((int)srt, stride);
+            const bool lower = (lane & stride) == 0, desc = (lane & size) == 0;
+            srt = (lower == desc) ? max(srt, o) : min(srt, o);
+        }
+    const uint32_t w16 = (uint32_t)__builtin_amdgcn_readlane((int)srt, 15);
     if (lane == 0) {
         redf[wv] = mx;
-        tmp[wv] = wfloor;
+        tmp[wv] = w16;
     }
     __syncthreads();
-    uint32_t floor_key = 0u;
+    uint32_t floor_key = 0xffffffffu;
 #pragma unroll
     for (int q = 0; q < kTopT / 64; ++q) {
         mx = fmaxf(mx, redf[q]);
-        floor_key = max(floor_key, tmp[q]);
+        floor_key = min(floor_key, tmp[q]);
     }
     __syncthreads();
-    // radix select over the keys >= floor_key: the key of rank 63 (descending)
-    uint32_t prefix = 0, pmask = 0;
-    int need = 64;
-    for (int shift = 24; shift >= 0; shift -= 8) {
-        hist[t] = 0u;
-        __syncthreads();
+    // candidates: the keys >= floor_key (at least 64 of them)
+    uint32_t my_c = 0;
 #pragma unroll
-        for (int q = 0; q < kTopPer; ++q)
-            if (q * kTopT + t < C && key[q] >= floor_key && (key[q] & pmask) == prefix)
-                atomicAdd(&hist[(key[q] >> shift) & 255u], 1u);
-        __syncthreads();
-        const uint32_t h = hist[255 - t];   // thread t: the t-th bin from the top
-        uint32_t tot;
-        const uint32_t before = topk_scan(h, tmp, &tot);
-        if (before < (uint32_t)need && before + h >= (uint32_t)need) {
-            s_bin = 255u - (uint32_t)t;
-            s_before = before;
-        }
-        __syncthreads();
-        prefix |= s_bin << shift;
-        pmask |= 255u << shift;
-        need -= (int)s_before;
-        __syncthreads();
-    }
-    const uint32_t T = prefix;   // the 64th largest key; take every key above it
-    // and the `need` entries equal to it of smallest column
-    if (t == 0) {
-        s_ngt = 0u;
-        s_bin = 0u;   // count of keys equal to T
-    }
-    __syncthreads();
-    uint32_t my_eq = 0;
-#pragma unroll
-    for (int q = 0; q < kTopPer; ++q) {
-        const int c = q * kTopT + t;
-        if (c < C && key[q] > T) {
-            const uint32_t pos = atomicAdd(&s_ngt, 1u);
-            if (pos < 64u) {
-                sel_key[pos] = key[q];
-                sel_idx[pos] = (uint32_t)c;
-            }
-        }
-        my_eq += (c < C && key[q] == T) ? 1u : 0u;
-    }
-    if (my_eq) atomicAdd(&s_bin, my_eq);
-    __syncthreads();
-    if (s_bin == (uint32_t)need) {   // every equal key is selected: no order needed
+    for (int q = 0; q < kTopPer; ++q) my_c += (q * kTopT + t < C && key[q] >= floor_key) ? 1u : 0u;
+    uint32_t n_cand;
+    uint32_t cpos = topk_scan(my_c, tmp, &n_cand);
+    if (n_cand <= (uint32_t)kTopT) {
+        // few candidates (the usual case): each thread ranks one of them
+        // against all others in the order (key descending, column ascending),
+        // which places the 64 best directly in order
 #pragma unroll
         for (int q = 0; q < kTopPer; ++q) {
             const int c = q * kTopT + t;
-            if (c < C && key[q] == T) {
+            if (c < C && key[q] >= floor_key) {
+                cand_key[cpos] = key[q];
+                cand_col[cpos] = (uint32_t)c;
+                ++cpos;
+            }
+        }
+        __syncthreads();
+        if (t < (int)n_cand) {
+            const uint32_t k = cand_key[t], c = cand_col[t];
+            uint32_t rank = 0;
+#pragma unroll 4
+            for (uint32_t j = 0; j < n_cand; ++j) {
+                const uint32_t kj = cand_key[j], cj = cand_col[j];
+                rank += ((kj > k) | ((kj == k) & (cj < c))) ? 1u : 0u;
+            }
+            if (rank < 64u) {
+                sel_key[rank] = k;
+                sel_idx[rank] = c;
+            }
+        }
+        __syncthreads();
+    } else {
+        // radix select over the keys >= floor_key: the key of rank 63 (descending)
+        uint32_t prefix = 0, pmask = 0;
+        int need = 64;
+        for (int shift = 24; shift >= 0; shift -= 8) {
+            hist[t] = 0u;
+            __syncthreads();
+    #pragma unroll
+            for (int q = 0; q < kTopPer; ++q)
+                if (q * kTopT + t < C && key[q] >= floor_key && (key[q] & pmask) == prefix)
+                    atomicAdd(&hist[(key[q] >> shift) & 255u], 1u);
+            __syncthreads();
+            const uint32_t h = hist[255 - t];   // thread t: the t-th bin from the top
+            uint32_t tot;
+            const uint32_t before = topk_scan(h, tmp, &tot);
+            if (before < (uint32_t)need && before + h >= (uint32_t)need) {
+                s_bin = 255u - (uint32_t)t;
+                s_before = before;
+            }
+            __syncthreads();
+            prefix |= s_bin << shift;
+            pmask |= 255u << shift;
+            need -= (int)s_before;
+            __syncthreads();
+        }
+        const uint32_t T = prefix;   // the 64th largest key; take every key above it
+        // and the `need` entries equal to it of smallest column
+        if (t == 0) {
+            s_ngt = 0u;
+            s_bin = 0u;   // count of keys equal to T
+        }
+        __syncthreads();
+        uint32_t my_eq = 0;
+    #pragma unroll
+        for (int q = 0; q < kTopPer; ++q) {
+            const int c = q * kTopT + t;
+            if (c < C && key[q] > T) {
                 const uint32_t pos = atomicAdd(&s_ngt, 1u);
                 if (pos < 64u) {
                     sel_key[pos] = key[q];
                     sel_idx[pos] = (uint32_t)c;
                 }
             }
+            my_eq += (c < C && key[q] == T) ? 1u : 0u;
         }
-    } else {   // ties at the boundary: the equal keys of smallest column, block by block
-        uint32_t eq_run = 0;
-#pragma unroll
-        for (int q = 0; q < kTopPer; ++q) {
-            const int c = q * kTopT + t;
-            const bool eq = c < C && key[q] == T;
-            uint32_t tot;
-            const uint32_t rank = topk_scan(eq ? 1u : 0u, tmp, &tot);
-            if (eq && eq_run + rank < (uint32_t)need) {
-                const uint32_t pos = (uint32_t)(64 - need) + eq_run + rank;
-                sel_key[pos] = key[q];
-                sel_idx[pos] = (uint32_t)c;
+        if (my_eq) atomicAdd(&s_bin, my_eq);
+        __syncthreads();
+        if (s_bin == (uint32_t)need) {   // every equal key is selected: no order needed
+    #pragma unroll
+            for (int q = 0; q < kTopPer; ++q) {
+                const int c = q * kTopT + t;
+                if (c < C && key[q] == T) {
+                    const uint32_t pos = atomicAdd(&s_ngt, 1u);
+                    if (pos < 64u) {
+                        sel_key[pos] = key[q];
+                        sel_idx[pos] = (uint32_t)c;
+                    }
+                }
             }
-            eq_run += tot;
+        } else {   // ties at the boundary: the equal keys of smallest column, block by block
+            uint32_t eq_run = 0;
+    #pragma unroll
+            for (int q = 0; q < kTopPer; ++q) {
+                const int c = q * kTopT + t;
+                const bool eq = c < C && key[q] == T;
+                uint32_t tot;
+                const uint32_t rank = topk_scan(eq ? 1u : 0u, tmp, &tot);
+                if (eq && eq_run + rank < (uint32_t)need) {
+                    const uint32_t pos = (uint32_t)(64 - need) + eq_run + rank;
+                    sel_key[pos] = key[q];
+                    sel_idx[pos] = (uint32_t)c;
+                }
+                eq_run += tot;
+            }
         }
     }
     // softmax denominator from the registers: per thread around its own maximum
