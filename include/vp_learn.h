@@ -111,7 +111,8 @@ int vp_gemm_bf16(int m, int n, int k, const uint16_t *A, int64_t lda, int trans_
  *
  * idx (int32 [rows][64]) lists the selected columns by decreasing score,
  * equal scores by increasing column (a total order, so the result is unique;
- * -0.0 ranks below +0.0, NaN above everything).  mass (float32 [rows], or
+ * -0.0 ranks below +0.0, a NaN with the sign bit clear above +inf and one
+ * with it set below -inf).  mass (float32 [rows], or
  * NULL) receives the softmax probability mass of the selected columns,
  * sum_sel exp(x - max) / sum_all exp(x - max).
  *

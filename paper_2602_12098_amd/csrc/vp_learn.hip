@@ -321,236 +321,188 @@ __global__ __launch_bounds__(64) void k_ranks(const float2 *__restrict__ W, cons
 }
 
 // ---------------------------------------------------------------------------
-// top-64 of each row of fp32 scores [rows][C] (C <= 4096): indices ordered by
-// (score desc, index asc), and the softmax mass of the selected 64.  One wave
-// per row: 4 radix passes of 8 bits over order-preserving keys find the 64th
-// key, then the selected entries are sorted by a wave bitonic sort.
+// top-64 of each row of fp32 scores [rows][C] (64 <= C <= 4096): columns
+// ordered by (score desc, column asc) in the IEEE total order, and the softmax
+// mass of the selected 64.  One wave per row; lane L keeps the columns
+// 256 q + 4 L + e (q < 16, e < 4) as order-preserving keys in registers
+// (absent columns: key 0, below every present one that the searches try).
+//   bound:   the 64th largest of the 128 keys made of every lane's two largest
+//            is at most the row's 64th largest key, since those are 128
+//            distinct entries; a bitwise search with wave ballots finds it
+//   select:  the keys at or above the bound (64 to 128 in the usual case) are
+//            packed as (key, ~column), so that one unsigned order is the
+//            selection order, and each is ranked against all the others
+//   others:  (short rows, more than 128 candidates, ties over many columns)
+//            the exact 64th key by a bitwise search over all keys, the keys
+//            above it and the equal keys of smallest column, ranked the same way
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t okey(float f) {   // larger float -> larger key
     const uint32_t u = __float_as_uint(f);
-    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    return u ^ ((uint32_t)((int32_t)u >> 31) | 0x80000000u);
 }
 
 __device__ __forceinline__ float key_value(uint32_t k) {   // inverse of okey
     return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
 }
 
-constexpr int kTopT = 256;              // threads per row
-constexpr int kTopPer = 4096 / kTopT;   // columns per thread
+constexpr int kTopQ = 16;          // float4 column blocks per lane
+constexpr int kTopV = 4 * kTopQ;   // keys per lane
+constexpr float kLog2e = 1.4426950408889634f;
 
-// Block-wide exclusive prefix of x over threads (thread order); *total gets the sum.
-__device__ __forceinline__ uint32_t topk_scan(uint32_t x, uint32_t *tmp, uint32_t *total) {
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
-    const uint32_t incl = wave_scan_incl(x);
-    if (lane == 63) tmp[wv] = incl;
-    __syncthreads();
-    uint32_t base = 0, tot = 0;
-#pragma unroll
-    for (int q = 0; q < kTopT / 64; ++q) {
-        base += (q < wv) ? tmp[q] : 0u;
-        tot += tmp[q];
-    }
-    __syncthreads();
-    *total = tot;
-    return base + incl - x;
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t x) {
+    return wave_reduce(x, 0u, [](uint32_t a, uint32_t b) { return a + b; });
 }
 
-__global__ __launch_bounds__(kTopT) void k_topk64(const float *__restrict__ S, int rows, int C,
-                                                  int32_t *__restrict__ idx_out, float *__restrict__ mass_out) {
-    __shared__ uint32_t hist[256];
-    __shared__ uint32_t sel_key[64];
-    __shared__ uint32_t sel_idx[64];
-    __shared__ uint32_t cand_key[kTopT];
-    __shared__ uint32_t cand_col[kTopT];
-    __shared__ uint32_t tmp[kTopT / 64];
-    __shared__ float redf[kTopT / 64];
-    __shared__ uint32_t s_bin, s_before, s_ngt;
-    const int row = blockIdx.x;
-    const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
+__device__ __forceinline__ int ballot_count(bool p) { return __popcll(__ballot(p)); }
+
+__device__ __forceinline__ uint64_t topk_pack(uint32_t key, uint32_t ncol) {
+    return ((uint64_t)key << 32) | ncol;
+}
+
+// candidate p: key and ~column in two arrays, so that the registers holding
+// the keys need not pair with a column register
+struct TopkCand {
+    uint32_t key[128];
+    uint32_t ncol[128];
+    __device__ __forceinline__ void put(uint32_t p, uint32_t k, uint32_t nc) {
+        key[p] = k;
+        ncol[p] = nc;
+    }
+    __device__ __forceinline__ uint64_t get(int p) const { return topk_pack(key[p], ncol[p]); }
+};
+
+template <bool FULL, bool VEC4>
+__global__ __launch_bounds__(64) void k_topk64(const float *__restrict__ S, int C, int32_t *__restrict__ idx_out,
+                                               float *__restrict__ mass_out) {
+    __shared__ TopkCand cand;
+    __shared__ uint32_t sel[64];
+    const int row = blockIdx.x, lane = threadIdx.x;
     const float *x = S + (size_t)row * C;
-    uint32_t key[kTopPer];
-    uint32_t tmax = 0u;
-    float mx = -INFINITY;
+    const uint32_t ncol0 = ~(uint32_t)(4 * lane);   // ~column of value 0; value i = 4 q + e is ncol0 - (256 q + e)
+    uint32_t key[kTopV];
 #pragma unroll
-    for (int q = 0; q < kTopPer; ++q) {   // column q * 256 + t
-        const int c = q * kTopT + t;
-        const float f = c < C ? x[c] : -INFINITY;
-        key[q] = c < C ? okey(f) : 0u;
-        if (c < C) tmax = max(tmax, key[q]);
-        mx = fmaxf(mx, f);
-    }
-    // bounds: the row maximum (for the softmax mass) and a lower bound of the
-    // 64th largest key: in each wave the 16 largest lane maxima are 16
-    // distinct entries, so the four waves hold 64 distinct entries at or above
-    // the smallest of the waves' 16th largest lane maxima (a lane without
-    // columns holds 0, which only weakens the bound)
-    mx = wave_max_f(mx);
-    uint32_t srt = tmax;   // bitonic sort of the wave's lane maxima, descending
-    for (int size = 2; size <= 64; size <<= 1)
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            const uint32_t o = (uint32_t)__shfl_xor((int)srt, stride);
-            const bool lower = (lane & stride) == 0, desc = (lane & size) == 0;
-            srt = (lower == desc) ? max(srt, o) : min(srt, o);
+    for (int q = 0; q < kTopQ; ++q) {
+        const int c = 256 * q + 4 * lane;
+        if (VEC4) {
+            float4 v = make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+            if (FULL || c < C) v = *reinterpret_cast<const float4 *>(x + c);
+            key[4 * q + 0] = __float_as_uint(v.x);
+            key[4 * q + 1] = __float_as_uint(v.y);
+            key[4 * q + 2] = __float_as_uint(v.z);
+            key[4 * q + 3] = __float_as_uint(v.w);
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) key[4 * q + e] = __float_as_uint((FULL || c + e < C) ? x[c + e] : -INFINITY);
         }
-    const uint32_t w16 = (uint32_t)__builtin_amdgcn_readlane((int)srt, 15);
-    if (lane == 0) {
-        redf[wv] = mx;
-        tmp[wv] = w16;
     }
-    __syncthreads();
-    uint32_t floor_key = 0xffffffffu;
+    // softmax denominator around the lane's maximum, rescaled to the row's
+    float lmx = -INFINITY;
 #pragma unroll
-    for (int q = 0; q < kTopT / 64; ++q) {
-        mx = fmaxf(mx, redf[q]);
-        floor_key = min(floor_key, tmp[q]);
+    for (int i = 0; i < kTopV; ++i) lmx = fmaxf(lmx, __uint_as_float(key[i]));
+    const float mx = wave_max_f(lmx);
+    float sall = 0.f;
+    if (mass_out) {
+        const float off = -lmx * kLog2e;
+        float se = 0.f;
+#pragma unroll
+        for (int i = 0; i < kTopV; ++i) se += __builtin_amdgcn_exp2f(fmaf(__uint_as_float(key[i]), kLog2e, off));
+        se = (lmx > -INFINITY) ? se * __builtin_amdgcn_exp2f((lmx - mx) * kLog2e) : 0.f;
+        sall = wave_sum_f(se);
     }
-    __syncthreads();
-    // candidates: the keys >= floor_key (at least 64 of them)
-    uint32_t my_c = 0;
+    // keys, and every lane's two largest
+    uint32_t m1 = 0, m2 = 0;
 #pragma unroll
-    for (int q = 0; q < kTopPer; ++q) my_c += (q * kTopT + t < C && key[q] >= floor_key) ? 1u : 0u;
-    uint32_t n_cand;
-    uint32_t cpos = topk_scan(my_c, tmp, &n_cand);
-    if (n_cand <= (uint32_t)kTopT) {
-        // few candidates (the usual case): each thread ranks one of them
-        // against all others in the order (key descending, column ascending),
-        // which places the 64 best directly in order
+    for (int i = 0; i < kTopV; ++i) {
+        uint32_t k = okey(__uint_as_float(key[i]));
+        if (!FULL && 256 * (i >> 2) + 4 * lane + (i & 3) >= C) k = 0u;
+        key[i] = k;
+        m2 = max(m2, min(m1, k));
+        m1 = max(m1, k);
+    }
+    uint32_t T = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t t = T | (1u << b);
+        if (ballot_count(m1 >= t) + ballot_count(m2 >= t) >= 64) T = t;
+    }
+    uint32_t cl = 0;
 #pragma unroll
-        for (int q = 0; q < kTopPer; ++q) {
-            const int c = q * kTopT + t;
-            if (c < C && key[q] >= floor_key) {
-                cand_key[cpos] = key[q];
-                cand_col[cpos] = (uint32_t)c;
-                ++cpos;
-            }
-        }
-        __syncthreads();
-        if (t < (int)n_cand) {
-            const uint32_t k = cand_key[t], c = cand_col[t];
-            uint32_t rank = 0;
-#pragma unroll 4
-            for (uint32_t j = 0; j < n_cand; ++j) {
-                const uint32_t kj = cand_key[j], cj = cand_col[j];
-                rank += ((kj > k) | ((kj == k) & (cj < c))) ? 1u : 0u;
-            }
-            if (rank < 64u) {
-                sel_key[rank] = k;
-                sel_idx[rank] = c;
-            }
-        }
-        __syncthreads();
+    for (int i = 0; i < kTopV; ++i) cl += key[i] >= T ? 1u : 0u;
+    uint32_t incl = wave_scan_incl(cl);
+    int n = __builtin_amdgcn_readlane((int)incl, 63);
+    if (T >= 1u && n <= 128) {
+        uint32_t pos = incl - cl;
+#pragma unroll
+        for (int i = 0; i < kTopV; ++i)
+            if (key[i] >= T) cand.put(pos++, key[i], ncol0 - (uint32_t)(256 * (i >> 2) + (i & 3)));
     } else {
-        // radix select over the keys >= floor_key: the key of rank 63 (descending)
-        uint32_t prefix = 0, pmask = 0;
-        int need = 64;
-        for (int shift = 24; shift >= 0; shift -= 8) {
-            hist[t] = 0u;
-            __syncthreads();
-    #pragma unroll
-            for (int q = 0; q < kTopPer; ++q)
-                if (q * kTopT + t < C && key[q] >= floor_key && (key[q] & pmask) == prefix)
-                    atomicAdd(&hist[(key[q] >> shift) & 255u], 1u);
-            __syncthreads();
-            const uint32_t h = hist[255 - t];   // thread t: the t-th bin from the top
-            uint32_t tot;
-            const uint32_t before = topk_scan(h, tmp, &tot);
-            if (before < (uint32_t)need && before + h >= (uint32_t)need) {
-                s_bin = 255u - (uint32_t)t;
-                s_before = before;
-            }
-            __syncthreads();
-            prefix |= s_bin << shift;
-            pmask |= 255u << shift;
-            need -= (int)s_before;
-            __syncthreads();
+        // the exact 64th largest key; every threshold tried is at least 1,
+        // so absent columns never count
+        T = 0;
+        for (int b = 31; b >= 0; --b) {
+            const uint32_t t = T | (1u << b);
+            uint32_t c = 0;
+#pragma unroll
+            for (int i = 0; i < kTopV; ++i) c += key[i] >= t ? 1u : 0u;
+            if (wave_sum_u(c) >= 64u) T = t;
         }
-        const uint32_t T = prefix;   // the 64th largest key; take every key above it
-        // and the `need` entries equal to it of smallest column
-        if (t == 0) {
-            s_ngt = 0u;
-            s_bin = 0u;   // count of keys equal to T
-        }
-        __syncthreads();
-        uint32_t my_eq = 0;
-    #pragma unroll
-        for (int q = 0; q < kTopPer; ++q) {
-            const int c = q * kTopT + t;
-            if (c < C && key[q] > T) {
-                const uint32_t pos = atomicAdd(&s_ngt, 1u);
-                if (pos < 64u) {
-                    sel_key[pos] = key[q];
-                    sel_idx[pos] = (uint32_t)c;
-                }
-            }
-            my_eq += (c < C && key[q] == T) ? 1u : 0u;
-        }
-        if (my_eq) atomicAdd(&s_bin, my_eq);
-        __syncthreads();
-        if (s_bin == (uint32_t)need) {   // every equal key is selected: no order needed
-    #pragma unroll
-            for (int q = 0; q < kTopPer; ++q) {
-                const int c = q * kTopT + t;
-                if (c < C && key[q] == T) {
-                    const uint32_t pos = atomicAdd(&s_ngt, 1u);
-                    if (pos < 64u) {
-                        sel_key[pos] = key[q];
-                        sel_idx[pos] = (uint32_t)c;
+        uint32_t cg = 0;
+#pragma unroll
+        for (int i = 0; i < kTopV; ++i) cg += key[i] > T ? 1u : 0u;
+        incl = wave_scan_incl(cg);
+        uint32_t run = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);   // fewer than 64
+        uint32_t pos = incl - cg;
+#pragma unroll
+        for (int i = 0; i < kTopV; ++i)
+            if (key[i] > T) cand.put(pos++, key[i], ncol0 - (uint32_t)(256 * (i >> 2) + (i & 3)));
+        // keys equal to T by increasing column: block q holds columns
+        // [256 q, 256 q + 256) in (lane, e) order
+#pragma unroll
+        for (int q = 0; q < kTopQ; ++q) {
+            if (run < 64u) {
+                uint32_t ce = 0;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) ce += (key[4 * q + e] == T && 256 * q + 4 * lane + e < C) ? 1u : 0u;
+                const uint32_t ie = wave_scan_incl(ce);
+                uint32_t p = run + ie - ce;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (key[4 * q + e] == T && 256 * q + 4 * lane + e < C) {
+                        if (p < 64u) cand.put(p, T, ncol0 - (uint32_t)(256 * q + e));
+                        ++p;
                     }
-                }
+                run += (uint32_t)__builtin_amdgcn_readlane((int)ie, 63);
             }
-        } else {   // ties at the boundary: the equal keys of smallest column, block by block
-            uint32_t eq_run = 0;
-    #pragma unroll
-            for (int q = 0; q < kTopPer; ++q) {
-                const int c = q * kTopT + t;
-                const bool eq = c < C && key[q] == T;
-                uint32_t tot;
-                const uint32_t rank = topk_scan(eq ? 1u : 0u, tmp, &tot);
-                if (eq && eq_run + rank < (uint32_t)need) {
-                    const uint32_t pos = (uint32_t)(64 - need) + eq_run + rank;
-                    sel_key[pos] = key[q];
-                    sel_idx[pos] = (uint32_t)c;
-                }
-                eq_run += tot;
-            }
+        }
+        n = 64;
+    }
+    __syncthreads();   // one wave: orders the candidate writes before the reads
+    const uint64_t a = lane < n ? cand.get(lane) : 0ull;
+    const uint64_t b = lane + 64 < n ? cand.get(lane + 64) : 0ull;
+    uint32_t ra = 0, rb = 0;
+    if (n <= 64) {
+        for (int j = 0; j < n; ++j) ra += cand.get(j) > a ? 1u : 0u;
+    } else {
+        for (int j = 0; j < n; ++j) {
+            const uint64_t v = cand.get(j);
+            ra += v > a ? 1u : 0u;
+            rb += v > b ? 1u : 0u;
         }
     }
-    // softmax denominator from the registers: per thread around its own maximum
-    float tmx = -INFINITY;
-#pragma unroll
-    for (int q = 0; q < kTopPer; ++q)
-        if (q * kTopT + t < C) tmx = fmaxf(tmx, key_value(key[q]));
-    float se = 0.f;
-#pragma unroll
-    for (int q = 0; q < kTopPer; ++q)
-        if (q * kTopT + t < C) se += __expf(key_value(key[q]) - tmx);
-    se = (tmx > -INFINITY) ? se * __expf(tmx - mx) : 0.f;
-    se = wave_sum_f(se);
-    if (lane == 0) redf[wv] = se;
+    float ssel = 0.f;
+    const float off = -mx * kLog2e;
+    if (lane < n && ra < 64u) {
+        sel[ra] = ~(uint32_t)a;
+        ssel += __builtin_amdgcn_exp2f(fmaf(key_value((uint32_t)(a >> 32)), kLog2e, off));
+    }
+    if (lane + 64 < n && rb < 64u) {
+        sel[rb] = ~(uint32_t)b;
+        ssel += __builtin_amdgcn_exp2f(fmaf(key_value((uint32_t)(b >> 32)), kLog2e, off));
+    }
     __syncthreads();
-    if (wv == 0) {
-        float sall = 0.f;
-#pragma unroll
-        for (int q = 0; q < kTopT / 64; ++q) sall += redf[q];
-        // bitonic sort of the 64 selected entries (key desc, column asc) in wave 0
-        uint32_t k = sel_key[lane], id = sel_idx[lane];
-        float ssel = __expf(key_value(k) - mx);
-        for (int size = 2; size <= 64; size <<= 1) {
-            for (int stride = size >> 1; stride > 0; stride >>= 1) {
-                const uint32_t ok_ = __shfl_xor(k, stride), oi = __shfl_xor(id, stride);
-                const bool lower = (lane & stride) == 0;
-                const bool desc = (lane & size) == 0;
-                const bool mine_first = (k > ok_) || (k == ok_ && id < oi);
-                const bool keep = (lower == desc) ? mine_first : !mine_first;
-                if (!keep) {
-                    k = ok_;
-                    id = oi;
-                }
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1) ssel += __shfl_xor(ssel, off);
-        idx_out[(size_t)row * 64 + lane] = (int32_t)id;
-        if (lane == 0 && mass_out) mass_out[row] = sall > 0.f ? ssel / sall : 0.f;
+    idx_out[(size_t)row * 64 + lane] = (int32_t)sel[lane];
+    if (mass_out) {
+        ssel = wave_sum_f(ssel);
+        if (lane == 0) mass_out[row] = sall > 0.f ? ssel / sall : 0.f;
     }
 }
 
@@ -688,7 +640,10 @@ int launch_ranks(const float2 *W, const uint8_t *perm, const float2 *s, float ta
 
 int launch_topk64(const float *S, int rows, int C, int32_t *idx, float *mass, hipStream_t st) {
     if (rows == 0) return VP_OK;
-    hipLaunchKernelGGL(k_topk64, dim3(rows), dim3(kTopT), 0, st, S, rows, C, idx, mass);
+    const bool full = C == 64 * kTopV, vec4 = (C & 3) == 0 && ((uintptr_t)S & 15) == 0;
+    auto k = full ? (vec4 ? k_topk64<true, true> : k_topk64<true, false>)
+                  : (vec4 ? k_topk64<false, true> : k_topk64<false, false>);
+    hipLaunchKernelGGL(k, dim3(rows), dim3(64), 0, st, S, C, idx, mass);
     return launch_status();
 }
 

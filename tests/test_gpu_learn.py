@@ -241,12 +241,26 @@ def test_path_ranks_vs_oracle(lib, N, Q):
 # --------------------------------------------------------------------------- selection / loss
 
 @pytest.mark.parametrize("rows,C,kind", [(1, 64, "normal"), (37, 65, "ties"), (200, 4096, "normal"),
-                                         (50, 1000, "ties"), (8, 4096, "zeros"), (3, 4096, "const")])
+                                         (50, 1000, "ties"), (8, 4096, "zeros"), (3, 4096, "const"),
+                                         (300, 4096, "coarse"), (40, 4096, "skewed"), (33, 4095, "normal"),
+                                         (21, 4096, "unaligned"), (64, 130, "coarse")])
 def test_topk64_vs_oracle(lib, rows, C, kind):
+    """Every selection route of the kernel: candidates above the bound from the
+    lanes' two largest (normal, coarse = ties at the boundary), the exact
+    search (short rows, ties over many columns, skewed = the 128 largest in
+    two lanes' columns), rows of C = 4095 (no float4 loads) and rows at an
+    address that is not 16-byte aligned."""
     _, learn = lib
+    torch = pytest.importorskip("torch")
     rng = np.random.default_rng(rows + C)
-    if kind == "normal":
+    if kind in ("normal", "unaligned"):
         s = (rng.standard_normal((rows, C)) * 3).astype(np.float32)
+    elif kind == "coarse":
+        s = (np.round(rng.standard_normal((rows, C)) * 48) / 16).astype(np.float32)
+    elif kind == "skewed":
+        s = rng.standard_normal((rows, C)).astype(np.float32)
+        c = np.arange(C)
+        s[:, ((c % 256) // 4) < 2] += 10.0
     elif kind == "ties":
         s = rng.integers(-3, 4, size=(rows, C)).astype(np.float32)
     elif kind == "zeros":
@@ -254,12 +268,21 @@ def test_topk64_vs_oracle(lib, rows, C, kind):
         s[:, ::7] = -1.0
     else:
         s = np.full((rows, C), 1.25, np.float32)
-    idx, mass = learn.topk64(dev(s))
+    if kind == "unaligned":
+        buf = torch.zeros(rows * C + 1, dtype=torch.float32, device="cuda")
+        scores = buf[1:].view(rows, C)
+        scores.copy_(torch.from_numpy(s))
+    else:
+        scores = dev(s)
+    idx, mass = learn.topk64(scores)
     idx, mass = host(idx), host(mass)
     want = L.topk(s, 64)
     np.testing.assert_array_equal(idx, want)
     wm = L.softmax_mass(s.astype(np.float64), want)
     assert np.all(np.abs(mass - wm) <= 1e-4 * (1 + wm))
+    idx2, mass2 = learn.topk64(scores, with_mass=False)
+    assert mass2 is None
+    np.testing.assert_array_equal(host(idx2), want)
 
 
 def test_softmax_xent_vs_oracle(lib):
