@@ -36,7 +36,8 @@ __device__ __forceinline__ uint16_t f2bf(float f) {   // round to nearest even
 //   TA: A is stored as [K][M] (lda = row stride of the stored matrix)
 //   TB: B is stored as [N][K]
 // 128 x 128 tile per workgroup, 2 x 2 waves of 64 x 64 (2 x 2 MFMA blocks of
-// 32 x 32 each), K in steps of 32 through LDS ([row][k] with a padded row).
+// 32 x 32 each), K in steps of 32 through LDS ([row][k] with a padded row),
+// the global loads of step s + 1 issued before the MFMAs of step s.
 // ---------------------------------------------------------------------------
 constexpr int GT = 256, BM = 128, BN = 128, BK = 32, LDK = BK + 8;
 
@@ -55,26 +56,48 @@ __device__ __forceinline__ uint4 load8(const uint16_t *__restrict__ row, int sta
     return r;
 }
 
-// Stage a ROWS x BK tile of op(X) (rows = m or n) into S[row][k].  CONTIG_K:
-// the stored matrix is contiguous along k (X[row][k]); else along rows (X[k][row]).
+// A ROWS x BK tile of op(X) (rows = m or n) in two steps, so that the global
+// loads of the next K step are in flight while the current one is computed:
+// fetch() loads this thread's 8-element chunks into registers, put() stores
+// them to S[row][k].  CONTIG_K: the stored matrix is contiguous along k
+// (X[row][k]); else along rows (X[k][row]).
 template <bool CONTIG_K, int ROWS>
-__device__ __forceinline__ void stage(uint16_t (*S)[LDK], const uint16_t *__restrict__ X, long long ld, int r0,
+struct TileRegs {
+    static constexpr int Q = ROWS * BK / 8 / GT;   // chunks per thread
+    uint4 x[Q];
+};
+
+template <bool CONTIG_K, int ROWS>
+__device__ __forceinline__ void fetch(TileRegs<CONTIG_K, ROWS> &R, const uint16_t *__restrict__ X, long long ld, int r0,
                                       int nrows, int k0, int K, bool vec, int t) {
-    constexpr int CH = ROWS * BK / 8;   // 8-element chunks in the tile
 #pragma unroll
-    for (int q = 0; q < CH / GT; ++q) {
+    for (int q = 0; q < R.Q; ++q) {
         const int c = q * GT + t;
+        uint4 x = make_uint4(0, 0, 0, 0);
         if (CONTIG_K) {
             const int rr = c / (BK / 8), kk = (c % (BK / 8)) * 8;
             const int gr = r0 + rr;
-            uint4 x = make_uint4(0, 0, 0, 0);
             if (gr < nrows && k0 + kk < K) x = load8(X + (size_t)gr * ld, k0 + kk, K, vec);
-            *reinterpret_cast<uint4 *>(&S[rr][kk]) = x;
         } else {
             const int kk = c / (ROWS / 8), rr = (c % (ROWS / 8)) * 8;
             const int gk = k0 + kk;
-            uint4 x = make_uint4(0, 0, 0, 0);
             if (gk < K && r0 + rr < nrows) x = load8(X + (size_t)gk * ld, r0 + rr, nrows, vec);
+        }
+        R.x[q] = x;
+    }
+}
+
+template <bool CONTIG_K, int ROWS>
+__device__ __forceinline__ void put(uint16_t (*S)[LDK], const TileRegs<CONTIG_K, ROWS> &R, int t) {
+#pragma unroll
+    for (int q = 0; q < R.Q; ++q) {
+        const int c = q * GT + t;
+        const uint4 x = R.x[q];
+        if (CONTIG_K) {
+            const int rr = c / (BK / 8), kk = (c % (BK / 8)) * 8;
+            *reinterpret_cast<uint4 *>(&S[rr][kk]) = x;
+        } else {
+            const int kk = c / (ROWS / 8), rr = (c % (ROWS / 8)) * 8;
             const uint32_t w[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
@@ -85,9 +108,10 @@ __device__ __forceinline__ void stage(uint16_t (*S)[LDK], const uint16_t *__rest
     }
 }
 
-// Four waves per SIMD: the accumulators then sit in ordinary VGPRs (114 in
-// all) instead of 144 VGPRs + 64 accumulation registers at two waves, which
-// hides more of each K step's load latency.
+// Four waves per SIMD: the accumulators then sit in ordinary VGPRs (128 in
+// all, with the registers of the next step's loads) instead of 144 VGPRs + 64
+// accumulation registers at two waves, which hides more of each K step's load
+// latency.
 template <bool TA, bool TB>
 __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_gemm(int M, int N, int K, const uint16_t *__restrict__ A, long long lda,
                                              const uint16_t *__restrict__ B, long long ldb, int vec_a, int vec_b,
@@ -106,10 +130,18 @@ __global__ __launch_bounds__(GT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         for (int b = 0; b < 2; ++b)
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+    TileRegs<!TA, BM> ra;
+    TileRegs<TB, BN> rb;
+    fetch<!TA, BM>(ra, A, lda, m0, M, 0, K, vec_a != 0, t);
+    fetch<TB, BN>(rb, B, ldb, n0, N, 0, K, vec_b != 0, t);
     for (int k0 = 0; k0 < K; k0 += BK) {
-        stage<!TA, BM>(As, A, lda, m0, M, k0, K, vec_a != 0, t);
-        stage<TB, BN>(Bs, B, ldb, n0, N, k0, K, vec_b != 0, t);
+        put<!TA, BM>(As, ra, t);
+        put<TB, BN>(Bs, rb, t);
         __syncthreads();
+        if (k0 + BK < K) {   // the next step's loads, in flight during this step's MFMAs
+            fetch<!TA, BM>(ra, A, lda, m0, M, k0 + BK, K, vec_a != 0, t);
+            fetch<TB, BN>(rb, B, ldb, n0, N, k0 + BK, K, vec_b != 0, t);
+        }
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 16) {
             // lane l: row (l % 32) of a 32-row block, k = kk + 8 (l / 32) .. +7
