@@ -181,6 +181,59 @@ def bench_learned(vp, steps, warmup, wl, H, s, K_mop=64):
             "train_meta": getattr(prop, "meta", {})}
 
 
+
+def bench_learned_fallback(vp, steps, warmup, wl, H, s, theta=0.3, K_mop=64, K_fix=512):
+    """The learned proposal with its fallback: vectors whose top-64 softmax mass
+    is below theta are searched again over the subcarrier's fixed K_fix MoP set
+    (vp_search_fallback), which replaces the proposal's result where it is
+    cheaper.  The proposal's table holds the 64 proposed paths and the first
+    K_mop paths of that same fixed set.  Timed per stage, with its power gap."""
+    import torch
+    from paper_2602_12098_amd import learn
+    path = os.path.join(ROOT, "paper_2602_12098_amd", "weights", "proposer_16x16_256qam_res64.safetensors")
+    if not os.path.exists(path):
+        return None
+    prop = learn.load_proposer(path)
+    n_sym = wl.n_sym
+    order = torch.empty((wl.n_sc, 2, K_fix), dtype=torch.int16, device="cuda:0")
+    work = torch.empty((2 * wl.n_vec,), dtype=torch.int32, device="cuda:0")
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
+    out = {}
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        prep = vp.preprocess(H, wl.alpha)
+        if ev: ev[1].record()
+        paths = vp.paths_mop(prep.w2, K_fix, order=order)
+        if ev: ev[2].record()
+        table, mass = prop.propose(prep.W, prep.perm, s, wl.tau, n_sym, fixed_paths=paths, K_fixed=K_mop)
+        if ev: ev[3].record()
+        o = vp.search(prep.W, prep.perm, s, wl.tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
+        if ev: ev[4].record()
+        learn.search_fallback(prep.W, prep.perm, s, wl.tau, paths, n_sym, mass, theta, o, 64 + K_mop + 1,
+                              order=order, work=work)
+        if ev: ev[5].record()
+        vp.precode(prep.G, s, o.l, wl.tau, o.cost, n_sym, P_T=1.0)
+        if ev: ev[6].record()
+        out["prep"], out["o"], out["mass"] = prep, o, mass
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    names = ["preprocess", "paths_mop", "propose", "search", "fallback", "precode"]
+    stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+              for i, n in enumerate(names)}
+    ms = float(np.mean([evs[k][0].elapsed_time(evs[k][6]) for k in range(steps)]))
+    g, _ = gap_to_exact(vp, out["prep"], s, wl.tau, n_sym, out["o"].cost)
+    frac = float((~(out["mass"] >= theta)).float().mean())
+    return {"theta": theta, "fallback_fraction": frac, "fixed_paths": K_fix,
+            "paths_per_vector": 64 + K_mop, "value": wl.n_vec / (ms * 1e-3), "unit": "vectors/s",
+            "ms_per_step": ms, "stages_ms": stages, "gap_db": g}
+
+
 def _cpu_worker(args):
     sc_list, wl_seed, K = args
     import vpgen
@@ -263,7 +316,10 @@ def main():
                         torch.empty((n_vec,), dtype=torch.int32, device=dev))
     x = torch.empty((n_vec, M), dtype=torch.complex64, device=dev)
     if args.only == "learned":
-        print(json.dumps({"learned": bench_learned(vp, args.steps, args.warmup, wl, H, s)}), flush=True)
+        lr = bench_learned(vp, args.steps, args.warmup, wl, H, s)
+        if lr is not None:
+            lr["fallback"] = bench_learned_fallback(vp, args.steps, args.warmup, wl, H, s)
+        print(json.dumps({"learned": lr}), flush=True)
         return
 
     def step(ev=None):
@@ -320,6 +376,9 @@ def main():
         line["batched"] = bench_batched(vp, args.steps, args.warmup)
         print("learned proposal ...", file=sys.stderr, flush=True)
         line["learned"] = bench_learned(vp, args.steps, args.warmup, wl, H, s)
+        if line["learned"] is not None:
+            print("learned proposal with fallback ...", file=sys.stderr, flush=True)
+            line["learned"]["fallback"] = bench_learned_fallback(vp, args.steps, args.warmup, wl, H, s)
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(K)

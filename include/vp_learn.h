@@ -159,6 +159,37 @@ int vp_colsum_bf16(const uint16_t *X, int rows, int cols, float *out, void *stre
 int vp_learned_paths(const uint8_t *vocab, int V, int n_r, const int32_t *top, int K_learned, const uint8_t *fixed,
                      int K_fixed_table, int K_fixed, int n_sc, int n_sym, uint8_t *table, void *stream);
 
+/*
+ * vp_search_fallback -- the fixed path set for the vectors whose proposal is
+ * not confident (the fallback of the learned proposal; the paper has no
+ * learned part, the search itself is that of vp_search: Sec. II-B PED
+ * recursion, Sec. III-A-2 centres and DEMAP, Alg. 2 argmin).
+ *
+ * l, cost, kidx are in/out and hold on entry the proposal's search result
+ * (vp_search with VP_PATHS_PER_VECTOR on the tables of vp_learned_paths).
+ * Every vector v with !(mass[v] >= theta) -- a NaN mass counts as not
+ * confident; mass from vp_topk64 -- is searched again over the subcarrier's
+ * fixed table (paths, order, K, paths_sc_stride and VP_INCLUDE_ZERO as for
+ * vp_search, e.g. the K = 512 MoP set of vp_paths_mop).  Where that cost is
+ * below cost[v], v takes the fixed result: l from the winning fixed path,
+ * its cost, and kidx = kidx_base + k (k = the fixed table's path index, K =
+ * the zero perturbation).  Equal costs keep the proposal's result, so the
+ * fixed set decides only where it is strictly better.  Vectors with
+ * mass[v] >= theta are not touched.  theta = +inf sends every vector to the
+ * fixed set, theta <= 0 none with a finite mass.
+ *
+ * work: device memory of 8 * n_sc * n_sym bytes owned by the caller (the
+ * fixed search's cost and index per vector), 4-byte aligned.
+ *
+ * Errors: as vp_search (VP_PATHS_PER_VECTOR is not accepted: the fixed set is
+ * one table per subcarrier), plus VP_EINVAL for NULL mass or work, theta NaN
+ * or kidx_base < 0.
+ */
+int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const uint8_t *paths,
+                       const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
+                       uint32_t flags, const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost,
+                       int32_t *kidx, void *work, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -70,6 +70,24 @@ int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, 
                          n_r, flags, l, cost, kidx, (hipStream_t)stream);
 }
 
+int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const uint8_t *paths,
+                       const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
+                       uint32_t flags, const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost,
+                       int32_t *kidx, void *work, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+    if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
+    if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
+    if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;
+    if (flags & ~(uint32_t)VP_INCLUDE_ZERO) return VP_EINVAL;
+    if (isnan(theta) || kidx_base < 0) return VP_EINVAL;
+    if (n_sc == 0) return VP_OK;
+    if (!W || !perm || !s || !paths || !mass || !l || !cost || !kidx || !work) return VP_EINVAL;
+    if (reinterpret_cast<uintptr_t>(work) & 3) return VP_EINVAL;
+    return launch_search_fallback((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K, paths_sc_stride,
+                                  n_sc, n_sym, n_r, flags, mass, theta, kidx_base, l, cost, kidx, work,
+                                  (hipStream_t)stream);
+}
+
 int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, float tau, const float *cost, int n_sc, int n_sym,
                int n_r, int n_t, float P_T, vp_c32 *x, void *stream) {
     if (n_sc < 0 || n_sym < 1 || n_r < 1 || n_t < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;

@@ -79,6 +79,10 @@ int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, ui
 int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
                   const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                   int8_t *l, float *cost, int32_t *kidx, hipStream_t st);
+int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+                           const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
+                           const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
+                           void *work, hipStream_t st);
 int launch_precode(const float2 *G, const float2 *s, const int8_t *l, float tau, const float *cost,
                    int n_sc, int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st);
 

@@ -24,12 +24,22 @@ namespace {
 
 constexpr int kT = 256;
 
-template <int N>
+// The vectors a search serves: all of them (mass == nullptr), or those whose
+// proposal mass is not at least theta (a NaN mass counts as not confident).
+// Kernels take it with a compile-time MASKED flag, so that the plain search
+// carries no trace of it.
+struct VecMask {
+    const float *mass;
+    float theta;
+    __device__ __forceinline__ bool on(size_t v) const { return !mass || !(mass[v] >= theta); }
+};
+
+template <int N, bool MASKED>
 __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
                                                const float2 *__restrict__ s, float tau,
                                                const uint8_t *__restrict__ paths, int K, long long pstride,
                                                int n_sym, unsigned flags, float *__restrict__ cost_out,
-                                               int32_t *__restrict__ kidx_out) {
+                                               int32_t *__restrict__ kidx_out, VecMask mask) {
     __shared__ float2 s_r0[N];
     __shared__ float s_linv[N];
     __shared__ float s_wdiag[N];
@@ -38,6 +48,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
 
     constexpr int NP = VP_PACKED(N);
     const size_t v = xcd_contiguous(blockIdx.x, gridDim.x);   // one vector per workgroup
+    if (MASKED && !mask.on(v)) return;
     const int sc = (int)(v / n_sym);
     const int t = threadIdx.x;
     const size_t n_vec = (size_t)gridDim.x;
@@ -114,11 +125,11 @@ constexpr int kVPB = 2;                 // vectors of one subcarrier per workgro
 constexpr int kTB = kTT * kVPB;         // threads of the prefix-sharing search
 static_assert(kVPB == 2 && 2 * kMaxPrefix <= kTB, "stage 1 packs both vectors' prefixes over the workgroup");
 
-template <int N>
+template <int N, bool MASKED>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(
     const float2 *__restrict__ W, const uint8_t *__restrict__ perm, const float2 *__restrict__ s, float tau,
     const uint8_t *__restrict__ paths, const uint16_t *__restrict__ order, int K, long long pstride, int n_sym,
-    size_t n_vec, unsigned flags, float *__restrict__ cost_out, int32_t *__restrict__ kidx_out) {
+    size_t n_vec, unsigned flags, float *__restrict__ cost_out, int32_t *__restrict__ kidx_out, VecMask mask) {
     constexpr int P1 = prefix_levels<N>();
     constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
     extern __shared__ unsigned long long s_words[];   // [K] rank nibbles of path k
@@ -143,10 +154,20 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const int sym = (int)(blk % slots) * kVPB + h;
     const bool live = sym < n_sym;
     const size_t v = (size_t)sc * n_sym + (live ? sym : 0);
+    const int nlive = min(kVPB, n_sym - (int)(blk % slots) * kVPB);   // live vectors of this workgroup
+    // masked search: the live vectors it serves (the same in every thread)
+    bool on0 = true, on1 = true;
+    if (MASKED) {
+        const size_t v0 = (size_t)sc * n_sym + (blk % slots) * kVPB;
+        on0 = mask.on(v0);
+        on1 = nlive > 1 && mask.on(v0 + 1);
+        if (!on0 && !on1) return;
+    }
+    const bool act = live && (h == 0 ? on0 : on1);
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
     if (!(w00 > 0.f) || !isfinite(w00)) {   // failed preprocessing (the whole subcarrier)
-        if (tl == 0 && live) {
+        if (tl == 0 && act) {
             cost_out[v] = __int_as_float(0x7fc00000);
             kidx_out[v] = -1;
         }
@@ -202,13 +223,12 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const float tau2 = tau * tau;
     unsigned long long best = ~0ull;
     float *state = s_state[h];
-    const int nlive = min(kVPB, n_sym - (int)(blk % slots) * kVPB);   // live vectors of this workgroup
     for (uint32_t base = 0; base < n1; base += kMaxPrefix) {
         const uint32_t nc = min(n1 - base, (uint32_t)kMaxPrefix);
         // stage 1: one lane per (vector, distinct prefix), the vectors' prefixes
         // packed one after the other over the workgroup (2 nc <= kTB)
         const int hh = t >= (int)nc ? 1 : 0, pp = t - hh * (int)nc;
-        if (hh < nlive && pp < (int)nc) {
+        if (hh < nlive && (hh == 0 ? on0 : on1) && pp < (int)nc) {
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) r[i] = s_r0[hh][i];
@@ -227,7 +247,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
         // case) the contiguous lexicographic range of this chunk's prefixes
         const bool whole = (n1 <= (uint32_t)kMaxPrefix);
         const int q0 = whole ? 0 : s_first[base];
-        const int q1 = live ? (whole ? K : s_first[base + nc]) : q0;
+        const int q1 = act ? (whole ? K : s_first[base + nc]) : q0;
         for (int q = q0 + tl; q < q1; q += kTT) {
             int k;
             if (whole) {
@@ -250,7 +270,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
         }
         __syncthreads();
     }
-    if ((flags & VP_INCLUDE_ZERO) && tl == 0 && live) {
+    if ((flags & VP_INCLUDE_ZERO) && tl == 0 && act) {
         float z = 0.f;
         for (int i = 0; i < N; ++i) {
             z = fmaf(s_r0[h][i].x, s_r0[h][i].x, z);
@@ -261,7 +281,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     best = wave_min(best);
     if ((t & 63) == 0) s_red[t >> 6] = best;
     __syncthreads();
-    if (tl == 0 && live) {
+    if (tl == 0 && act) {
         constexpr int WPV = kTT / 64;   // waves per vector
         unsigned long long b = s_red[h * WPV];
         for (int w = 1; w < WPV; ++w) b = umin64(b, s_red[h * WPV + w]);
@@ -276,14 +296,14 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
 constexpr int kWV = 4;          // vectors (waves) per workgroup
 constexpr int kWaveMaxK = 192;  // tables up to this size use one wave per vector
 
-template <int N>
+template <int N, bool MASKED>
 __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restrict__ W,
                                                           const uint8_t *__restrict__ perm,
                                                           const float2 *__restrict__ s, float tau,
                                                           const uint8_t *__restrict__ paths, int K,
                                                           long long pstride, int n_sym, size_t n_vec,
                                                           unsigned flags, float *__restrict__ cost_out,
-                                                          int32_t *__restrict__ kidx_out) {
+                                                          int32_t *__restrict__ kidx_out, VecMask mask) {
     __shared__ float2 s_r0[kWV][N];
     __shared__ float s_linv[kWV][N];
     __shared__ float s_wdiag[kWV][N];
@@ -293,7 +313,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int t = threadIdx.x & 63;
     const size_t v0 = (size_t)xcd_contiguous(blockIdx.x, gridDim.x) * kWV + wv;
-    const bool live = v0 < n_vec;   // the last workgroup may hold fewer vectors
+    const bool live = v0 < n_vec && (!MASKED || mask.on(v0));   // the last workgroup may hold fewer vectors
     const size_t v = live ? v0 : n_vec - 1;
     const int sc = (int)(v / n_sym);
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
@@ -385,27 +405,106 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
     }
 }
 
+// Fallback merge: a vector the fixed-table search served takes that result
+// where its cost is below the one already held (the proposal's), with l from
+// a re-walk of the winning fixed path (the arithmetic of k_search_finalize).
+template <int N>
+__global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                                       const float2 *__restrict__ s, float tau,
+                                                       const uint8_t *__restrict__ paths, int K, long long pstride,
+                                                       int n_sc, int n_sym, VecMask mask,
+                                                       const float *__restrict__ cost_fix,
+                                                       const int32_t *__restrict__ kidx_fix, int32_t kidx_base,
+                                                       int8_t *__restrict__ l_out, float *__restrict__ cost_io,
+                                                       int32_t *__restrict__ kidx_io) {
+    constexpr int NP = VP_PACKED(N);
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
+    if (v >= n_vec || !mask.on(v)) return;
+    const float c = cost_fix[v];
+    if (!(c < cost_io[v])) return;   // ties and NaN keep the proposal's result
+    const int sc = (int)(v / n_sym);
+    const int k = kidx_fix[v];
+    const uint8_t *pm = perm + (size_t)sc * N;
+    float ra[N], rb[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) ra[i] = rb[i] = 0.f;
+    if (k >= 0 && k < K) {
+        const float2 *__restrict__ Wc = W + (size_t)sc * NP;
+        float linv[N], wdiag[N];
+        float2 r[N];
+        const float inv_tau = 1.0f / tau;
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            wdiag[i] = Wc[vp_pidx(N, i, i)].x;
+            linv[i] = 1.0f / wdiag[i];
+            r[i] = stilde_over_tau<N>(Wc, pm, s, v, n_vec, i, inv_tau);
+        }
+        const uint8_t *P = paths + (size_t)sc * pstride + (size_t)k * N;
+        unsigned long long wd = 0;
+        for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
+        (void)walk<N, false, true>(Wc, linv, wdiag, r, wd, VP_DEMAP_LUT, ra, rb);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int u = pm[i] < N ? pm[i] : N - 1;
+        int8_t *o = l_out + ((size_t)u * n_vec + v) * 2;
+        o[0] = (int8_t)ra[i];
+        o[1] = (int8_t)rb[i];
+    }
+    cost_io[v] = c;
+    kidx_io[v] = kidx_base + k;
+}
+
+// The search kernel for a table shape: prefix sharing with orders, one wave
+// per vector for short tables, else one workgroup per vector.
+template <int N, bool MASKED>
+void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+                          const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags,
+                          VecMask mask, float *cost, int32_t *kidx, hipStream_t st) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    if (order) {
+        const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(3 * K + 1) * sizeof(uint16_t);
+        static const bool lds_ok = allow_dynamic_lds(k_search_trie<N, MASKED>, 64 * 1024);
+        (void)lds_ok;
+        const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);
+        hipLaunchKernelGGL((k_search_trie<N, MASKED>), dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths, order, K,
+                           (long long)pstride, n_sym, n_vec, flags, cost, kidx, mask);
+    } else if (K <= kWaveMaxK) {
+        hipLaunchKernelGGL((k_search_wave<N, MASKED>), dim3((unsigned)((n_vec + kWV - 1) / kWV)), dim3(64 * kWV), 0, st, W,
+                           perm, s, tau, paths, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx, mask);
+    } else {
+        hipLaunchKernelGGL((k_search<N, MASKED>), dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
+                           (long long)pstride, n_sym, flags, cost, kidx, mask);
+    }
+}
+
 template <int N>
 int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
                     const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
                     float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
-    if (order) {
-        const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(3 * K + 1) * sizeof(uint16_t);
-        static const bool lds_ok = allow_dynamic_lds(k_search_trie<N>, 64 * 1024);
-        (void)lds_ok;
-        const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);
-        hipLaunchKernelGGL(k_search_trie<N>, dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths, order, K,
-                           (long long)pstride, n_sym, n_vec, flags, cost, kidx);
-    } else if (K <= kWaveMaxK) {
-        hipLaunchKernelGGL(k_search_wave<N>, dim3((unsigned)((n_vec + kWV - 1) / kWV)), dim3(64 * kWV), 0, st, W,
-                           perm, s, tau, paths, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx);
-    } else {
-        hipLaunchKernelGGL(k_search<N>, dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
-                           (long long)pstride, n_sym, flags, cost, kidx);
-    }
+    launch_search_kernel<N, false>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags,
+                                   VecMask{nullptr, 0.f}, cost, kidx, st);
     hipLaunchKernelGGL(k_search_finalize<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
                        tau, paths, K, (long long)pstride, n_sc, n_sym, flags, kidx, l);
+    return launch_status();
+}
+
+template <int N>
+int launch_fallback_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+                      const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags,
+                      const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
+                      void *work, hipStream_t st) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    float *cost_fix = static_cast<float *>(work);
+    int32_t *kidx_fix = reinterpret_cast<int32_t *>(cost_fix + n_vec);
+    const VecMask mask{mass, theta};
+    launch_search_kernel<N, true>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, mask, cost_fix,
+                                  kidx_fix, st);
+    hipLaunchKernelGGL(k_fallback_merge<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
+                       tau, paths, K, (long long)pstride, n_sc, n_sym, mask, cost_fix, kidx_fix, kidx_base, l, cost,
+                       kidx);
     return launch_status();
 }
 
@@ -420,6 +519,23 @@ int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float t
     case n:                                                                                                   \
         return launch_search_n<n>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, l, cost, \
                                   kidx, st);
+        VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
+        VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
+#undef VP_CASE
+        default: return VP_EUNSUPPORTED;
+    }
+}
+
+int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+                           const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
+                           const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
+                           void *work, hipStream_t st) {
+    if (n_sc == 0) return VP_OK;
+    switch (N) {
+#define VP_CASE(n)                                                                                              \
+    case n:                                                                                                     \
+        return launch_fallback_n<n>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, mass, theta, \
+                                    kidx_base, l, cost, kidx, work, st);
         VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
         VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
 #undef VP_CASE

@@ -22,7 +22,7 @@ import torch
 
 from . import _lib
 from ._lib import check
-from .vp import _req, _stream, packed_size
+from .vp import VP_INCLUDE_ZERO, _req, _stream, packed_size
 
 __all__ = ["VP_EPI_RELU", "VP_PATHS_PER_VECTOR", "N_FEATURES", "TOPK", "mlp_features", "path_ranks", "gemm_bf16",
            "topk64", "softmax_xent", "colsum_bf16", "learned_paths", "MLPParams", "MLPFunction", "mlp_logits",
@@ -184,6 +184,36 @@ def learned_paths(vocab: torch.Tensor, top: torch.Tensor, fixed: Optional[torch.
                                Kl, _req(fixed, "fixed", torch.uint8, (n_sc, Kft, N)) if fixed is not None else None,
                                Kft, int(K_fixed), n_sc, int(n_sym), _req(out, "table", torch.uint8, (n_vec, Kt, N)),
                                _stream()), "vp_learned_paths")
+    return out
+
+
+def search_fallback(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
+                    n_sym: int, mass: torch.Tensor, theta: float, out, kidx_base: int,
+                    order: Optional[torch.Tensor] = None, flags: int = VP_INCLUDE_ZERO,
+                    work: Optional[torch.Tensor] = None):
+    """vp_search_fallback: vectors with mass < theta (or NaN mass) are searched
+    over the fixed per-subcarrier table paths [n_sc][K][N]; out (a SearchOut
+    holding the proposal's search result) takes the fixed result where it is
+    strictly cheaper, with kidx = kidx_base + k.  Returns out."""
+    lib = _load()
+    n_sc, K, N = paths.shape
+    n_vec = n_sc * n_sym
+    if work is None:
+        work = torch.empty((2 * n_vec,), dtype=torch.int32, device=W.device)
+    pw = _req(work, "work", torch.int32)
+    if work.numel() < 2 * n_vec:
+        raise ValueError(f"work: needs {2 * n_vec} int32 elements")
+    check(lib.vp_search_fallback(_req(W, "W", torch.complex64, (n_sc, packed_size(N))),
+                                 _req(perm, "perm", torch.uint8, (n_sc, N)),
+                                 _req(s, "s", torch.complex64, (N, n_vec)), float(tau),
+                                 _req(paths, "paths", torch.uint8, (n_sc, K, N)),
+                                 _req(order, "order", torch.int16, (n_sc, 2, K)) if order is not None else None,
+                                 int(K), int(K * N), n_sc, int(n_sym), N, int(flags),
+                                 _req(mass, "mass", torch.float32, (n_vec,)), float(theta), int(kidx_base),
+                                 _req(out.l, "l", torch.int8, (N, n_vec, 2)),
+                                 _req(out.cost, "cost", torch.float32, (n_vec,)),
+                                 _req(out.kidx, "kidx", torch.int32, (n_vec,)), pw, _stream()),
+          "vp_search_fallback")
     return out
 
 

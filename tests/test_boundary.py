@@ -34,7 +34,7 @@ def test_header_symbols_exported(lib):
     names = declared_functions()
     assert {"vp_preprocess", "vp_paths_mop", "vp_search", "vp_precode", "vp_strerror", "vp_sphere_encode",
             "vp_mlp_features", "vp_path_ranks", "vp_gemm_bf16", "vp_topk64", "vp_softmax_xent", "vp_colsum_bf16",
-            "vp_learned_paths"} <= set(names)
+            "vp_learned_paths", "vp_search_fallback"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(PKG, "libvp.so")],
@@ -79,6 +79,29 @@ def test_argument_validation(lib):
     assert search(flags=2, n_sc=0) == VP_EINVAL
     assert search(n_sym=0, n_sc=0) == VP_EINVAL
     assert search(lex=1, stride=0, n_sc=0) == VP_EINVAL       # lexorder needs a per-subcarrier table
+    # vp_search_fallback: the checks of vp_search, plus mass, theta, kidx_base and work
+    fargs = dict(tau=8.0, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1, theta=0.5, base=72)
+
+    def fallback(P=None, **kw):
+        a = dict(fargs, **kw)
+        return lib.vp_search_fallback(P, P, P, a["tau"], P, a.get("lex"), a["K"], a["stride"], a["n_sc"],
+                                      a["n_sym"], a["N"], a["flags"], a.get("mass", P), a["theta"], a["base"],
+                                      P, P, P, a.get("work", P), None)
+    P = ctypes.c_void_p(16)   # non-NULL, never dereferenced (every call below fails its checks or has n_sc = 0)
+    assert fallback() == VP_EINVAL
+    assert fallback(n_sc=0) == VP_OK
+    assert fallback(P, mass=None) == VP_EINVAL
+    assert fallback(P, work=None) == VP_EINVAL
+    assert fallback(P, work=ctypes.c_void_p(18)) == VP_EINVAL             # work not 4-byte aligned
+    assert fallback(P, theta=float("nan")) == VP_EINVAL
+    assert fallback(P, base=-1) == VP_EINVAL
+    assert fallback(P, flags=2) == VP_EINVAL                               # VP_PATHS_PER_VECTOR
+    assert fallback(P, tau=0.0) == VP_EINVAL
+    assert fallback(P, N=17) == VP_EUNSUPPORTED
+    assert fallback(P, K=4097) == VP_EUNSUPPORTED
+    assert fallback(P, stride=5) == VP_EINVAL
+    assert fallback(P, lex=P, stride=0) == VP_EINVAL
+    assert fallback(theta=float("inf"), n_sc=0) == VP_OK
     # vp_precode
     assert lib.vp_precode(None, None, None, 8.0, None, 0, 14, 4, 4, 0.0, None, None) == VP_OK
     assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 4, 4, 1.0, None, None) == VP_EINVAL
