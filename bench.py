@@ -109,17 +109,23 @@ def bench_batched(vp, steps, warmup):
         sg = torch.from_numpy(np.concatenate([wl.s[i] for i in idx], axis=1)).to("cuda:0")
         per.append((H, sg, float(vpgen.qam_tau(q)), float(u) / 100.0, int(kcal[str(u)])))
 
-    def per_size():
+    def per_size(min_K_sharing=None):
+        """One call per stage and (U, QAM) group; with min_K_sharing, groups
+        with K >= it pass the MoP orders to vp_search (prefix sharing)."""
         outs = []
         for H, sg, tau, alpha, K in per:
             prep = vp.preprocess(H, alpha)
-            paths = vp.paths_mop(prep.w2, K)
-            o = vp.search(prep.W, prep.perm, sg, tau, paths, wl.n_sym)
+            share = min_K_sharing is not None and K >= min_K_sharing
+            order = torch.empty((H.shape[0], 2, K), dtype=torch.int16, device="cuda:0") if share else None
+            paths = vp.paths_mop(prep.w2, K, order=order)
+            o = vp.search(prep.W, prep.perm, sg, tau, paths, wl.n_sym, order=order)
             vp.precode(prep.G, sg, o.l, tau, o.cost, wl.n_sym, P_T=1.0)
             outs.append((prep, o))
         return outs
 
-    ms_per_size = timed(per_size)
+    ms_per_size_plain = timed(per_size)
+    ms_per_size_shared = timed(lambda: per_size(64))
+    ms_per_size = min(ms_per_size_plain, ms_per_size_shared)
     num = den = 0.0
     for (H, sg, tau, alpha, K), (prep, o) in zip(per, per_size()):
         g, exact = gap_to_exact(vp, prep, sg, tau, wl.n_sym, o.cost)
@@ -129,6 +135,7 @@ def bench_batched(vp, steps, warmup):
     res = {"workload": f"{wl.n_rbg} RBGs x {wl.sc_per_rbg} sc x {wl.n_sym} sym, U 4..16, QAM 4..256, M {wl.M}",
            "n_vec": n_vec, "K_by_U": kcal, "value": n_vec / (ms_tuned * 1e-3), "unit": "vectors/s",
            "ms_graph_default": ms_default, "ms_graph_tuned": ms_tuned, "ms_per_size_launches": ms_per_size,
+           "ms_per_size_plain": ms_per_size_plain, "ms_per_size_prefix_sharing_K64": ms_per_size_shared,
            "per_size_launch_groups": len(per), "speedup_vs_per_size": ms_per_size / ms_tuned,
            "gap_db": 10 * math.log10(num / den), "tuning": info}
     b.close()
