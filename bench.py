@@ -46,12 +46,15 @@ SEARCH_SOURCES = ["paper_2602_12098_amd/csrc/vp_search.hip", "paper_2602_12098_a
 TRAFFIC_FILE = "profiles/k_search_trie_16x16_256qam_K512.traffic.json"
 
 
-def search_traffic():
+def search_traffic(K):
     """HBM bytes per launch of the search kernel from the committed counter
-    profile, or None when it is missing or the kernel sources changed since."""
+    profile (taken at K = 512), or None when it is missing, K differs or the
+    kernel sources changed since."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None, "no traffic profile"
+    if K != 512:
+        return None, "the counters were taken at K = 512"
     rec = json.load(open(path))
     h = hashlib.sha256()
     for f in rec.get("source_files", SEARCH_SOURCES):
@@ -290,6 +293,7 @@ def main():
     ap.add_argument("--K", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip the gap, batched and learned measurements")
+    ap.add_argument("--no-forms", action="store_true", help="keep the gap, skip the batched and learned forms")
     ap.add_argument("--only", choices=("batched", "learned"), default=None,
                     help="run one further form alone (for profiling) and print its record")
     args = ap.parse_args()
@@ -361,7 +365,7 @@ def main():
 
     flops = search_cm_per_vector(M, K) * FLOP_PER_CM * n_vec
     achieved = flops / (stage["search"] * 1e-3) / 1e12
-    traffic, traffic_src = search_traffic()
+    traffic, traffic_src = search_traffic(K)
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic, "traffic_source": traffic_src,
             "kernel": "vp_search (k_search_trie + k_search_finalize)",
@@ -379,6 +383,7 @@ def main():
     if not args.no_extras:
         print("gap to exact VP ...", file=sys.stderr, flush=True)
         line["gap_db"], _ = gap_to_exact(vp, prep, s, wl.tau, n_sym, sout.cost)
+    if not args.no_extras and not args.no_forms:
         print("batched slot ...", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(vp, args.steps, args.warmup)
         print("learned proposal ...", file=sys.stderr, flush=True)
