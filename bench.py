@@ -74,6 +74,22 @@ def gap_to_exact(vp, prep, s, tau, n_sym, cost):
     return 10 * math.log10(float(cost.double().sum()) / float(exact.sum())), exact
 
 
+def rzf_powers(prep, s, n_sym):
+    """gamma of linear RZF (l = 0) per vector: ||W s_pi||^2, from the packed
+    lower W (column-major) and the level order, in complex128 (a reported
+    reference, outside every timed region)."""
+    import torch
+    n_sc, N = prep.perm.shape
+    cols = [j for j in range(N) for _ in range(j, N)]
+    rows = [i for j in range(N) for i in range(j, N)]
+    Wd = torch.zeros((n_sc, N, N), dtype=torch.complex128, device=prep.W.device)
+    Wd[:, rows, cols] = prep.W.to(torch.complex128)
+    S = s.to(torch.complex128).t().reshape(n_sc, n_sym, N)
+    Sp = torch.gather(S, 2, prep.perm.long()[:, None, :].expand(n_sc, n_sym, N)).contiguous()
+    Y = torch.matmul(Sp, Wd.transpose(1, 2).contiguous())
+    return (Y.abs() ** 2).sum(dim=2).reshape(-1)
+
+
 def bench_batched(vp, steps, warmup):
     """The 2048-RBG uneven slot (U ~ 4..16, mixed QAM, M = 16) with K(U) from the
     calibration table: one captured graph (default and autotuned tile shapes)
@@ -382,7 +398,13 @@ def main():
     }
     if not args.no_extras:
         print("gap to exact VP ...", file=sys.stderr, flush=True)
-        line["gap_db"], _ = gap_to_exact(vp, prep, s, wl.tau, n_sym, sout.cost)
+        line["gap_db"], exact = gap_to_exact(vp, prep, s, wl.tau, n_sym, sout.cost)
+        # the gain of VP over linear RZF (l = 0) at exact VP, and at the K paths
+        g0 = rzf_powers(prep, s, n_sym)
+        ok = torch.isfinite(g0) & torch.isfinite(exact)
+        line["gain_over_rzf_db"] = {
+            "exact": 10 * math.log10(float(g0[ok].sum()) / float(exact[ok].sum())),
+            "paths": 10 * math.log10(float(g0[ok].sum()) / float(sout.cost.double()[ok].sum()))}
     if not args.no_extras and not args.no_forms:
         print("batched slot ...", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(vp, args.steps, args.warmup)

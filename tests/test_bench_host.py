@@ -40,3 +40,30 @@ def test_traffic_profile_belongs_to_the_sources():
     assert value == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     assert rec["source_files"] == bench.SEARCH_SOURCES
     assert bench.search_traffic(256)[0] is None
+
+
+def test_rzf_powers_match_the_oracle():
+    """The l = 0 reference of the RZF-gain report: ||W s_pi||^2 from the packed
+    W and the level order equals the oracle's dense computation."""
+    torch = pytest.importorskip("torch")
+    import collections
+
+    import numpy as np
+
+    import vpgen
+    from oracle import vp_oracle as O
+    wl = vpgen.make("t", 6, 8, 3, 5, 64, 0.1, 16, seed=9)
+    Ws, perms = [], []
+    want = []
+    for sc in range(wl.n_sc):
+        p = O.preprocess(wl.H[sc], wl.alpha)
+        W = np.asarray(p.W)
+        Ws.append(np.concatenate([W[j:, j] for j in range(wl.N)]))   # packed lower, column-major
+        perms.append(np.asarray(p.perm))
+        for j in range(wl.n_sym):
+            v = sc * wl.n_sym + j
+            want.append(np.linalg.norm(W @ wl.s[np.asarray(p.perm), v]) ** 2)
+    Prep = collections.namedtuple("Prep", "W perm")
+    prep = Prep(torch.from_numpy(np.array(Ws)), torch.from_numpy(np.array(perms).astype(np.uint8)))
+    got = bench.rzf_powers(prep, torch.from_numpy(wl.s), wl.n_sym).numpy()
+    np.testing.assert_allclose(got, np.array(want), rtol=1e-12)
