@@ -121,3 +121,39 @@ def test_fallback_theta_nothing_flagged(lib):
             assert np.array_equal(a[keep], b[keep])
     c3, cp3, cf3 = float(out.cost[3]), float(lr.cost[3]), float(fx.cost[3])
     assert c3 == (cf3 if cf3 < cp3 else cp3)
+
+
+def test_fallback_at_the_benchmark_launch(lib):
+    """The benchmark's launch: 3276 subcarriers x 14 symbols, the committed
+    proposer's tables and masses, theta = 0.3 over the K = 512 MoP set with its
+    orders.  Every vector is checked against the plain search restricted to
+    the flagged ones (bit-exact)."""
+    import os
+    vp, learn = lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "paper_2602_12098_amd", "weights", "proposer_16x16_256qam_res64.safetensors")
+    if not os.path.exists(path):
+        pytest.skip("no committed proposer")
+    prop = learn.load_proposer(path)
+    wl = vpgen.cfg3(512)
+    print("fallback at the benchmark launch", flush=True)
+    H = torch.from_numpy(wl.H).to(DEV)
+    s = torch.from_numpy(wl.s).to(DEV)
+    prep = vp.preprocess(H, wl.alpha)
+    order = torch.empty((wl.n_sc, 2, 512), dtype=torch.int16, device=DEV)
+    fixed = vp.paths_mop(prep.w2, 512, order=order)
+    table, mass = prop.propose(prep.W, prep.perm, s, wl.tau, wl.n_sym, fixed_paths=fixed, K_fixed=64)
+    lr = vp.search(prep.W, prep.perm, s, wl.tau, table, wl.n_sym,
+                   flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
+    out = vp.SearchOut(lr.l.clone(), lr.cost.clone(), lr.kidx.clone())
+    base = table.shape[1] + 1
+    learn.search_fallback(prep.W, prep.perm, s, wl.tau, fixed, wl.n_sym, mass, 0.3, out, base, order=order)
+    fx = vp.search(prep.W, prep.perm, s, wl.tau, fixed, wl.n_sym, order=order)
+    flagged = ~(mass >= 0.3)
+    take = flagged & (fx.cost < lr.cost)
+    assert torch.equal(out.cost, torch.where(take, fx.cost, lr.cost))
+    assert torch.equal(out.kidx, torch.where(take, fx.kidx + base, lr.kidx))
+    assert torch.equal(out.l, torch.where(take[None, :, None], fx.l, lr.l))
+    frac = float(flagged.float().mean())
+    print(f"flagged {frac:.3f}, fixed set better for {int(take.sum())} vectors", flush=True)
+    assert 0.05 < frac < 0.95 and int(take.sum()) > 0
