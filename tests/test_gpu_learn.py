@@ -285,6 +285,33 @@ def test_topk64_vs_oracle(lib, rows, C, kind):
     np.testing.assert_array_equal(host(idx2), want)
 
 
+
+def test_topk64_on_trained_logits_at_the_benchmark_launch(lib):
+    """The committed network's logits for all 45,864 vectors of the benchmark's
+    slot, selected on the GPU in one launch; 400 sampled rows against the
+    oracle (selection bit-exact, mass within 1e-4)."""
+    import os
+    _, learn = lib
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    path = os.path.join(root, "paper_2602_12098_amd", "weights", "proposer_16x16_256qam_res64.safetensors")
+    if not os.path.exists(path):
+        pytest.skip("no committed proposer")
+    import paper_2602_12098_amd as vp
+    prop = learn.load_proposer(path)
+    wl = vpgen.cfg3(512)
+    prep = vp.preprocess(dev(wl.H), wl.alpha)
+    with torch.no_grad():
+        x = learn.mlp_features(prep.W, prep.perm, dev(wl.s), wl.tau, wl.n_sym, kind=prop.kind)
+        z = learn.mlp_logits(x, prop.p)
+    assert z.dtype == torch.float32 and tuple(z.shape) == (wl.n_vec, 4096)
+    idx, mass = learn.topk64(z)
+    rows = np.random.default_rng(3).choice(wl.n_vec, 400, replace=False)
+    zs = host(z[torch.from_numpy(rows).to(DEV)])
+    want = L.topk(zs, 64)
+    np.testing.assert_array_equal(host(idx)[rows], want)
+    wm = L.softmax_mass(zs.astype(np.float64), want)
+    assert np.all(np.abs(host(mass)[rows] - wm) <= 1e-4 * (1 + wm))
+
 def test_softmax_xent_vs_oracle(lib):
     _, learn = lib
     rng = np.random.default_rng(17)
