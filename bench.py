@@ -46,31 +46,62 @@ SEARCH_SOURCES = ["paper_2602_12098_amd/csrc/vp_search.hip", "paper_2602_12098_a
 TRAFFIC_FILE = "profiles/k_search_trie_16x16_256qam_K512.traffic.json"
 
 
-def search_traffic(K):
+def sources_sha256(files):
+    """sha256 over the concatenated bytes of the given repository files."""
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def search_traffic(K, path=None):
     """HBM bytes per launch of the search kernel from the committed counter
     profile (taken at K = 512), or None when it is missing, K differs or the
     kernel sources changed since."""
-    path = os.path.join(ROOT, TRAFFIC_FILE)
+    path = path or os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None, "no traffic profile"
     if K != 512:
         return None, "the counters were taken at K = 512"
     rec = json.load(open(path))
-    h = hashlib.sha256()
-    for f in rec.get("source_files", SEARCH_SOURCES):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    if h.hexdigest() != rec.get("source_sha256"):
+    if sources_sha256(rec.get("source_files", SEARCH_SOURCES)) != rec.get("source_sha256"):
         return None, "kernel changed since the counters were taken"
-    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], TRAFFIC_FILE
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"], os.path.relpath(path, ROOT)
 
 
-def gap_to_exact(vp, prep, s, tau, n_sym, cost):
+COUNTERS_FILE = "profiles/search_16x16_256qam_K512.valu.json"
+
+
+def search_counters(K, path=None):
+    """Measured clock and VALU issue of the search kernel from the committed
+    counter profile (GRBM_GUI_ACTIVE against the kernel's duration gives the
+    shader clock; SQ_ACTIVE_INST_VALU x 4 cycles over all SIMDs gives the VALU
+    issue fraction), or {} when it is missing, K differs or the sources changed."""
+    path = path or os.path.join(ROOT, COUNTERS_FILE)
+    if K != 512 or not os.path.exists(path):
+        return {}
+    rec = json.load(open(path))
+    if sources_sha256(rec.get("source_files", SEARCH_SOURCES)) != rec.get("source_sha256"):
+        return {}
+    return {"sclk_ghz_measured": rec["sclk_ghz"], "valu_busy": rec["valu_busy"],
+            "valu_instr_per_vector": rec["valu_instr_per_vector"], "counters_source": os.path.relpath(path, ROOT)}
+
+
+def gap_to_exact(vp, prep, s, tau, n_sym, cost, counts=None):
     """Power gap (dB) of the selected perturbations to exact VP over the box:
-    the sphere encoder seeded with each vector's own cost as radius."""
+    the GPU sphere encoder seeded with each vector's own cost as radius.  A
+    vector whose encoder ran out of its node budget contributes the best point
+    it found (never above the method's cost); one with no point inside the
+    radius contributes the method's own cost.  `counts` (a dict) receives how
+    many vectors took either way."""
     import torch
     se = vp.sphere_encode(prep.W, prep.perm, s, tau, n_sym, radius=cost * (1 + 1e-6))
     exact = torch.where(torch.isfinite(se.cost), se.cost, cost).double()
+    if counts is not None:
+        counts["budget_exhausted"] = int((se.status == vp.VP_SE_EXHAUSTED).sum())
+        counts["no_point_inside_radius"] = int((se.status == vp.VP_SE_NONE).sum())
+        counts["vectors"] = int(cost.numel())
     return 10 * math.log10(float(cost.double().sum()) / float(exact.sum())), exact
 
 
@@ -126,7 +157,8 @@ def bench_batched(vp, steps, warmup):
         idx = [i for i in range(wl.n_rbg) if wl.U[i] == u and wl.Q[i] == q]
         H = torch.from_numpy(np.concatenate([wl.H[i] for i in idx])).to("cuda:0")
         sg = torch.from_numpy(np.concatenate([wl.s[i] for i in idx], axis=1)).to("cuda:0")
-        per.append((H, sg, float(vpgen.qam_tau(q)), float(u) / 100.0, int(kcal[str(u)])))
+        per.append((H, sg, vp.tau_array(float(vpgen.qam_tau(q)), H.shape[0], "cuda:0"), float(u) / 100.0,
+                    int(kcal[str(u)])))
 
     def per_size(min_K_sharing=None):
         """One call per stage and (U, QAM) group; with min_K_sharing, groups
@@ -172,6 +204,7 @@ def bench_learned(vp, steps, warmup, wl, H, s, K_mop=64):
         return None
     prop = learn.load_proposer(path)
     n_sym = wl.n_sym
+    tau = vp.tau_array(wl.tau, wl.n_sc, "cuda:0")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(6)] for _ in range(steps)]
     out = {}
 
@@ -183,9 +216,9 @@ def bench_learned(vp, steps, warmup, wl, H, s, K_mop=64):
         if ev: ev[2].record()
         table, mass = prop.propose(prep.W, prep.perm, s, wl.tau, n_sym, fixed_paths=paths, K_fixed=K_mop)
         if ev: ev[3].record()
-        o = vp.search(prep.W, prep.perm, s, wl.tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
+        o = vp.search(prep.W, prep.perm, s, tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
         if ev: ev[4].record()
-        vp.precode(prep.G, s, o.l, wl.tau, o.cost, n_sym, P_T=1.0)
+        vp.precode(prep.G, s, o.l, tau, o.cost, n_sym, P_T=1.0)
         if ev: ev[5].record()
         out["prep"], out["o"] = prep, o
 
@@ -221,6 +254,7 @@ def bench_learned_fallback(vp, steps, warmup, wl, H, s, theta=0.3, K_mop=64, K_f
         return None
     prop = learn.load_proposer(path)
     n_sym = wl.n_sym
+    tau = vp.tau_array(wl.tau, wl.n_sc, "cuda:0")
     order = torch.empty((wl.n_sc, 2, K_fix), dtype=torch.int16, device="cuda:0")
     work = torch.empty((2 * wl.n_vec,), dtype=torch.int32, device="cuda:0")
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(7)] for _ in range(steps)]
@@ -234,12 +268,12 @@ def bench_learned_fallback(vp, steps, warmup, wl, H, s, theta=0.3, K_mop=64, K_f
         if ev: ev[2].record()
         table, mass = prop.propose(prep.W, prep.perm, s, wl.tau, n_sym, fixed_paths=paths, K_fixed=K_mop)
         if ev: ev[3].record()
-        o = vp.search(prep.W, prep.perm, s, wl.tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
+        o = vp.search(prep.W, prep.perm, s, tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
         if ev: ev[4].record()
-        learn.search_fallback(prep.W, prep.perm, s, wl.tau, paths, n_sym, mass, theta, o, 64 + K_mop + 1,
+        learn.search_fallback(prep.W, prep.perm, s, tau, paths, n_sym, mass, theta, o, 64 + K_mop + 1,
                               order=order, work=work)
         if ev: ev[5].record()
-        vp.precode(prep.G, s, o.l, wl.tau, o.cost, n_sym, P_T=1.0)
+        vp.precode(prep.G, s, o.l, tau, o.cost, n_sym, P_T=1.0)
         if ev: ev[6].record()
         out["prep"], out["o"], out["mass"] = prep, o, mass
 
@@ -260,11 +294,15 @@ def bench_learned_fallback(vp, steps, warmup, wl, H, s, theta=0.3, K_mop=64, K_f
             "ms_per_step": ms, "stages_ms": stages, "gap_db": g}
 
 
-def _cpu_worker(args):
-    sc_list, wl_seed, K = args
-    import vpgen
+# The workload the oracle workers read: built once in the parent before the
+# pool forks, so that no worker regenerates it inside the timed wall.
+_CPU_WL = None
+
+
+def _cpu_worker(sc_list):
     from oracle import vp_oracle as O
-    wl = vpgen.cfg3(K)
+    wl = _CPU_WL
+    K = wl.K
     t0 = time.perf_counter()
     nv = 0
     for sc in sc_list:
@@ -278,27 +316,136 @@ def _cpu_worker(args):
     return nv, time.perf_counter() - t0
 
 
-def cpu_baseline(K, budget_s=12.0):
-    """FP64 oracle (numpy) on a bounded sample of subcarriers, all host cores."""
+def host_description():
+    """nproc, the CPUs this process may run on, and the CPU model of the host."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"nproc": os.cpu_count() or 1, "cpus_available": avail, "cpu_model": model}
+
+
+# The GPU machines grant 16 host CPUs per GPU, whatever nproc reports there.
+HOST_PROCS_CAP = 16
+
+
+def cpu_baseline(wl, budget_s=12.0):
+    """FP64 oracle (numpy) on a bounded sample of subcarriers of the same
+    workload, one process per granted host CPU."""
     import multiprocessing as mp
-    cores = os.cpu_count() or 1
-    cores = min(cores, 16)
+    global _CPU_WL
+    _CPU_WL = wl
+    host = host_description()
+    procs = max(1, min(host["cpus_available"], HOST_PROCS_CAP))
     # calibrate on one subcarrier, then size the sample to ~budget_s of wall time
-    nv, dt = _cpu_worker(([0], 3, K))
-    per_sc = dt
-    n_sc = int(max(cores, min(3276, budget_s * cores / per_sc)))
-    n_sc = min(n_sc, 3275)
+    _, per_sc = _cpu_worker([0])
+    n_sc = int(max(procs, min(wl.n_sc - 1, budget_s * procs / per_sc)))
     scs = list(range(1, 1 + n_sc))
-    chunks = [scs[i::cores] for i in range(cores)]
-    t0 = time.perf_counter()
-    with mp.get_context("fork").Pool(cores) as pool:
-        res = pool.map(_cpu_worker, [(c, 3, K) for c in chunks])
-    wall = time.perf_counter() - t0
+    chunks = [scs[i::procs] for i in range(procs)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(procs) as pool:
+        pool.map(abs, range(procs))          # processes started before the clock
+        t0 = time.perf_counter()
+        res = pool.map(_cpu_worker, chunks)
+        wall = time.perf_counter() - t0
     nvec = sum(r[0] for r in res)
-    return {"value": nvec / wall, "unit": "vectors/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n_sc} of 3276 subcarriers x 14 symbols (16x16, K={K}), full pipeline "
-                      f"(preprocess, K-best MoP, path search, precode) in float64 numpy, "
-                      f"{cores} processes, {wall:.1f} s wall"}
+    return dict({"value": nvec / wall, "unit": "vectors/s", "cores": procs, "kind": "oracle",
+                 "sample": f"{n_sc} of {wl.n_sc} subcarriers x {wl.n_sym} symbols ({wl.N}x{wl.M}, K={wl.K}), "
+                           f"full pipeline (preprocess, K-best MoP, path search, precode) in float64 numpy, "
+                           f"{procs} processes (capped at {HOST_PROCS_CAP}), {wall:.1f} s wall; the workload is "
+                           f"generated before the clock starts"}, **host)
+
+
+def exact_vp_host(wl, l_gpu, n_vec=4096):
+    """The oracle's exact VP (its C sphere encoder, float64) on the first n_vec
+    vectors of the workload, timed on the host cores, and the power gap of the
+    GPU's selected perturbations to it: both costs are formed in float64 from
+    the oracle's own factorisation of H.  The encoder is seeded with each
+    vector's method cost (which only prunes)."""
+    import numpy as np
+    from oracle import se_c
+    from oracle import vp_oracle as O
+    n_sc = (n_vec + wl.n_sym - 1) // wl.n_sym
+    preps = [O.preprocess(wl.H[sc], wl.alpha) for sc in range(n_sc)]
+    W = np.stack([p.W for p in preps])
+    perm = np.stack([p.perm for p in preps])
+    wsel = (np.arange(n_vec) // wl.n_sym).astype(np.int32)
+    s = wl.s[:, :n_vec].astype(np.complex128)
+    l = l_gpu[:n_vec]
+    g_method = np.array([O.cost_tri(W[wsel[v]], perm[wsel[v]], s[:, v], l[v], wl.tau) for v in range(n_vec)])
+    se_c.build()
+    t0 = time.perf_counter()
+    _, g_exact, nodes = se_c.sphere_encode_batch(W, perm, s, wl.tau, radius=g_method * (1 + 1e-9), wsel=wsel)
+    wall = time.perf_counter() - t0
+    found = np.isfinite(g_exact)
+    g_exact = np.where(found, g_exact, g_method)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or host_description()["cpus_available"]
+    return {"gap_db": 10 * math.log10(float(g_method.sum()) / float(g_exact.sum())),
+            "vectors": n_vec, "value": n_vec / wall, "unit": "vectors/s", "threads": threads,
+            "kind": "oracle C sphere encoder (float64, OpenMP), seeded with the method's cost",
+            "median_nodes": float(np.median(nodes)), "no_point_inside_radius": int(np.sum(~found)),
+            "wall_s": wall}
+
+
+def run_plain(vp, wl, K, steps, warmup, dev="cuda:0"):
+    """Time the plain path (preprocess, MoP paths with their orders, search,
+    precode) on workload wl with K paths: inputs resident in HBM, outputs
+    preallocated.  Returns the timings and the buffers of the last step."""
+    import torch
+    N, M, n_sc, n_sym = wl.N, wl.M, wl.n_sc, wl.n_sym
+    n_vec = n_sc * n_sym
+    H = torch.from_numpy(wl.H).to(dev)
+    s = torch.from_numpy(wl.s).to(dev)
+    tau = vp.tau_array(wl.tau, n_sc, dev)
+    prep = vp.Prep(torch.empty((n_sc, vp.packed_size(N)), dtype=torch.complex64, device=dev),
+                   torch.empty((n_sc, N), dtype=torch.float32, device=dev),
+                   torch.empty((n_sc, N), dtype=torch.uint8, device=dev),
+                   torch.empty((n_sc, M, N), dtype=torch.complex64, device=dev),
+                   torch.empty((n_sc,), dtype=torch.int32, device=dev))
+    paths = torch.empty((n_sc, K, N), dtype=torch.uint8, device=dev)
+    order = torch.empty((n_sc, 2, K), dtype=torch.int16, device=dev)
+    sout = vp.SearchOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
+                        torch.empty((n_vec,), dtype=torch.float32, device=dev),
+                        torch.empty((n_vec,), dtype=torch.int32, device=dev))
+    x = torch.empty((n_vec, M), dtype=torch.complex64, device=dev)
+
+    def step(ev=None):
+        if ev: ev[0].record()
+        vp.preprocess(H, wl.alpha, out=prep)
+        if ev: ev[1].record()
+        vp.paths_mop(prep.w2, K, out=paths, order=order)
+        if ev: ev[2].record()
+        vp.search(prep.W, prep.perm, s, tau, paths, n_sym, out=sout, order=order)
+        if ev: ev[3].record()
+        vp.precode(prep.G, s, sout.l, tau, sout.cost, n_sym, P_T=1.0, out=x)
+        if ev: ev[4].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    names = ["preprocess", "paths_mop", "search", "precode"]
+    stages = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(steps)]))
+              for i, n in enumerate(names)}
+    ms_event = float(np.mean([evs[k][0].elapsed_time(evs[k][4]) for k in range(steps)]))
+    assert bool(torch.all(prep.status == 0)), "preprocessing failed on some subcarrier"
+    return {"value": n_vec * steps / wall, "wall_ms_per_step": wall * 1e3 / steps, "event_ms_per_step": ms_event,
+            "stages_ms": stages, "prep": prep, "s": s, "tau": tau, "sout": sout, "x": x}
 
 
 def main():
@@ -308,8 +455,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--K", type=int, default=512)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip the gap, batched and learned measurements")
-    ap.add_argument("--no-forms", action="store_true", help="keep the gap, skip the batched and learned forms")
+    ap.add_argument("--no-extras", action="store_true", help="skip the gap, K points, batched and learned forms")
+    ap.add_argument("--no-forms", action="store_true", help="keep the gap and K points, skip the batched and "
+                                                            "learned forms")
     ap.add_argument("--only", choices=("batched", "learned"), default=None,
                     help="run one further form alone (for profiling) and print its record")
     args = ap.parse_args()
@@ -329,85 +477,70 @@ def main():
     wl = vpgen.cfg3(args.K)
     N, M, n_sc, n_sym, K = wl.N, wl.M, wl.n_sc, wl.n_sym, args.K
     n_vec = n_sc * n_sym
-    H = torch.from_numpy(wl.H).to(dev)
-    s = torch.from_numpy(wl.s).to(dev)
-    prep = vp.Prep(torch.empty((n_sc, vp.packed_size(N)), dtype=torch.complex64, device=dev),
-                   torch.empty((n_sc, N), dtype=torch.float32, device=dev),
-                   torch.empty((n_sc, N), dtype=torch.uint8, device=dev),
-                   torch.empty((n_sc, M, N), dtype=torch.complex64, device=dev),
-                   torch.empty((n_sc,), dtype=torch.int32, device=dev))
-    paths = torch.empty((n_sc, K, N), dtype=torch.uint8, device=dev)
-    order = torch.empty((n_sc, 2, K), dtype=torch.int16, device=dev)
-    sout = vp.SearchOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
-                        torch.empty((n_vec,), dtype=torch.float32, device=dev),
-                        torch.empty((n_vec,), dtype=torch.int32, device=dev))
-    x = torch.empty((n_vec, M), dtype=torch.complex64, device=dev)
     if args.only == "learned":
+        H = torch.from_numpy(wl.H).to(dev)
+        s = torch.from_numpy(wl.s).to(dev)
         lr = bench_learned(vp, args.steps, args.warmup, wl, H, s)
         if lr is not None:
             lr["fallback"] = bench_learned_fallback(vp, args.steps, args.warmup, wl, H, s)
         print(json.dumps({"learned": lr}), flush=True)
         return
 
-    def step(ev=None):
-        if ev: ev[0].record()
-        vp.preprocess(H, wl.alpha, out=prep)
-        if ev: ev[1].record()
-        vp.paths_mop(prep.w2, K, out=paths, order=order)
-        if ev: ev[2].record()
-        vp.search(prep.W, prep.perm, s, wl.tau, paths, n_sym, out=sout, order=order)
-        if ev: ev[3].record()
-        vp.precode(prep.G, s, sout.l, wl.tau, sout.cost, n_sym, P_T=1.0, out=x)
-        if ev: ev[4].record()
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    print(f"warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
-
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(evs[k])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    stage_names = ["preprocess", "paths_mop", "search", "precode"]
-    stage = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(args.steps)]))
-             for i, n in enumerate(stage_names)}
-    ms_step = float(np.mean([evs[k][0].elapsed_time(evs[k][4]) for k in range(args.steps)]))
-    value = n_vec * args.steps / wall
-    assert bool(torch.all(prep.status == 0)), "preprocessing failed on some subcarrier"
+    r = run_plain(vp, wl, K, args.steps, args.warmup, dev)
+    print(f"timed {args.steps} steps of K = {K}: {r['wall_ms_per_step']:.3f} ms per step", file=sys.stderr,
+          flush=True)
+    stage = r["stages_ms"]
+    prep, s, sout = r["prep"], r["s"], r["sout"]
 
     flops = search_cm_per_vector(M, K) * FLOP_PER_CM * n_vec
     achieved = flops / (stage["search"] * 1e-3) / 1e12
     traffic, traffic_src = search_traffic(K)
     roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / PEAK_VALU_TFLOPS, "traffic": traffic, "traffic_source": traffic_src,
-            "kernel": "vp_search (k_search_trie + k_search_finalize)",
+            "kernel": "vp_search (the search kernel and its l write-back, timed together by HIP events on "
+                      "the launch stream)",
             "work": f"{search_cm_per_vector(M, K)} complex mult/vector x {FLOP_PER_CM} flop x {n_vec} vectors"}
+    roof.update(search_counters(K))
 
     line = {
-        "metric": METRIC, "value": value, "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall * 1e3 / args.steps, "higher_is_better": True,
+        "metric": METRIC, "value": r["value"], "unit": "vectors/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": r["wall_ms_per_step"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "N": N, "M": M, "n_sc": n_sc, "n_sym": n_sym, "K": K, "Q": wl.Q,
                    "alpha": wl.alpha, "rho": wl.rho, "seed": wl.seed},
-        "event_ms_per_step": ms_step, "stages_ms": stage, "roofline": roof,
+        "event_ms_per_step": r["event_ms_per_step"], "stages_ms": stage, "roofline": roof,
         "gap_db": None,
     }
     if not args.no_extras:
         print("gap to exact VP ...", file=sys.stderr, flush=True)
-        line["gap_db"], exact = gap_to_exact(vp, prep, s, wl.tau, n_sym, sout.cost)
+        counts = {}
+        line["gap_db"], exact = gap_to_exact(vp, prep, s, wl.tau, n_sym, sout.cost, counts)
+        line["gap_exact_vp"] = dict(counts, encoder="GPU sphere encoder (vp_sphere_encode), every vector")
         # the gain of VP over linear RZF (l = 0) at exact VP, and at the K paths
         g0 = rzf_powers(prep, s, n_sym)
         ok = torch.isfinite(g0) & torch.isfinite(exact)
         line["gain_over_rzf_db"] = {
             "exact": 10 * math.log10(float(g0[ok].sum()) / float(exact[ok].sum())),
             "paths": 10 * math.log10(float(g0[ok].sum()) / float(sout.cost.double()[ok].sum()))}
+        line["K_points"] = {}
+        for Kp in (128, 256):
+            if Kp == K:
+                continue
+            print(f"K = {Kp} ...", file=sys.stderr, flush=True)
+            rp = run_plain(vp, vpgen.cfg3(Kp), Kp, args.steps, args.warmup, dev)
+            g, _ = gap_to_exact(vp, rp["prep"], rp["s"], wl.tau, n_sym, rp["sout"].cost)
+            line["K_points"][str(Kp)] = {"value": rp["value"], "unit": "vectors/s",
+                                         "ms_per_step": rp["wall_ms_per_step"], "stages_ms": rp["stages_ms"],
+                                         "gap_db": g}
+            del rp
+    l_host = None
+    if not args.no_cpu:
+        l_i8 = sout.l.cpu().numpy()
+        l_host = (l_i8[..., 0].astype(np.float64) + 1j * l_i8[..., 1].astype(np.float64)).T
     if not args.no_extras and not args.no_forms:
         print("batched slot ...", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(vp, args.steps, args.warmup)
+        H = torch.from_numpy(wl.H).to(dev)
         print("learned proposal ...", file=sys.stderr, flush=True)
         line["learned"] = bench_learned(vp, args.steps, args.warmup, wl, H, s)
         if line["learned"] is not None:
@@ -415,7 +548,11 @@ def main():
             line["learned"]["fallback"] = bench_learned_fallback(vp, args.steps, args.warmup, wl, H, s)
     if not args.no_cpu:
         print("cpu baseline ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(K)
+        line["cpu_baseline"] = cpu_baseline(wl)
+        print("exact VP on the host (oracle sphere encoder) ...", file=sys.stderr, flush=True)
+        ev = exact_vp_host(wl, l_host)
+        line["cpu_baseline"]["exact_vp"] = ev
+        line["gap_db_oracle_first4096"] = ev["gap_db"]
     print(json.dumps(line), flush=True)
 
 

@@ -61,6 +61,14 @@ enum {
     VP_PATHS_PER_VECTOR = 2 /* one [K][N] table per vector (paths + v * paths_sc_stride) */
 };
 
+/* per-vector status written by vp_sphere_encode */
+enum {
+    VP_SE_EXACT = 0,      /* the search completed: l is the exact minimiser over the box */
+    VP_SE_EXHAUSTED = 1,  /* the node budget ran out: l and cost are the best point found so far
+                             (cost NaN, l = 0 if none was found inside the radius) */
+    VP_SE_NONE = 2        /* the search completed and no point lies inside the radius: l = 0, cost NaN */
+};
+
 /* Size (in vp_c32) of one packed lower-triangular N x N matrix. */
 #define VP_PACKED(N) ((N) * ((N) + 1) / 2)
 
@@ -141,7 +149,9 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  *
  *  W, perm  from vp_preprocess (W's diagonal must be real and > 0)
  *  s        [N][n_vec]  symbols, structure of arrays (user-major), user order
- *  tau      perturbation interval 2 sqrt(Q) (Sec. II-B), > 0
+ *  tau      [n_sc] perturbation interval of each subcarrier, 2 sqrt(Q) for
+ *           its Q-QAM constellation (Sec. II-B), so that one call may mix
+ *           modulation orders across subcarriers
  *  paths    ranks uint8; subcarrier sc uses paths + sc * paths_sc_stride,
  *           a [K][N] table (stride 0 = one table for every subcarrier).
  *           With VP_PATHS_PER_VECTOR vector v uses paths + v * paths_sc_stride
@@ -154,16 +164,16 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  *  cost     [n_vec] output
  *  kidx     [n_vec] output, selected path (K = zero perturbation)
  *
- * A subcarrier whose W_00 is not finite and > 0 (a failed vp_preprocess)
- * gets l = 0, cost = NaN, kidx = -1.
+ * A subcarrier whose W_00 is not finite and > 0 (a failed vp_preprocess), or
+ * whose tau is not finite and > 0, gets l = 0, cost = NaN, kidx = -1.
  *
  * Errors: VP_EINVAL for NULL pointers, n_sc < 0, n_sym < 1, N < 1, K < 1,
- * tau <= 0 or not finite, paths_sc_stride < 0 (or 0 < stride < K*N), order
+ * paths_sc_stride < 0 (or 0 < stride < K*N), order
  * given with paths_sc_stride != K*N, unknown flags, VP_PATHS_PER_VECTOR with
  * an order or with paths_sc_stride != K*N; VP_EUNSUPPORTED for N > 16 or
  * K > 4096.
  */
-int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
+int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau,
               const uint8_t *paths, const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc,
               int n_sym, int n_r, uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream);
 
@@ -171,19 +181,20 @@ int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau,
  * vp_precode -- precoded vector (Alg. 2 output; Sec. IV-B channel-inverse,
  * gamma and PV blocks).
  *
- * x_v = G (s_v + tau l_v); with P_T > 0 also scaled by sqrt(P_T / cost_v), the
- * transmit-power normalisation of Sec. II-B.  A vector whose cost is not
- * finite and > 0 is written as NaN when P_T > 0.
+ * x_v = G (s_v + tau_sc l_v); with P_T > 0 also scaled by sqrt(P_T / cost_v),
+ * the transmit-power normalisation of Sec. II-B.  A vector whose cost is not
+ * finite and > 0 is written as NaN when P_T > 0, and so is every vector of a
+ * subcarrier whose tau is not finite and > 0.
  *
  *  G     [n_sc][M][N]  from vp_preprocess
- *  s     [N][n_vec], l [N][n_vec][2] as in vp_search
+ *  s     [N][n_vec], l [N][n_vec][2], tau [n_sc] as in vp_search
  *  cost  [n_vec] (may be NULL when P_T == 0)
  *  x     [n_vec][M] output
  *
- * Errors: VP_EINVAL for NULL pointers, bad sizes, tau <= 0, P_T < 0, or
- * cost == NULL with P_T > 0; VP_EUNSUPPORTED for N > 16 or M > 64.
+ * Errors: VP_EINVAL for NULL pointers, bad sizes, P_T < 0, or cost == NULL
+ * with P_T > 0; VP_EUNSUPPORTED for N > 16 or M > 64.
  */
-int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, float tau, const float *cost,
+int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, const float *tau, const float *cost,
                int n_sc, int n_sym, int n_r, int n_t, float P_T, vp_c32 *x, void *stream);
 
 /*
@@ -196,20 +207,23 @@ int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, float tau, con
  * This is the reference the power gap of the K-path method is measured
  * against, and the label generator of the learned path proposal.
  *
- *  W, perm, s, tau, n_sc, n_sym, n_r  as in vp_search
+ *  W, perm, s, n_sc, n_sym, n_r  as in vp_search
+ *  tau       one perturbation interval for every subcarrier, > 0
  *  radius    [n_vec] initial squared radius, or NULL for none; a radius at or
  *            slightly above a known solution's cost (e.g. vp_search's cost)
  *            only prunes
- *  max_nodes per-vector node budget (> 0); a vector that exhausts it, or has
- *            no point inside its radius, gets l = 0 and cost = NaN
+ *  max_nodes per-vector node budget (> 0); a vector that exhausts it keeps the
+ *            best point found so far (status VP_SE_EXHAUSTED); a vector with
+ *            no point inside its radius gets l = 0 and cost = NaN
  *  l         [N][n_vec][2] output, user order;  cost [n_vec] output
  *  nodes     [n_vec] output (int64) or NULL: tree nodes visited
+ *  status    [n_vec] output (uint8, VP_SE_*) or NULL
  *
  * Errors: as vp_search (no K / paths), plus max_nodes <= 0 -> VP_EINVAL.
  */
 int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym,
                      int n_r, const float *radius, int64_t max_nodes, int8_t *l, float *cost, int64_t *nodes,
-                     void *stream);
+                     uint8_t *status, void *stream);
 
 /* Human-readable text for a return code. */
 const char *vp_strerror(int code);

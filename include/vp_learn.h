@@ -169,7 +169,7 @@ int vp_learned_paths(const uint8_t *vocab, int V, int n_r, const int32_t *top, i
  * (vp_search with VP_PATHS_PER_VECTOR on the tables of vp_learned_paths).
  * Every vector v with !(mass[v] >= theta) -- a NaN mass counts as not
  * confident; mass from vp_topk64 -- is searched again over the subcarrier's
- * fixed table (paths, order, K, paths_sc_stride and VP_INCLUDE_ZERO as for
+ * fixed table (tau [n_sc], paths, order, K, paths_sc_stride and VP_INCLUDE_ZERO as for
  * vp_search, e.g. the K = 512 MoP set of vp_paths_mop).  Where that cost is
  * below cost[v], v takes the fixed result: l from the winning fixed path,
  * its cost, and kidx = kidx_base + k (k = the fixed table's path index, K =
@@ -185,7 +185,7 @@ int vp_learned_paths(const uint8_t *vocab, int V, int n_r, const int32_t *top, i
  * one table per subcarrier), plus VP_EINVAL for NULL mass or work, theta NaN
  * or kidx_base < 0.
  */
-int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const uint8_t *paths,
+int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau, const uint8_t *paths,
                        const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
                        uint32_t flags, const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost,
                        int32_t *kidx, void *work, void *stream);

@@ -15,6 +15,9 @@ VP_EUNSUPPORTED = -2
 VP_ELAUNCH = -3
 VP_INCLUDE_ZERO = 1
 VP_PATHS_PER_VECTOR = 2
+VP_SE_EXACT = 0
+VP_SE_EXHAUSTED = 1
+VP_SE_NONE = 2
 
 _lib = None
 
@@ -36,11 +39,11 @@ _F = ctypes.c_float
 SIGNATURES = {
     "vp_preprocess": [_P, _I, _I, _I, _F, _P, _P, _P, _P, _P, _P],
     "vp_paths_mop": [_P, _I, _I, _I, _P, _P, _P],
-    "vp_search": [_P, _P, _P, _F, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _P, _P, _P],
-    "vp_search_fallback": [_P, _P, _P, _F, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _F,
+    "vp_search": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _P, _P, _P],
+    "vp_search_fallback": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _F,
                            ctypes.c_int32, _P, _P, _P, _P, _P],
-    "vp_precode": [_P, _P, _P, _F, _P, _I, _I, _I, _I, _F, _P, _P],
-    "vp_sphere_encode": [_P, _P, _P, _F, _I, _I, _I, _P, ctypes.c_int64, _P, _P, _P, _P],
+    "vp_precode": [_P, _P, _P, _P, _P, _I, _I, _I, _I, _F, _P, _P],
+    "vp_sphere_encode": [_P, _P, _P, _F, _I, _I, _I, _P, ctypes.c_int64, _P, _P, _P, _P, _P],
     "vp_strerror": [_I],
     "vp_last_hip_error": [],
     "vp_version": [],

@@ -54,60 +54,60 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
     return launch_mop(w2, n_sc, n_r, K, paths, order, (hipStream_t)stream);
 }
 
-int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const uint8_t *paths,
+int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau, const uint8_t *paths,
               const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
               uint32_t flags, int8_t *l, float *cost, int32_t *kidx, void *stream) {
-    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1) return VP_EINVAL;
     if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
     if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
     if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;   // one order per subcarrier table
     if (flags & ~(uint32_t)(VP_INCLUDE_ZERO | VP_PATHS_PER_VECTOR)) return VP_EINVAL;
     if ((flags & VP_PATHS_PER_VECTOR) && (order || paths_sc_stride != (int64_t)K * n_r)) return VP_EINVAL;
     if (n_sc == 0) return VP_OK;
-    if (!W || !perm || !s || !paths || !l || !cost || !kidx) return VP_EINVAL;
+    if (!W || !perm || !s || !tau || !paths || !l || !cost || !kidx) return VP_EINVAL;
     return launch_search((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K, paths_sc_stride, n_sc,
                          n_sym,
                          n_r, flags, l, cost, kidx, (hipStream_t)stream);
 }
 
-int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, const uint8_t *paths,
+int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau, const uint8_t *paths,
                        const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r,
                        uint32_t flags, const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost,
                        int32_t *kidx, void *work, void *stream) {
-    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1) return VP_EINVAL;
     if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
     if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
     if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;
     if (flags & ~(uint32_t)VP_INCLUDE_ZERO) return VP_EINVAL;
     if (isnan(theta) || kidx_base < 0) return VP_EINVAL;
     if (n_sc == 0) return VP_OK;
-    if (!W || !perm || !s || !paths || !mass || !l || !cost || !kidx || !work) return VP_EINVAL;
+    if (!W || !perm || !s || !tau || !paths || !mass || !l || !cost || !kidx || !work) return VP_EINVAL;
     if (reinterpret_cast<uintptr_t>(work) & 3) return VP_EINVAL;
     return launch_search_fallback((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K, paths_sc_stride,
                                   n_sc, n_sym, n_r, flags, mass, theta, kidx_base, l, cost, kidx, work,
                                   (hipStream_t)stream);
 }
 
-int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, float tau, const float *cost, int n_sc, int n_sym,
-               int n_r, int n_t, float P_T, vp_c32 *x, void *stream) {
-    if (n_sc < 0 || n_sym < 1 || n_r < 1 || n_t < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;
+int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, const float *tau, const float *cost, int n_sc,
+               int n_sym, int n_r, int n_t, float P_T, vp_c32 *x, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || n_t < 1) return VP_EINVAL;
     if (!(P_T >= 0.f) || !isfinite(P_T)) return VP_EINVAL;
     if (n_r > kMaxN || n_t > kMaxM) return VP_EUNSUPPORTED;
     if (n_sc == 0) return VP_OK;
-    if (!G || !s || !l || !x || (P_T > 0.f && !cost)) return VP_EINVAL;
+    if (!G || !s || !l || !tau || !x || (P_T > 0.f && !cost)) return VP_EINVAL;
     return launch_precode((const float2 *)G, (const float2 *)s, l, tau, cost, n_sc, n_sym, n_r, n_t, P_T,
                           (float2 *)x, (hipStream_t)stream);
 }
 
 int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym,
                      int n_r, const float *radius, int64_t max_nodes, int8_t *l, float *cost, int64_t *nodes,
-                     void *stream) {
+                     uint8_t *status, void *stream) {
     if (n_sc < 0 || n_sym < 1 || n_r < 1 || !(tau > 0.f) || !isfinite(tau) || max_nodes <= 0) return VP_EINVAL;
     if (n_r > kMaxN) return VP_EUNSUPPORTED;
     if (n_sc == 0) return VP_OK;
     if (!W || !perm || !s || !l || !cost) return VP_EINVAL;
     return launch_sphere((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, radius, l, cost, nodes,
-                         (long long)max_nodes, (hipStream_t)stream);
+                         status, (long long)max_nodes, (hipStream_t)stream);
 }
 
 int vp_mlp_features(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym, int n_r,

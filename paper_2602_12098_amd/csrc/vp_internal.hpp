@@ -76,19 +76,20 @@ int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, floa
                       uint8_t *perm, float2 *G, int32_t *status, hipStream_t st);
 int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st);
 int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st);
-int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                   const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                   int8_t *l, float *cost, int32_t *kidx, hipStream_t st);
-int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau,
+                           const uint8_t *paths,
                            const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                            const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
                            void *work, hipStream_t st);
-int launch_precode(const float2 *G, const float2 *s, const int8_t *l, float tau, const float *cost,
+int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost,
                    int n_sc, int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st);
 
 int launch_sphere(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
-                  const float *radius, int8_t *l, float *cost, int64_t *nodes, long long max_nodes,
-                  hipStream_t st);
+                  const float *radius, int8_t *l, float *cost, int64_t *nodes, uint8_t *status,
+                  long long max_nodes, hipStream_t st);
 
 // Batched workload: one descriptor per group of subcarriers that share the
 // number of users, perturbation interval, regularisation and path count.

@@ -1,5 +1,5 @@
 // Linear precoding of the perturbed vector (Alg. 2 output; Sec. IV-B
-// channel-inverse, gamma and PV blocks): x = G (s + tau l), optionally scaled
+// channel-inverse, gamma and PV blocks): x = G (s + tau l), tau per subcarrier, optionally scaled
 // by sqrt(P_T / gamma) with gamma the selected search cost (Sec. II-B).
 //
 // One workgroup per subcarrier and up to kVB of its vectors: the
@@ -15,7 +15,7 @@ constexpr int kT = 256;
 constexpr int kVB = 16;   // vectors per workgroup
 
 __global__ __launch_bounds__(kT) void k_precode(const float2 *__restrict__ G, const float2 *__restrict__ s,
-                                                const int8_t *__restrict__ l, float tau,
+                                                const int8_t *__restrict__ l, const float *__restrict__ taus,
                                                 const float *__restrict__ cost, int n_sc, int n_sym, int N,
                                                 int M, float P_T, float2 *__restrict__ x) {
     __shared__ float2 sG[kMaxM][kMaxN + 1];   // padded rows: lanes of different antennas hit different banks
@@ -28,6 +28,8 @@ __global__ __launch_bounds__(kT) void k_precode(const float2 *__restrict__ G, co
     const size_t vb = (size_t)sc * n_sym + v0;
     const int t = threadIdx.x;
     const float2 *__restrict__ g = G + (size_t)sc * M * N;
+    float tau = taus[sc];
+    if (!(tau > 0.f) || !isfinite(tau)) tau = __int_as_float(0x7fc00000);   // an invalid tau gives x = NaN
     for (int e = t; e < M * N; e += kT) sG[e / N][e % N] = g[e];
     for (int e = t; e < N * nv; e += kT) {   // consecutive lanes: consecutive vectors of one user
         const int i = e / nv, vl = e % nv;
@@ -58,7 +60,7 @@ __global__ __launch_bounds__(kT) void k_precode(const float2 *__restrict__ G, co
 
 }  // namespace
 
-int launch_precode(const float2 *G, const float2 *s, const int8_t *l, float tau, const float *cost, int n_sc,
+int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost, int n_sc,
                    int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st) {
     if ((size_t)n_sc * n_sym * M == 0) return VP_OK;
     const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVB - 1) / kVB);

@@ -9,7 +9,8 @@
 // tried in increasing squared distance (equal distances in canonical box
 // order), so the first child whose PED reaches the best cost ends the level.
 // The search radius may be seeded (e.g. with the K-path result), which only
-// prunes: the minimum found is the same.
+// prunes: the minimum found is the same.  A vector that runs out of its node
+// budget keeps the best point found so far (its status says so).
 #include "vp_internal.hpp"
 
 #define VP_LUT_STORAGE static __constant__
@@ -25,7 +26,7 @@ __global__ __launch_bounds__(kT) void k_sphere(const float2 *__restrict__ W, con
                                                const float2 *__restrict__ s, float tau, int n_sc, int n_sym,
                                                const float *__restrict__ radius, int8_t *__restrict__ l_out,
                                                float *__restrict__ cost_out, int64_t *__restrict__ nodes_out,
-                                               long long max_nodes) {
+                                               uint8_t *__restrict__ status_out, long long max_nodes) {
     constexpr int NP = VP_PACKED(N);
     const size_t n_vec = (size_t)n_sc * n_sym;
     const size_t v = (size_t)blockIdx.x * kT + threadIdx.x;
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(kT) void k_sphere(const float2 *__restrict__ W, con
     for (int i = 0; i < N; ++i) la[i] = lb[i] = 0.f;
     float best = radius ? radius[v] : __int_as_float(0x7f800000);
     long long nodes = 0;
-    bool found = false;
+    bool found = false, cut = false;
     if (w00 > 0.f && isfinite(w00)) {
         const float inv_tau = 1.0f / tau;
         float st[2 * N];   // s-tilde / tau
@@ -112,12 +113,15 @@ __global__ __launch_bounds__(kT) void k_sphere(const float2 *__restrict__ W, con
                 }
             }
             if (up) {
-                if (i == 0 || nodes >= max_nodes) break;
+                if (i == 0) break;   // the root's children are done: the search is complete
+                if (nodes >= max_nodes) {
+                    cut = true;
+                    break;
+                }
                 --i;
                 ++rk[i];
             }
         }
-        if (nodes >= max_nodes) found = false;
     }
     const size_t base = v;
 #pragma unroll
@@ -129,27 +133,29 @@ __global__ __launch_bounds__(kT) void k_sphere(const float2 *__restrict__ W, con
     }
     cost_out[v] = found ? best : __int_as_float(0x7fc00000);
     if (nodes_out) nodes_out[v] = nodes;
+    if (status_out)
+        status_out[v] = cut ? (uint8_t)VP_SE_EXHAUSTED : (found ? (uint8_t)VP_SE_EXACT : (uint8_t)VP_SE_NONE);
 }
 
 template <int N>
 int launch_sphere_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym,
-                    const float *radius, int8_t *l, float *cost, int64_t *nodes, long long max_nodes,
-                    hipStream_t st) {
+                    const float *radius, int8_t *l, float *cost, int64_t *nodes, uint8_t *status,
+                    long long max_nodes, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
     hipLaunchKernelGGL(k_sphere<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s, tau, n_sc,
-                       n_sym, radius, l, cost, nodes, max_nodes);
+                       n_sym, radius, l, cost, nodes, status, max_nodes);
     return launch_status();
 }
 
 }  // namespace
 
 int launch_sphere(const float2 *W, const uint8_t *perm, const float2 *s, float tau, int n_sc, int n_sym, int N,
-                  const float *radius, int8_t *l, float *cost, int64_t *nodes, long long max_nodes,
-                  hipStream_t st) {
+                  const float *radius, int8_t *l, float *cost, int64_t *nodes, uint8_t *status,
+                  long long max_nodes, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
     switch (N) {
 #define VP_CASE(n) \
-    case n: return launch_sphere_n<n>(W, perm, s, tau, n_sc, n_sym, radius, l, cost, nodes, max_nodes, st);
+    case n: return launch_sphere_n<n>(W, perm, s, tau, n_sc, n_sym, radius, l, cost, nodes, status, max_nodes, st);
         VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
         VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
 #undef VP_CASE

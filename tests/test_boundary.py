@@ -61,17 +61,18 @@ def test_argument_validation(lib):
     assert lib.vp_paths_mop(None, 1, 16, 0, None, None, None) == VP_EINVAL
     assert lib.vp_paths_mop(None, 0, 4, 32, None, None, None) == VP_OK
     assert lib.vp_paths_mop(None, 3, 4, 32, None, None, None) == VP_EINVAL          # null pointers
-    # vp_search
-    args = dict(tau=8.0, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1)
+    # vp_search (tau is a per-subcarrier device array: a NULL tau is an
+    # argument error, its values are data, checked per subcarrier on the GPU)
+    P = ctypes.c_void_p(16)   # non-NULL, never dereferenced (every call below fails its checks or has n_sc = 0)
+    args = dict(tau=P, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1)
 
-    def search(**kw):
+    def search(Q=None, **kw):
         a = dict(args, **kw)
-        return lib.vp_search(None, None, None, a["tau"], None, a.get("lex"), a["K"], a["stride"], a["n_sc"],
-                             a["n_sym"], a["N"], a["flags"], None, None, None, None)
+        return lib.vp_search(Q, Q, Q, a["tau"], Q, a.get("lex"), a["K"], a["stride"], a["n_sc"],
+                             a["n_sym"], a["N"], a["flags"], Q, Q, Q, None)
     assert search() == VP_EINVAL
     assert search(n_sc=0) == VP_OK
-    assert search(tau=0.0, n_sc=0) == VP_EINVAL
-    assert search(tau=float("inf"), n_sc=0) == VP_EINVAL
+    assert search(P, tau=None) == VP_EINVAL
     assert search(N=17, n_sc=0) == VP_EUNSUPPORTED
     assert search(K=4097, n_sc=0) == VP_EUNSUPPORTED
     assert search(stride=5, n_sc=0) == VP_EINVAL      # 0 < stride < K*N
@@ -80,14 +81,13 @@ def test_argument_validation(lib):
     assert search(n_sym=0, n_sc=0) == VP_EINVAL
     assert search(lex=1, stride=0, n_sc=0) == VP_EINVAL       # lexorder needs a per-subcarrier table
     # vp_search_fallback: the checks of vp_search, plus mass, theta, kidx_base and work
-    fargs = dict(tau=8.0, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1, theta=0.5, base=72)
+    fargs = dict(tau=P, K=32, stride=0, n_sc=1, n_sym=14, N=4, flags=1, theta=0.5, base=72)
 
     def fallback(P=None, **kw):
         a = dict(fargs, **kw)
         return lib.vp_search_fallback(P, P, P, a["tau"], P, a.get("lex"), a["K"], a["stride"], a["n_sc"],
                                       a["n_sym"], a["N"], a["flags"], a.get("mass", P), a["theta"], a["base"],
                                       P, P, P, a.get("work", P), None)
-    P = ctypes.c_void_p(16)   # non-NULL, never dereferenced (every call below fails its checks or has n_sc = 0)
     assert fallback() == VP_EINVAL
     assert fallback(n_sc=0) == VP_OK
     assert fallback(P, mass=None) == VP_EINVAL
@@ -96,17 +96,18 @@ def test_argument_validation(lib):
     assert fallback(P, theta=float("nan")) == VP_EINVAL
     assert fallback(P, base=-1) == VP_EINVAL
     assert fallback(P, flags=2) == VP_EINVAL                               # VP_PATHS_PER_VECTOR
-    assert fallback(P, tau=0.0) == VP_EINVAL
+    assert fallback(P, tau=None) == VP_EINVAL
     assert fallback(P, N=17) == VP_EUNSUPPORTED
     assert fallback(P, K=4097) == VP_EUNSUPPORTED
     assert fallback(P, stride=5) == VP_EINVAL
     assert fallback(P, lex=P, stride=0) == VP_EINVAL
     assert fallback(theta=float("inf"), n_sc=0) == VP_OK
     # vp_precode
-    assert lib.vp_precode(None, None, None, 8.0, None, 0, 14, 4, 4, 0.0, None, None) == VP_OK
-    assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 4, 4, 1.0, None, None) == VP_EINVAL
-    assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 4, 4, -1.0, None, None) == VP_EINVAL
-    assert lib.vp_precode(None, None, None, 8.0, None, 1, 14, 17, 4, 0.0, None, None) == VP_EUNSUPPORTED
+    assert lib.vp_precode(None, None, None, P, None, 0, 14, 4, 4, 0.0, None, None) == VP_OK
+    assert lib.vp_precode(None, None, None, P, None, 1, 14, 4, 4, 1.0, None, None) == VP_EINVAL
+    assert lib.vp_precode(P, P, P, None, P, 1, 14, 4, 4, 1.0, P, None) == VP_EINVAL       # NULL tau
+    assert lib.vp_precode(None, None, None, P, None, 1, 14, 4, 4, -1.0, None, None) == VP_EINVAL
+    assert lib.vp_precode(None, None, None, P, None, 1, 14, 17, 4, 0.0, None, None) == VP_EUNSUPPORTED
     assert lib.vp_strerror(VP_EINVAL) == b"invalid argument"
     assert lib.vp_last_hip_error() == 0
     _ = F

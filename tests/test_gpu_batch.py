@@ -15,7 +15,7 @@ import pytest
 
 import vpgen
 from oracle import vp_oracle as O
-from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W
+from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W, record
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -115,6 +115,7 @@ def test_batch_matches_oracle_and_per_call(mods):
             check_search_subcarrier(rep, Wd[sc], perm[sc], wl.s[gi][:, sl].astype(np.complex128), b.groups[gi].tau,
                                     P[sc], True, lg[sl], cg[sl], kidx[sl])
     _say(rep)
+    record("batched-groups", rep)
     assert rep.ok(), rep.failures[:4]
     assert rep.exact >= 0.98 * rep.n
     info = b.info()

@@ -12,7 +12,7 @@ import vpgen
 from oracle import mlp_oracle as L
 from oracle import vp_oracle as O
 from tests import mlp_bounds as MB
-from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W
+from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W, record
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -373,6 +373,7 @@ def test_search_per_vector_tables(lib, N, Q, K):
         check_search_subcarrier(rep, Wd[sc], perm[sc], wl.s[:, sl].astype(np.complex128), wl.tau, tables[v], True,
                                 l[sl], cost[sl], kidx[sl])
     _say(rep)
+    record("learned-tables", rep)
     assert rep.ok(), rep.failures[:4]
     assert rep.exact >= 0.98 * rep.n
 

@@ -11,7 +11,7 @@ import pytest
 
 import vpgen
 from oracle import vp_oracle as O
-from tests.vp_parity import ParityReport, check_search_subcarrier, l_from_gpu, unpack_W
+from tests.vp_parity import ParityReport, check_search_subcarrier, count, l_from_gpu, record, unpack_W
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -56,7 +56,7 @@ def host(t):
     return t.detach().cpu().numpy()
 
 
-def check_same_input(vp, wl, prep, paths, out, scs, include_zero=True, n_sym=None):
+def check_same_input(vp, wl, prep, paths, out, scs, include_zero=True, n_sym=None, kind="same-input"):
     n_sym = n_sym or wl.n_sym
     N = wl.N
     Wd = unpack_W(host(prep.W), N)
@@ -69,6 +69,7 @@ def check_same_input(vp, wl, prep, paths, out, scs, include_zero=True, n_sym=Non
         sl = slice(sc * n_sym, (sc + 1) * n_sym)
         check_search_subcarrier(rep, Wd[sc], perm[sc], wl.s[:, sl].astype(np.complex128), wl.tau, P[sc],
                                 include_zero, l[sl], cost[sl], kidx[sl])
+    record(kind, rep)
     return rep
 
 
@@ -180,37 +181,129 @@ def test_cfg3_full_size_sampled(vp):
     P = host(paths)
     for sc in scs[:4]:
         assert np.array_equal(P[sc], O.mop_paths_kbest(w2[sc], 512))
-    rep = check_same_input(vp, wl, prep, paths, out, scs)
+    rep = check_same_input(vp, wl, prep, paths, out, scs, kind="full-launch-sampled")
     _say(rep)
     assert rep.ok(), rep.failures[:5]
-    # every vector: the cost never exceeds the plain RZF (l = 0) cost, and l in the box
+    # every vector of the launch: l in the box, a valid index, and (the zero
+    # perturbation competes) a cost never above the plain RZF cost ||W s_pi||^2,
+    # formed here in float64 from the GPU's own W
     l = host(out.l)
     assert l.min() >= -1 and l.max() <= 1
-    assert np.all(host(out.kidx) >= 0) and np.all(host(out.kidx) <= 512)
+    kidx = host(out.kidx)
+    assert np.all(kidx >= 0) and np.all(kidx <= 512)
+    Wd = unpack_W(host(prep.W), wl.N)
+    perm = host(prep.perm).astype(np.int64)
+    S = wl.s.astype(np.complex128).T.reshape(wl.n_sc, wl.n_sym, wl.N)
+    Sp = np.take_along_axis(S, perm[:, None, :].repeat(wl.n_sym, 1), axis=2)
+    rzf = (np.abs(np.einsum("cij,csj->csi", Wd, Sp)) ** 2).sum(axis=2).reshape(-1)
+    cost = host(out.cost).astype(np.float64)
+    above = int(np.sum(cost > rzf * (1 + 1e-5)))
+    count("full-launch-sampled", "cost_above_rzf", above)
+    assert above == 0, above
+
+
+def _mop_boundary_ties(w2, a, b):
+    """True if the path tables a and b (both claiming the K smallest Metric-of-
+    Promise values for weights w2) differ only in rows whose metric lies within
+    1e-5 (relative) of the K-th smallest value: a tie at the K boundary that
+    float32 and float64 weights may resolve differently."""
+    ma = np.array([O.mop_value(w2, r) for r in a])
+    mb = np.array([O.mop_value(w2, r) for r in b])
+    kth = max(ma.max(), mb.max())
+    diff = set(map(tuple, a)) ^ set(map(tuple, b))
+    return all(abs(O.mop_value(w2, r) - kth) <= 1e-5 * kth for r in diff)
 
 
 def test_end_to_end_from_H(vp):
+    # The oracle preprocesses H itself (float64) and picks its own path set.
+    # Each GPU result is then judged by the same-input rule with the oracle's
+    # float64 W and perm: bit-exact l, else a cost tie, else an order tie --
+    # the GPU's own winning path, re-walked with near-tied DEMAP decisions
+    # relaxed, must reach the GPU's l, whose cost must not exceed any path's.
+    # Flagged and counted: a user order that differs only by a near-tied pivot
+    # (then the GPU is judged same-input, on its own W), and path sets that
+    # differ only by Metric-of-Promise ties at the K boundary (then the GPU's
+    # set is the one walked).
     wl = vpgen.cfg3(256, n_sc=12)
     prep, paths, out, _ = run_pipeline(vp, wl)
     l = l_from_gpu(host(out.l))
-    cost = host(out.cost)
+    cost, kidx = host(out.cost), host(out.kidx)
     P = host(paths)
-    mism = 0
+    Wg = unpack_W(host(prep.W), wl.N)
+    permg = host(prep.perm).astype(np.int64)
+    rep, rep_self = ParityReport(), ParityReport()
+    pivot_flags = mop_flags = 0
     for sc in range(wl.n_sc):
         ref = O.preprocess(wl.H[sc], wl.alpha)
+        sl = slice(sc * wl.n_sym, (sc + 1) * wl.n_sym)
+        s_sc = wl.s[:, sl].astype(np.complex128)
+        if not np.array_equal(ref.perm, permg[sc]):
+            assert np.min(ref.pivot_margin) <= 1e-4 * np.max(ref.pivots), sc
+            pivot_flags += 1
+            check_search_subcarrier(rep_self, Wg[sc], permg[sc], s_sc, wl.tau, P[sc], True, l[sl], cost[sl],
+                                    kidx[sl])
+            continue
         refp = O.mop_paths_kbest(ref.w2, 256)
-        sl = slice(sc * 14, (sc + 1) * 14)
-        res = O.search_paths(ref.W, ref.perm, wl.s[:, sl], wl.tau, refp)
-        same_set = np.array_equal(refp, P[sc])
-        for v in range(14):
-            c64 = O.cost_closed_form(O.gram(wl.H[sc], wl.alpha), wl.s[:, sl][:, v], l[sl][v], wl.tau)
-            assert abs(cost[sl][v] - c64) <= 1e-5 * c64 * 4
-            if not np.array_equal(l[sl][v], res.l[v]):
-                if abs(c64 - res.cost[v]) > 1e-5 * res.cost[v]:
-                    mism += 1
-                    assert (not same_set) or np.min(res.margin[v]) <= 1e-2, (sc, v)
-    _say("end-to-end mismatches (pivot / path-set / order near ties):", mism)
-    assert mism <= 3
+        if not np.array_equal(refp, P[sc]):
+            assert _mop_boundary_ties(ref.w2, refp, P[sc]), sc
+            mop_flags += 1
+        # the cost of l is taken from the float64 factorisation of H, the GPU's
+        # from its float32 one: their W differ by the float32 preprocessing
+        # error, which this bound allows on top of the search's 1e-5
+        check_search_subcarrier(rep, ref.W, ref.perm, s_sc, wl.tau, P[sc], True, l[sl], cost[sl], kidx[sl],
+                                cost_rtol=4e-5)
+    record("end-to-end", rep)
+    record("end-to-end-pivot-flagged", rep_self)
+    count("end-to-end", "pivot_tie_subcarriers", pivot_flags)
+    count("end-to-end", "mop_boundary_subcarriers", mop_flags)
+    _say("end-to-end", rep, "| pivot-flagged", rep_self, "| mop-boundary subcarriers", mop_flags)
+    assert rep.ok(), rep.failures[:5]
+    assert rep_self.ok(), rep_self.failures[:5]
+    assert rep.exact >= 0.99 * rep.n
+    assert pivot_flags <= 1 and mop_flags <= 1
+
+
+def test_overloaded_regularised_N_gt_M(vp):
+    # more users than antennas (N = 16, M = 8): only the regularised Gram
+    # matrix A = H H^H + alpha I is positive definite (the Tikhonov extension
+    # of Sec. III-A-1).  Preprocess, MoP, search and precode against the oracle.
+    rng = np.random.default_rng(1608)
+    N, M, n_sc, n_sym, K, alpha = 16, 8, 10, 14, 256, 0.16
+    H = vpgen.draw_rayleigh(rng, n_sc, N, M)
+    s = vpgen.draw_symbols(rng, N, n_sc * n_sym, 256)
+    wl = vpgen.Workload("overloaded-16x8", N, M, n_sc, n_sym, 256, alpha, K, H, s, 1608)
+    prep, paths, out, sd = run_pipeline(vp, wl)
+    assert np.all(host(prep.status) == 0)
+    Wd = unpack_W(host(prep.W), N)
+    permg = host(prep.perm).astype(np.int64)
+    w2 = host(prep.w2).astype(np.float64)
+    Gg = host(prep.G).astype(np.complex128)
+    P = host(paths)
+    refs = [O.preprocess(H[sc], alpha) for sc in range(n_sc)]
+    for sc, ref in enumerate(refs):
+        if np.array_equal(ref.perm, permg[sc]):
+            scale = np.abs(ref.W).max()
+            assert np.abs(Wd[sc] - ref.W).max() <= 2e-5 * scale * N, sc
+            assert np.abs(Gg[sc] - ref.G).max() <= 2e-5 * np.abs(ref.G).max() * N, sc
+        else:
+            assert np.min(ref.pivot_margin) <= 1e-4 * np.max(ref.pivots), sc
+        assert np.array_equal(P[sc], O.mop_paths_kbest(w2[sc], K)), sc
+    rep = check_same_input(vp, wl, prep, paths, out, range(n_sc), kind="overloaded-N>M")
+    _say(rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.99 * rep.n
+    x = host(vp.precode(prep.G, sd, out.l, wl.tau, out.cost, n_sym))
+    l = l_from_gpu(host(out.l))
+    cost = host(out.cost)
+    for v in range(wl.n_vec):
+        sc = v // n_sym
+        u = s[:, v].astype(np.complex128) + wl.tau * l[v]
+        xr = O.precode(refs[sc].G, s[:, v], l[v], wl.tau)
+        assert np.abs(x[v] - xr).max() <= 1e-4 * np.abs(xr).max(), v
+        # gamma = ||x||^2 + alpha ||A^-1 u||^2: the regulariser's share of the cost
+        Ainv_u = np.linalg.solve(O.gram(H[sc], alpha), u)
+        gam = float(np.vdot(xr, xr).real + alpha * np.vdot(Ainv_u, Ainv_u).real)
+        assert math.isclose(gam, float(cost[v]), rel_tol=1e-4), v
 
 
 def test_precode_parity_and_invariants(vp):
@@ -348,6 +441,7 @@ def test_sphere_encoder_matches_oracle(vp):
             lg = l_from_gpu(host(se.l))
             cg = host(se.cost)
             assert np.all(np.isfinite(cg))
+            assert np.all(host(se.status) == vp.VP_SE_EXACT)
             ties = 0
             for v in range(wl.n_vec):
                 c64 = O.cost_tri(Wd[v // wl.n_sym], perm[v // wl.n_sym], wl.s[:, v], lg[v], wl.tau)
@@ -423,3 +517,81 @@ def test_trie_search_any_table_is_bit_identical(vp, N, K, hi, n_sym):
     b = vp.search(prep.W, prep.perm, sd, tau, pd, n_sym)
     torch.cuda.synchronize()
     assert torch.equal(a.cost, b.cost) and torch.equal(a.kidx, b.kidx) and torch.equal(a.l, b.l)
+
+
+@pytest.mark.parametrize("shared_prefix", [True, False])
+def test_mixed_tau_across_subcarriers(vp, shared_prefix):
+    # one call whose subcarriers carry different QAM orders, tau = 2 sqrt(Q)
+    # per subcarrier (Sec. II-B); one subcarrier gets an invalid tau and must
+    # come back as a failed subcarrier (l = 0, cost NaN, kidx -1, x NaN)
+    rng = np.random.default_rng(2026)
+    N, n_sc, n_sym, K, alpha = 8, 17, 7, 64, 0.08
+    Qs = np.array([4, 16, 64, 256])[rng.integers(0, 4, n_sc)]
+    H = vpgen.draw_rayleigh(rng, n_sc, N, N)
+    s = np.concatenate([vpgen.draw_symbols(rng, N, n_sym, int(q)) for q in Qs], axis=1)
+    taus = np.array([vpgen.qam_tau(int(q)) for q in Qs], np.float32)
+    bad = 5
+    taus_dev = taus.copy()
+    taus_dev[bad] = -1.0
+    Hd, sd, td = _to_dev(H), _to_dev(s), _to_dev(taus_dev)
+    prep = vp.preprocess(Hd, alpha)
+    order = torch.empty((n_sc, 2, K), dtype=torch.int16, device=DEV) if shared_prefix else None
+    paths = vp.paths_mop(prep.w2, K, order=order)
+    out = vp.search(prep.W, prep.perm, sd, td, paths, n_sym, order=order)
+    x = host(vp.precode(prep.G, sd, out.l, td, out.cost, n_sym))
+    torch.cuda.synchronize()
+    Wd = unpack_W(host(prep.W), N)
+    perm = host(prep.perm).astype(np.int64)
+    P = host(paths)
+    l = l_from_gpu(host(out.l))
+    cost, kidx = host(out.cost), host(out.kidx)
+    G = host(prep.G).astype(np.complex128)
+    rep = ParityReport()
+    for sc in range(n_sc):
+        sl = slice(sc * n_sym, (sc + 1) * n_sym)
+        if sc == bad:
+            assert np.all(np.isnan(cost[sl])) and np.all(kidx[sl] == -1) and not np.any(l[sl])
+            assert np.all(np.isnan(x[sl]))
+            continue
+        check_search_subcarrier(rep, Wd[sc], perm[sc], s[:, sl].astype(np.complex128), float(taus[sc]), P[sc],
+                                True, l[sl], cost[sl], kidx[sl])
+        for v in range(sl.start, sl.stop):
+            xr = G[sc] @ (s[:, v] + float(taus[sc]) * l[v])
+            assert np.abs(x[v] - xr).max() <= 1e-5 * np.abs(xr).max() * 4, v
+    record("mixed-tau", rep)
+    _say("mixed tau", rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.99 * rep.n
+
+
+def test_sphere_encoder_budget_keeps_the_best_point(vp):
+    # a node budget far below what the 16x16 search needs: the encoder stops,
+    # says so, and returns the best point found so far -- a valid l whose
+    # float64 cost matches the reported one and is never below the exact
+    # optimum (the oracle's C sphere encoder)
+    from oracle import se_c
+    wl = vpgen.cfg3(512, n_sc=4)
+    prep, paths, out, sd = run_pipeline(vp, wl)
+    Wd = unpack_W(host(prep.W), wl.N)
+    perm = host(prep.perm).astype(np.int64)
+    wsel = np.repeat(np.arange(wl.n_sc), wl.n_sym).astype(np.int32)
+    _, co, _ = se_c.sphere_encode_batch(Wd, perm, wl.s, wl.tau, wsel=wsel)
+    se = vp.sphere_encode(prep.W, prep.perm, sd, wl.tau, wl.n_sym, max_nodes=200)
+    full = vp.sphere_encode(prep.W, prep.perm, sd, wl.tau, wl.n_sym)
+    torch.cuda.synchronize()
+    st, cg, lg = host(se.status), host(se.cost), l_from_gpu(host(se.l))
+    assert np.all(host(full.status) == vp.VP_SE_EXACT)
+    assert np.sum(st == vp.VP_SE_EXHAUSTED) > 0
+    assert np.all(np.isin(st, [vp.VP_SE_EXACT, vp.VP_SE_EXHAUSTED]))
+    assert np.all(np.isfinite(cg))   # without a radius the first dive always finds a point
+    for v in range(wl.n_vec):
+        c64 = O.cost_tri(Wd[v // wl.n_sym], perm[v // wl.n_sym], wl.s[:, v], lg[v], wl.tau)
+        assert abs(cg[v] - c64) <= 1e-5 * c64, v
+        assert c64 >= co[v] * (1 - 1e-5), v
+        if st[v] == vp.VP_SE_EXACT:
+            assert abs(c64 - co[v]) <= 1e-5 * co[v], v
+    # a radius below the exact optimum: nothing inside, status NONE
+    tiny = vp.sphere_encode(prep.W, prep.perm, sd, wl.tau, wl.n_sym, radius=full.cost * 0.5)
+    torch.cuda.synchronize()
+    assert np.all(host(tiny.status) == vp.VP_SE_NONE) and np.all(np.isnan(host(tiny.cost)))
+    assert not np.any(host(tiny.l))

@@ -23,6 +23,28 @@ from oracle import vp_oracle as O
 COST_RTOL = 1e-5
 TIE_EPS = 1e-4        # squared-distance units of the normalised level centre
 
+# Totals over every parity check of a test session, printed at the end of the
+# run (tests/conftest.py) so that tie and mismatch counts appear in the log.
+TOTALS: dict = {}
+
+
+def record(kind: str, rep: "ParityReport") -> None:
+    """Add one report to the session totals under `kind`."""
+    t = TOTALS.setdefault(kind, {"n": 0, "exact": 0, "cost_ties": 0, "order_ties": 0, "failures": 0,
+                                 "max_cost_rel_err": 0.0})
+    t["n"] += rep.n
+    t["exact"] += rep.exact
+    t["cost_ties"] += rep.cost_ties
+    t["order_ties"] += rep.order_ties
+    t["failures"] += len(rep.failures)
+    t["max_cost_rel_err"] = max(t["max_cost_rel_err"], rep.max_cost_rel_err)
+
+
+def count(kind: str, key: str, k: int = 1) -> None:
+    """Add k to a named counter of the session totals (e.g. flagged pivot ties)."""
+    TOTALS.setdefault(kind, {}).setdefault(key, 0)
+    TOTALS[kind][key] += k
+
 
 def unpack_W(Wp: np.ndarray, N: int) -> np.ndarray:
     """Packed column-major lower [..., N(N+1)/2] -> dense lower [..., N, N]."""
@@ -88,9 +110,13 @@ class ParityReport:
 
 
 def check_search_subcarrier(rep: ParityReport, W, perm, s_user, tau, paths, include_zero,
-                            l_gpu, cost_gpu, kidx_gpu):
+                            l_gpu, cost_gpu, kidx_gpu, cost_rtol: float = COST_RTOL):
     """Compare one subcarrier's GPU results (l_gpu complex [V][N], cost [V], kidx [V])
-    with the oracle's same-path-set search on the same (upcast) inputs."""
+    with the oracle's same-path-set search on the same (upcast) inputs.
+
+    cost_rtol bounds the reported cost against the float64 cost of l_gpu; it
+    is 1e-5 for same-input parity and larger only where W itself comes from a
+    different (float64) factorisation of H (end-to-end parity)."""
     W = np.asarray(W, np.complex128)
     perm = np.asarray(perm, np.int64)
     paths = np.asarray(paths, np.int64)
@@ -103,7 +129,7 @@ def check_search_subcarrier(rep: ParityReport, W, perm, s_user, tau, paths, incl
         c64_g = O.cost_tri(W, perm, s_user[:, v], lg, tau)
         rel = abs(float(cost_gpu[v]) - c64_g) / max(c64_g, 1e-30)
         rep.max_cost_rel_err = max(rep.max_cost_rel_err, rel)
-        if not rel <= COST_RTOL:
+        if not rel <= cost_rtol:
             rep.failures.append((v, "cost", float(cost_gpu[v]), c64_g))
             continue
         c_orc = float(res.cost[v])
