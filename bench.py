@@ -158,13 +158,13 @@ def bench_batched(vp, steps, warmup):
         H = torch.from_numpy(np.concatenate([wl.H[i] for i in idx])).to("cuda:0")
         sg = torch.from_numpy(np.concatenate([wl.s[i] for i in idx], axis=1)).to("cuda:0")
         per.append((H, sg, vp.tau_array(float(vpgen.qam_tau(q)), H.shape[0], "cuda:0"), float(u) / 100.0,
-                    int(kcal[str(u)])))
+                    int(kcal[str(u)]), float(vpgen.qam_tau(q))))
 
     def per_size(min_K_sharing=None):
         """One call per stage and (U, QAM) group; with min_K_sharing, groups
         with K >= it pass the MoP orders to vp_search (prefix sharing)."""
         outs = []
-        for H, sg, tau, alpha, K in per:
+        for H, sg, tau, alpha, K, _ in per:
             prep = vp.preprocess(H, alpha)
             share = min_K_sharing is not None and K >= min_K_sharing
             order = torch.empty((H.shape[0], 2, K), dtype=torch.int16, device="cuda:0") if share else None
@@ -178,7 +178,7 @@ def bench_batched(vp, steps, warmup):
     ms_per_size_shared = timed(lambda: per_size(64))
     ms_per_size = min(ms_per_size_plain, ms_per_size_shared)
     num = den = 0.0
-    for (H, sg, tau, alpha, K), (prep, o) in zip(per, per_size()):
+    for (H, sg, _, alpha, K, tau), (prep, o) in zip(per, per_size()):
         g, exact = gap_to_exact(vp, prep, sg, tau, wl.n_sym, o.cost)
         num += float(o.cost.double().sum())
         den += float(exact.sum())

@@ -388,7 +388,9 @@ def test_search_per_vector_rejects_bad_args(lib):
         vp.search(prep.W, prep.perm, dev(wl.s), wl.tau, tables[:2], wl.n_sym, flags=vp.VP_PATHS_PER_VECTOR)
     lib_ = _lib.load()
     out = vp.search(prep.W, prep.perm, dev(wl.s), wl.tau, tables, wl.n_sym, flags=vp.VP_PATHS_PER_VECTOR)
-    rc = lib_.vp_search(prep.W.data_ptr(), prep.perm.data_ptr(), dev(wl.s).data_ptr(), wl.tau, tables.data_ptr(),
+    taus = vp.tau_array(wl.tau, wl.n_sc, DEV)
+    rc = lib_.vp_search(prep.W.data_ptr(), prep.perm.data_ptr(), dev(wl.s).data_ptr(), taus.data_ptr(),
+                        tables.data_ptr(),
                         None, 8, 0, 2, 2, 4, vp.VP_PATHS_PER_VECTOR, out.l.data_ptr(), out.cost.data_ptr(),
                         out.kidx.data_ptr(), None)
     assert rc == _lib.VP_EINVAL

@@ -394,8 +394,13 @@ def test_errors_are_reported(vp):
     prep, paths, out, sd = run_pipeline(vp, wl)
     with pytest.raises(VPError):
         vp.paths_mop(prep.w2, 9 ** 4 + 1)
-    with pytest.raises(VPError):
-        vp.search(prep.W, prep.perm, sd, -1.0, paths, wl.n_sym)
+    # tau is per-subcarrier data: a wrongly shaped array is an argument error,
+    # a non-positive value fails its subcarrier (cost NaN, kidx -1)
+    with pytest.raises(ValueError):
+        vp.search(prep.W, prep.perm, sd, torch.full((3,), 8.0, device=DEV), paths, wl.n_sym)
+    bad = vp.search(prep.W, prep.perm, sd, -1.0, paths, wl.n_sym)
+    torch.cuda.synchronize()
+    assert torch.all(torch.isnan(bad.cost)) and torch.all(bad.kidx == -1) and not torch.any(bad.l)
     with pytest.raises(VPError):
         vp.preprocess(_to_dev(np.zeros((1, 5, 3), np.complex64)), 0.0)   # ZF with N > M
 
