@@ -492,6 +492,7 @@ def main():
     stage = r["stages_ms"]
     prep, s, sout = r["prep"], r["s"], r["sout"]
 
+
     flops = search_cm_per_vector(M, K) * FLOP_PER_CM * n_vec
     achieved = flops / (stage["search"] * 1e-3) / 1e12
     traffic, traffic_src = search_traffic(K)

@@ -49,7 +49,7 @@ __device__ __forceinline__ void batch_tile(const BatchGroup &g, int vfirst, int 
                                            const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
                                            const float2 *__restrict__ s, const uint8_t *__restrict__ paths,
                                            int n_sym, unsigned flags, unsigned long long *__restrict__ best,
-                                           float2 (*s_r0)[kMaxN], float *s_linv, float *s_wdiag) {
+                                           float2 (*s_r0)[kMaxN], float *s_nlinv, float *s_wdiag) {
     constexpr int NP = VP_PACKED(N);
     const int lpv = kBW / g.vt;                    // lanes per vector (64, 32 or 16)
     const int seg = lane / lpv, sl = lane % lpv;
@@ -62,7 +62,7 @@ __device__ __forceinline__ void batch_tile(const BatchGroup &g, int vfirst, int 
     const uint8_t *pm = perm + g.offN + (long long)sc * N;
     if (lane < N) {
         s_wdiag[lane] = Wc[vp_pidx(N, lane, lane)].x;
-        s_linv[lane] = 1.0f / s_wdiag[lane];
+        s_nlinv[lane] = -(1.0f / s_wdiag[lane]);
     }
     if (vok && sl < N)
         s_r0[seg][sl] = stilde_over_tau<N>(Wc, pm, s + g.offS, (size_t)v, (size_t)g.n_vec, sl, 1.0f / g.tau);
@@ -77,7 +77,7 @@ __device__ __forceinline__ void batch_tile(const BatchGroup &g, int vfirst, int 
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) r[i] = s_r0[seg][i];
-            const float ped = walk<N, true, false>(Wc, s_linv, s_wdiag, r, wd, VP_DEMAP_LUT, nullptr, nullptr);
+            const float ped = walk<N, kTierAny, false>(Wc, s_nlinv, s_wdiag, r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
             key = umin64(key, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
         }
         if ((flags & VP_INCLUDE_ZERO) && k0 == 0 && sl == 0) {
@@ -103,7 +103,7 @@ __global__ __launch_bounds__(kBW) void k_batch_search(const BatchGroup *__restri
                                                       const uint8_t *__restrict__ paths, int n_sym, unsigned flags,
                                                       unsigned long long *__restrict__ best) {
     __shared__ float2 s_r0[4][kMaxN];
-    __shared__ float s_linv[kMaxN];
+    __shared__ float s_nlinv[kMaxN];
     __shared__ float s_wdiag[kMaxN];
     const int lane = threadIdx.x;
     const uint32_t nt = *ntiles;
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(kBW) void k_batch_search(const BatchGroup *__restri
         switch (g.U) {
 #define VP_CASE(n)                                                                                             \
     case n:                                                                                                    \
-        batch_tile<n>(g, vfirst, k0, lane, W, perm, s, paths, n_sym, flags, best, s_r0, s_linv, s_wdiag); \
+        batch_tile<n>(g, vfirst, k0, lane, W, perm, s, paths, n_sym, flags, best, s_r0, s_nlinv, s_wdiag); \
         break;
             VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
             VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
@@ -145,19 +145,19 @@ __device__ __forceinline__ void batch_finish_one(const BatchGroup &g, int vloc, 
 #pragma unroll
     for (int i = 0; i < N; ++i) ra[i] = rb[i] = 0.f;
     if (k < (uint32_t)g.K) {
-        float linv[N], wdiag[N];
+        float nlinv[N], wdiag[N];
         float2 r[N];
         const float inv_tau = 1.0f / g.tau;
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             wdiag[i] = Wc[vp_pidx(N, i, i)].x;
-            linv[i] = 1.0f / wdiag[i];
+            nlinv[i] = -(1.0f / wdiag[i]);
             r[i] = stilde_over_tau<N>(Wc, pm, sg, (size_t)vloc, (size_t)g.n_vec, i, inv_tau);
         }
         const uint8_t *P = paths + g.offP + ((long long)sc * g.K + k) * N;
         unsigned long long wd = 0;
         for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
-        (void)walk<N, false, true>(Wc, linv, wdiag, r, wd, VP_DEMAP_LUT, ra, rb);
+        (void)walk<N, kTierLut, true>(Wc, nlinv, wdiag, r, wd, 0ull, VP_DEMAP_LUT, ra, rb);
     }
     const bool ok = k <= (uint32_t)g.K;   // a path or the zero perturbation
     const float c = ok ? __uint_as_float((uint32_t)(key >> 32)) : __int_as_float(0x7fc00000);

@@ -23,44 +23,58 @@
 // Offset of element (i, j), i >= j, in LAPACK column-major lower packed storage.
 VP_HD constexpr int vp_pidx(int n, int i, int j) { return j * n - (j * (j - 1)) / 2 + (i - j); }
 
-// Per-axis order of the three box offsets {-1, 0, 1} by squared distance to x:
-// o0 nearest, o2 farthest, with gaps A = (x-o1)^2 - (x-o0)^2 and
-// B = (x-o2)^2 - (x-o0)^2 (closed forms of those differences).
+// The DEMAP routines take the level centre c twice: as cp = c - 1/2, because
+// ceil(cp) is the integer nearest to c with a half-way c going to the smaller
+// integer (the canonical index order of equal distances) in one instruction,
+// and, for ranks above 0, as c itself, from which the per-axis gaps are
+// formed: gaps taken from cp would lose the low bits of c and break the exact
+// ties of symmetric centres (|c_x| = |c_y|) differently on the two axes.  The
+// walk forms cp with one fused multiply-add from the residual and c only
+// where a rank above 0 is asked for.
+
+// Nearest box offset to c = cp + 1/2 (half-way: the smaller offset).
+VP_HD float vp_o0(float cp) { return fminf(fmaxf(ceilf(cp), -1.0f), 1.0f); }
+
+// Per-axis order of the three box offsets {-1, 0, 1} by squared distance to
+// c: o0 nearest, o2 farthest, with gaps A = (c-o1)^2 - (c-o0)^2 and
+// B = (c-o2)^2 - (c-o0)^2.  With t = |2c|: A = |1 - t|, and B = 1 + t when the
+// nearest offset is 0, else 2t.  The side s of c (c = 0 counts as negative:
+// then -1 comes before +1) gives o2 = -s and o1 = s - o0.  Whatever rounding
+// did to cp and c, (o0, o1, o2) is a permutation of the box offsets with
+// 0 <= A <= B, so every variant below makes the same, consistent choice.
 struct vp_axis {
     float o0, o1, o2, A, B;
 };
 
-// Nearest box offset; half-way between two offsets the smaller one (the
-// canonical index order of equal distances).
-VP_HD float vp_nearest_offset(float x) { return (x == -0.5f) ? -1.0f : fminf(fmaxf(rintf(x), -1.0f), 1.0f); }
-
-VP_HD vp_axis vp_axis_order(float x) {
+VP_HD vp_axis vp_axis_order(float cp, float c) {
     vp_axis r;
-    const float o0 = vp_nearest_offset(x);
-    const float s = (x > 0.0f) ? 1.0f : -1.0f;
-    const bool near0 = (o0 == 0.0f);
-    const float t = fabsf(x);
+    const float o0 = vp_o0(cp);
+    const float s = (c > 0.0f) ? 1.0f : -1.0f;
+    const float t = fabsf(c + c);
     r.o0 = o0;
-    r.o1 = near0 ? s : 0.0f;
+    r.o1 = s - o0;
     r.o2 = -s;
-    r.A = fabsf(fmaf(-2.0f, t, 1.0f));        // |1 - 2|x||
-    r.B = near0 ? fmaf(2.0f, t, 1.0f) : 4.0f * t;
+    r.A = fabsf(1.0f - t);
+    r.B = (o0 == 0.0f) ? 1.0f + t : t + t;
     return r;
 }
 
-// Rank-0 child: the box point nearest to (cx, cy).
-VP_HD void vp_demap0(float cx, float cy, float &a, float &b) {
-    a = vp_nearest_offset(cx);
-    b = vp_nearest_offset(cy);
+// Rank-0 child: the box point nearest to c.
+VP_HD void vp_demap0(float cpx, float cpy, float &a, float &b) {
+    a = vp_o0(cpx);
+    b = vp_o0(cpy);
 }
 
-// Children of rank 0 or 1.  Cell (0,1) precedes (1,0) when C < A, or on a tie
-// when its x offset is smaller (canonical index order).  Written with
-// non-short-circuit logic and selects so that no lane-divergent branch is made.
-VP_HD void vp_demap1(float cx, float cy, int rank, float &a, float &b) {
-    const vp_axis X = vp_axis_order(cx);
-    const vp_axis Y = vp_axis_order(cy);
-    const bool q1 = (Y.A < X.A) | ((Y.A == X.A) & (X.o0 < X.o1));
+// Cell (0,1) -- y moved to its second offset -- precedes (1,0) when C < A, or
+// on a tie when its x offset (o0 of x) is the smaller one (canonical order).
+VP_HD bool vp_q1(const vp_axis &X, const vp_axis &Y) { return (Y.A < X.A) | ((Y.A == X.A) & (X.o0 < X.o1)); }
+
+// Children of rank 0 or 1.  Non-short-circuit logic and selects, so that no
+// lane-divergent branch is made.
+VP_HD void vp_demap1(float cpx, float cpy, float cx, float cy, int rank, float &a, float &b) {
+    const vp_axis X = vp_axis_order(cpx, cx);
+    const vp_axis Y = vp_axis_order(cpy, cy);
+    const bool q1 = vp_q1(X, Y);
     const bool r1 = (rank == 1);
     a = (r1 & !q1) ? X.o1 : X.o0;
     b = (r1 & q1) ? Y.o1 : Y.o0;
@@ -115,16 +129,14 @@ VP_HD float vp_pick_offset(float o0, float o1, float o2, int p) {
 // that is nearer on both axes, so the rank-2 cell is, after a rank-1 cell
 // (0,1), the first of (1,0) and (0,2), and after a rank-1 cell (1,0), the
 // first of (0,1) and (2,0).  The three comparisons are bits 0, 2 and 1 of the
-// signature above, with the same tie rule, so the result is that of the
-// table for every rank up to 2.
-VP_HD void vp_demap2(float cx, float cy, int rank, float &a, float &b) {
-    const vp_axis X = vp_axis_order(cx);
-    const vp_axis Y = vp_axis_order(cy);
-    const int32_t ia = vp_fbits(X.A), ib = vp_fbits(X.B), ic = vp_fbits(Y.A), id = vp_fbits(Y.B);
-    const int32_t a1 = ia + (int32_t)(X.o0 < X.o1);
-    const bool q1 = ic < a1;                                  // (0,1) before (1,0)
-    const bool y2 = id < a1;                                  // (0,2) before (1,0)
-    const bool y1 = ic < ib + (int32_t)(X.o0 < X.o2);         // (0,1) before (2,0)
+// signature above with the same tie rule (float compares of the same gaps),
+// so the result is that of the table for every rank up to 2.
+VP_HD void vp_demap2(float cpx, float cpy, float cx, float cy, int rank, float &a, float &b) {
+    const vp_axis X = vp_axis_order(cpx, cx);
+    const vp_axis Y = vp_axis_order(cpy, cy);
+    const bool q1 = vp_q1(X, Y);                                                // (0,1) before (1,0)
+    const bool y2 = (Y.B < X.A) | ((Y.B == X.A) & (X.o0 < X.o1));               // (0,2) before (1,0)
+    const bool y1 = (Y.A < X.B) | ((Y.A == X.B) & (X.o0 < X.o2));               // (0,1) before (2,0)
     const bool r1 = (rank == 1), r2 = (rank == 2);
     // cell (p, q) of the requested rank, as per-axis ranks
     const bool p1 = (r1 & !q1) | (r2 & q1 & !y2);
@@ -135,11 +147,11 @@ VP_HD void vp_demap2(float cx, float cy, int rank, float &a, float &b) {
     b = s2 ? Y.o2 : (s1 ? Y.o1 : Y.o0);
 }
 
-VP_HD void vp_demapN(float cx, float cy, int rank, const uint8_t *lut, float &a, float &b) {
-    const vp_axis X = vp_axis_order(cx);
-    const vp_axis Y = vp_axis_order(cy);
+VP_HD void vp_demapN(float cpx, float cpy, float cx, float cy, int rank, const uint8_t *lut, float &a, float &b) {
+    const vp_axis X = vp_axis_order(cpx, cx);
+    const vp_axis Y = vp_axis_order(cpy, cy);
     const int sig = vp_demap_signature(X, Y);
-    const int cell = lut[sig * 9 + rank];
+    const int cell = lut[sig * 9 + (rank < 8 ? rank : 8)];   // a rank beyond the box must not leave the table
     a = vp_pick_offset(X.o0, X.o1, X.o2, cell & 3);
     b = vp_pick_offset(Y.o0, Y.o1, Y.o2, cell >> 2);
 }

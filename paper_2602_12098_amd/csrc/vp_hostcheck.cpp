@@ -5,22 +5,24 @@
 extern "C" {
 
 // tier 0: rank 0 only; tier 1: ranks 0..1; tier 2: ranks 0..2; tier 3: any
-// rank (table lookup).
+// rank (table lookup).  The routines take the centre c and cp = c - 1/2,
+// formed here in float32 from the given centres.
 int vp_host_demap(const float *cx, const float *cy, const int32_t *rank, int n, int tier, float *a,
                   float *b) {
     for (int k = 0; k < n; ++k) {
+        const float cpx = cx[k] - 0.5f, cpy = cy[k] - 0.5f;
         float aa, bb;
         if (tier == 0) {
             if (rank[k] != 0) return -1;
-            vp_demap0(cx[k], cy[k], aa, bb);
+            vp_demap0(cpx, cpy, aa, bb);
         } else if (tier == 1) {
             if (rank[k] > 1) return -1;
-            vp_demap1(cx[k], cy[k], rank[k], aa, bb);
+            vp_demap1(cpx, cpy, cx[k], cy[k], rank[k], aa, bb);
         } else if (tier == 2) {
             if (rank[k] > 2) return -1;
-            vp_demap2(cx[k], cy[k], rank[k], aa, bb);
+            vp_demap2(cpx, cpy, cx[k], cy[k], rank[k], aa, bb);
         } else {
-            vp_demapN(cx[k], cy[k], rank[k], VP_DEMAP_LUT, aa, bb);
+            vp_demapN(cpx, cpy, cx[k], cy[k], rank[k], VP_DEMAP_LUT, aa, bb);
         }
         a[k] = aa;
         b[k] = bb;

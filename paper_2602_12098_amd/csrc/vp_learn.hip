@@ -223,7 +223,7 @@ __global__ __launch_bounds__(64) void k_features(const float2 *__restrict__ W, c
             a = wd[i] / mean;
             cx = -(re * inv_tau) / wd[i];
             cy = -(im * inv_tau) / wd[i];
-            const float ex = cx - vp_nearest_offset(cx), ey = cy - vp_nearest_offset(cy);
+            const float ex = cx - vp_o0(cx - 0.5f), ey = cy - vp_o0(cy - 0.5f);
             d0 = wd[i] * wd[i] * (ex * ex + ey * ey) / wmean;
         }
         f[i] = f2bf(a);
@@ -280,11 +280,13 @@ __global__ __launch_bounds__(64) void k_features_walk(const float2 *__restrict__
         r[i] = make_float2(re * inv_tau, im * inv_tau);
     }
     for (int i = 0; i < N; ++i) {
-        const float linv = 1.0f / wd[i];
-        const float cx = -(r[i].x * linv), cy = -(r[i].y * linv);
+        // the centre as the search's walk forms it: cp = c - 1/2 in one fma
+        const float nlinv = -(1.0f / wd[i]);
+        const float cpx = fmaf(r[i].x, nlinv, -0.5f), cpy = fmaf(r[i].y, nlinv, -0.5f);
+        const float cx = r[i].x * nlinv, cy = r[i].y * nlinv;
         float a, b, a1, b1;
-        vp_demap0(cx, cy, a, b);
-        vp_demap1(cx, cy, 1, a1, b1);
+        vp_demap0(cpx, cpy, a, b);
+        vp_demap1(cpx, cpy, cx, cy, 1, a1, b1);
         const float ex = cx - a, ey = cy - b;
         const float fx = cx - a1, fy = cy - b1;
         const float d0 = ex * ex + ey * ey, d1 = fx * fx + fy * fy;
@@ -335,12 +337,13 @@ __global__ __launch_bounds__(64) void k_ranks(const float2 *__restrict__ W, cons
         const int8_t *li = l + ((size_t)u * n_vec + v) * 2;
         const float la = (float)li[0], lb = (float)li[1];
         const float wii = Wc[vp_pidx(N, i, i)].x;
-        const float linv = 1.0f / wii;
-        const float cx = -(r[i].x * linv), cy = -(r[i].y * linv);
+        const float nlinv = -(1.0f / wii);
+        const float cpx = fmaf(r[i].x, nlinv, -0.5f), cpy = fmaf(r[i].y, nlinv, -0.5f);   // as the search's walk
+        const float cx = r[i].x * nlinv, cy = r[i].y * nlinv;
         int rk = 15;
         for (int q = 8; q >= 0; --q) {
             float a, b;
-            vp_demapN(cx, cy, q, VP_DEMAP_LUT, a, b);
+            vp_demapN(cpx, cpy, cx, cy, q, VP_DEMAP_LUT, a, b);
             if (a == la && b == lb) rk = q;
         }
         ranks[v * N + i] = (uint8_t)rk;

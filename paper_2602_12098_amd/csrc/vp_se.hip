@@ -75,7 +75,7 @@ __global__ __launch_bounds__(kT) void k_sphere(const float2 *__restrict__ W, con
                 up = true;
             } else {
                 float a, b;
-                vp_demapN(cx[i], cy[i], rk[i], VP_DEMAP_LUT, a, b);
+                vp_demapN(cx[i] - 0.5f, cy[i] - 0.5f, cx[i], cy[i], rk[i], VP_DEMAP_LUT, a, b);
                 // PED increment: tau^2 W_ii^2 |c_i - l_i|^2
                 const float dx = cx[i] - a, dy = cy[i] - b;
                 const float d = fmaf(dx, dx, dy * dy);

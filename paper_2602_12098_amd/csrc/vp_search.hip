@@ -41,7 +41,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
                                                int n_sym, unsigned flags, float *__restrict__ cost_out,
                                                int32_t *__restrict__ kidx_out, VecMask mask) {
     __shared__ float2 s_r0[N];
-    __shared__ float s_linv[N];
+    __shared__ float s_nlinv[N];
     __shared__ float s_wdiag[N];
     __shared__ uint8_t s_perm[N];
     __shared__ unsigned long long s_red[kT / 64];
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
     }
     if (t < N) {
         s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
-        s_linv[t] = 1.0f / s_wdiag[t];
+        s_nlinv[t] = -(1.0f / s_wdiag[t]);
         s_perm[t] = perm[(size_t)sc * N + t];
     }
     __syncthreads();
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
         float2 r[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = s_r0[i];
-        const float ped = walk<N, true, false>(Wc, s_linv, s_wdiag, r, wd, VP_DEMAP_LUT, nullptr, nullptr);
+        const float ped = walk<N, kTierAny, false>(Wc, s_nlinv, s_wdiag, r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
         best = umin64(best, ((unsigned long long)__float_as_uint(ped * (tau * tau)) << 32) | (unsigned)k);
     }
     if ((flags & VP_INCLUDE_ZERO) && t == 0) {
@@ -104,10 +104,13 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
 // deepest level most significant).
 // Stage 1: each distinct prefix of levels [0, P1) is walked once per vector,
 // one lane per (vector, prefix), and its residuals below P1 and its PED are
-// kept in LDS.  Stage 2:
-// each path continues from its prefix's state over levels [P1, N), taken in
-// deepest-level-first order so that the lanes of a wave mostly need the same
-// DEMAP work.  A table with more than kMaxPrefix distinct prefixes is done in
+// kept in LDS.  Stage 2: each path continues from its prefix's state over
+// levels [P1, N), taken in deepest-level-first order so that the paths of a
+// wave mostly need the same DEMAP work; the two vectors of the workgroup are
+// interleaved over the lanes (lane 2j + h: vector h, path j of the order), so
+// that a wave holds 32 paths, and each wave's DEMAP variant per level comes
+// from a tier word of its 32 paths built once in the set-up (no votes in the
+// walk).  A table with more than kMaxPrefix distinct prefixes is done in
 // chunks of kMaxPrefix prefixes (their paths are contiguous in lexicographic
 // order).  Every path sees exactly the arithmetic of a direct walk.
 //
@@ -124,55 +127,68 @@ constexpr int prefix_levels() { return N >= 4 ? N / 4 : 1; }
 
 constexpr int kVPB = 2;                 // vectors of one subcarrier per workgroup (they share its table)
 constexpr int kTB = kTT * kVPB;         // threads of the prefix-sharing search
+constexpr int kBatch = 64 / kVPB;       // distinct paths per wave in stage 2
 static_assert(kVPB == 2 && 2 * kMaxPrefix <= kTB, "stage 1 packs both vectors' prefixes over the workgroup");
+
+// Bytes of dynamic LDS of k_search_trie for a table of K paths.
+inline size_t trie_lds_bytes(int K) {
+    const size_t nb = (size_t)(K + kBatch - 1) / kBatch;
+    return (size_t)K * sizeof(unsigned long long) + nb * sizeof(unsigned long long) +
+           (size_t)(3 * K + 1) * sizeof(uint16_t);
+}
+
+// Minimum over the lanes of one parity (lane & 1) of a wave: lane 0 ends with
+// the minimum of the even lanes, lane 1 with that of the odd lanes.
+__device__ __forceinline__ unsigned long long wave_min_by_parity(unsigned long long x) {
+#pragma unroll
+    for (int off = 32; off > 1; off >>= 1) x = umin64(x, __shfl_xor(x, off));
+    return x;
+}
 
 template <int N, bool MASKED>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(
     const float2 *__restrict__ W, const uint8_t *__restrict__ perm, const float2 *__restrict__ s,
     const float *__restrict__ taus, const uint8_t *__restrict__ paths, const uint16_t *__restrict__ order, int K,
-    long long pstride, int n_sym,
-    size_t n_vec, unsigned flags, float *__restrict__ cost_out, int32_t *__restrict__ kidx_out, VecMask mask) {
+    long long pstride, int n_sym, size_t n_vec, unsigned flags, float *__restrict__ cost_out,
+    int32_t *__restrict__ kidx_out, VecMask mask) {
     constexpr int P1 = prefix_levels<N>();
     constexpr int SW = 2 * (N - P1) + 1;   // stage-1 state: residuals of levels P1..N-1 and the PED
-    extern __shared__ unsigned long long s_words[];   // [K] rank nibbles of path k
-    uint16_t *s_k = reinterpret_cast<uint16_t *>(s_words + K);     // [K] path index of lex position
+    const int NB = (K + kBatch - 1) / kBatch;
+    extern __shared__ unsigned long long s_words[];                 // [K] rank nibbles of path k
+    unsigned long long *s_therm = s_words + K;                      // [NB] tier words of stage-2 batches
+    uint16_t *s_k = reinterpret_cast<uint16_t *>(s_therm + NB);     // [K] path index of lex position
     uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of path k
     uint16_t *s_first = s_node + K;                                 // [K + 1] first lex position of a prefix
     __shared__ float s_state[kVPB][kMaxPrefix * SW];
     __shared__ float2 s_r0[kVPB][N];
-    __shared__ float s_linv[N];
+    __shared__ float s_nlinv[N];
     __shared__ float s_wdiag[N];
     __shared__ uint8_t s_perm[N];
     __shared__ uint32_t s_scan[kTB / 64];
-    __shared__ unsigned long long s_red[kTB / 64];
+    __shared__ unsigned long long s_red[kTB / 64][kVPB];
 
     constexpr int NP = VP_PACKED(N);
     const int slots = (n_sym + kVPB - 1) / kVPB;
     const uint32_t blk = xcd_contiguous(blockIdx.x, gridDim.x);
     const int sc = (int)(blk / slots);
     const int t = threadIdx.x;
-    const int h = __builtin_amdgcn_readfirstlane(t / kTT);   // this thread's vector in the workgroup
-    const int tl = t % kTT;
-    const int sym = (int)(blk % slots) * kVPB + h;
-    const bool live = sym < n_sym;
-    const size_t v = (size_t)sc * n_sym + (live ? sym : 0);
-    const int nlive = min(kVPB, n_sym - (int)(blk % slots) * kVPB);   // live vectors of this workgroup
+    const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+    const size_t vbase = (size_t)sc * n_sym + (size_t)(blk % slots) * kVPB;   // the workgroup's first vector
+    const int nlive = min(kVPB, n_sym - (int)(blk % slots) * kVPB);          // live vectors of this workgroup
     // masked search: the live vectors it serves (the same in every thread)
-    bool on0 = true, on1 = true;
+    bool on0 = true, on1 = nlive > 1;
     if (MASKED) {
-        const size_t v0 = (size_t)sc * n_sym + (blk % slots) * kVPB;
-        on0 = mask.on(v0);
-        on1 = nlive > 1 && mask.on(v0 + 1);
+        on0 = mask.on(vbase);
+        on1 = nlive > 1 && mask.on(vbase + 1);
         if (!on0 && !on1) return;
     }
-    const bool act = live && (h == 0 ? on0 : on1);
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
     const float tau = taus[sc];
     if (!(w00 > 0.f) || !isfinite(w00) || !(tau > 0.f) || !isfinite(tau)) {   // failed subcarrier (all its vectors)
-        if (tl == 0 && act) {
-            cost_out[v] = __int_as_float(0x7fc00000);
-            kidx_out[v] = -1;
+        if (t < nlive && (t == 0 ? on0 : on1)) {
+            cost_out[vbase + t] = __int_as_float(0x7fc00000);
+            kidx_out[vbase + t] = -1;
         }
         return;
     }
@@ -181,7 +197,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const uint16_t *SX = LX + K;                            // deepest level most significant
     if (t < N) {
         s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
-        s_linv[t] = 1.0f / s_wdiag[t];
+        s_nlinv[t] = -(1.0f / s_wdiag[t]);
         s_perm[t] = perm[(size_t)sc * N + t];
     }
     for (int j = t; j < K; j += kTB) {
@@ -191,7 +207,25 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
         s_words[j] = load_word<N>(P, j);
     }
     __syncthreads();
-    if (tl < N && live) s_r0[h][tl] = stilde_over_tau<N>(Wc, s_perm, s, v, n_vec, tl, 1.0f / tau);
+    {   // start residuals: thread (h, i) for vector h, level i
+        const int h = t / kTT, i = t % kTT;
+        if (i < N && h < nlive) s_r0[h][i] = stilde_over_tau<N>(Wc, s_perm, s, vbase + h, n_vec, i, 1.0f / tau);
+    }
+    // stage-2 tier words: batch b holds the paths at positions [32 b, 32 b + 32)
+    // of the deepest-level-first order; OR of their per-level rank thermometers
+    static_assert(kBatch == 32, "a batch is one half of a wave");
+    for (int b0 = 0; b0 < NB; b0 += kTB / kBatch) {
+        const int b = b0 + t / kBatch, q = b * kBatch + t % kBatch;
+        unsigned long long w = 0ull;
+        if (q < K) {
+            int k = SX[q];
+            k = k < K ? k : K - 1;
+            w = s_words[k];
+        }
+        const uint32_t lo = half_wave_or(rank_tiers32((uint32_t)w));
+        const uint32_t hi = half_wave_or(rank_tiers32((uint32_t)(w >> 32)));
+        if (t % kBatch == kBatch - 1 && b < NB) s_therm[b] = ((unsigned long long)hi << 32) | lo;
+    }
     // prefix boundaries: contiguous chunk of lex positions per thread, then a block scan
     constexpr unsigned long long PMASK = P1 >= 16 ? ~0ull : ((1ull << (4 * P1)) - 1ull);
     const int chunk = (K + kTB - 1) / kTB;
@@ -206,7 +240,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     }
     uint32_t incl = wave_scan_incl(cnt);
     {
-        const int lane = t & 63, wv = t >> 6;
+        const int lane = t & 63;
         if (lane == 63) s_scan[wv] = incl;
         __syncthreads();
         for (int q = 0; q < wv; ++q) incl += s_scan[q];
@@ -224,8 +258,10 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     if (t == 0) s_first[n1] = (uint16_t)K;
     __syncthreads();
     const float tau2 = tau * tau;
+    // stage-2 lane roles: vector hv, path slot t / 2 of each group of kTB / 2
+    const int hv = t & 1;
+    const bool hv_on = hv < nlive && (hv == 0 ? on0 : on1);
     unsigned long long best = ~0ull;
-    float *state = s_state[h];
     for (uint32_t base = 0; base < n1; base += kMaxPrefix) {
         const uint32_t nc = min(n1 - base, (uint32_t)kMaxPrefix);
         // stage 1: one lane per (vector, distinct prefix), the vectors' prefixes
@@ -235,8 +271,9 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) r[i] = s_r0[hh][i];
-            const float ped = walk<N, true, false, 0, P1>(Wc, s_linv, s_wdiag, r, s_words[s_k[s_first[base + pp]]],
-                                                           VP_DEMAP_LUT, nullptr, nullptr);
+            const float ped = walk<N, kTierAny, false, 0, P1>(Wc, s_nlinv, s_wdiag, r,
+                                                             s_words[s_k[s_first[base + pp]]], 0ull, VP_DEMAP_LUT,
+                                                             nullptr, nullptr);
             float *st = s_state[hh] + pp * SW;
 #pragma unroll
             for (int i = P1; i < N; ++i) {
@@ -246,50 +283,63 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
             st[SW - 1] = ped;
         }
         __syncthreads();
-        // stage 2: all paths at once in deepest-level-first order, or (chunked
-        // case) the contiguous lexicographic range of this chunk's prefixes
+        // stage 2: all paths at once in deepest-level-first order with the tier
+        // words of the set-up, or (chunked case) the contiguous lexicographic
+        // range of this chunk's prefixes with tier words formed per wave
         const bool whole = (n1 <= (uint32_t)kMaxPrefix);
         const int q0 = whole ? 0 : s_first[base];
-        const int q1 = act ? (whole ? K : s_first[base + nc]) : q0;
-        for (int q = q0 + tl; q < q1; q += kTT) {
-            int k;
-            if (whole) {
-                k = SX[q];
+        const int q1 = whole ? K : s_first[base + nc];
+        for (int it = 0; q0 + it * (kTB / kVPB) < q1; ++it) {
+            const int q = q0 + it * (kTB / kVPB) + (t >> 1);
+            const bool on = hv_on && q < q1;
+            int k = 0;
+            if (on) {
+                k = whole ? SX[q] : s_k[q];
                 k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
-            } else {
-                k = s_k[q];
             }
-            int nd = (int)s_node[k] - (int)base;   // in [0, nc) unless the order is corrupt
-            nd = nd < 0 ? 0 : (nd < (int)nc ? nd : (int)nc - 1);
-            const float *st = state + nd * SW;
-            float2 r[N];
+            const unsigned long long wd = s_words[k];
+            unsigned long long therm;
+            if (whole) {
+                // a wave whose paths all lie beyond K (its batch >= NB) walks nothing
+                const int bt = it * (kTB / 64) + wv;
+                therm = bt < NB ? s_therm[bt] : 0ull;
+                therm = ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(therm >> 32)) << 32) |
+                        __builtin_amdgcn_readfirstlane((uint32_t)therm);
+            } else {
+                therm = wave_or64(on ? rank_tiers(wd) : 0ull);
+            }
+            if (on) {
+                int nd = (int)s_node[k] - (int)base;   // in [0, nc) unless the order is corrupt
+                nd = nd < 0 ? 0 : (nd < (int)nc ? nd : (int)nc - 1);
+                const float *st = s_state[hv] + nd * SW;
+                float2 r[N];
 #pragma unroll
-            for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
+                for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
 #pragma unroll
-            for (int i = P1; i < N; ++i) r[i] = make_float2(st[2 * (i - P1)], st[2 * (i - P1) + 1]);
-            const float ped = walk<N, true, false, P1, N>(Wc, s_linv, s_wdiag, r, s_words[k], VP_DEMAP_LUT,
-                                                           nullptr, nullptr, st[SW - 1]);
-            best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
+                for (int i = P1; i < N; ++i) r[i] = make_float2(st[2 * (i - P1)], st[2 * (i - P1) + 1]);
+                const float ped = walk<N, kTierTherm, false, P1, N>(Wc, s_nlinv, s_wdiag, r, wd, therm,
+                                                                    VP_DEMAP_LUT, nullptr, nullptr, st[SW - 1]);
+                best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
+            }
         }
         __syncthreads();
     }
-    if ((flags & VP_INCLUDE_ZERO) && tl == 0 && act) {
+    if ((flags & VP_INCLUDE_ZERO) && t < kVPB && hv_on) {
         float z = 0.f;
         for (int i = 0; i < N; ++i) {
-            z = fmaf(s_r0[h][i].x, s_r0[h][i].x, z);
-            z = fmaf(s_r0[h][i].y, s_r0[h][i].y, z);
+            z = fmaf(s_r0[hv][i].x, s_r0[hv][i].x, z);
+            z = fmaf(s_r0[hv][i].y, s_r0[hv][i].y, z);
         }
         best = umin64(best, ((unsigned long long)__float_as_uint(z * tau2) << 32) | (unsigned)K);
     }
-    best = wave_min(best);
-    if ((t & 63) == 0) s_red[t >> 6] = best;
+    best = wave_min_by_parity(best);
+    if ((t & 63) < kVPB) s_red[wv][t & 63] = best;
     __syncthreads();
-    if (tl == 0 && act) {
-        constexpr int WPV = kTT / 64;   // waves per vector
-        unsigned long long b = s_red[h * WPV];
-        for (int w = 1; w < WPV; ++w) b = umin64(b, s_red[h * WPV + w]);
-        cost_out[v] = __uint_as_float((unsigned)(b >> 32));
-        kidx_out[v] = (int32_t)(b & 0xffffffffull);
+    if (t < kVPB && hv_on) {
+        unsigned long long b = s_red[0][t];
+        for (int w = 1; w < kTB / 64; ++w) b = umin64(b, s_red[w][t]);
+        cost_out[vbase + t] = __uint_as_float((unsigned)(b >> 32));
+        kidx_out[vbase + t] = (int32_t)(b & 0xffffffffull);
     }
 }
 
@@ -309,7 +359,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
                                                           unsigned flags, float *__restrict__ cost_out,
                                                           int32_t *__restrict__ kidx_out, VecMask mask) {
     __shared__ float2 s_r0[kWV][N];
-    __shared__ float s_linv[kWV][N];
+    __shared__ float s_nlinv[kWV][N];
     __shared__ float s_wdiag[kWV][N];
     __shared__ uint8_t s_perm[kWV][N];
 
@@ -326,7 +376,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     const bool ok = (w00 > 0.f) && isfinite(w00) && (tau > 0.f) && isfinite(tau);
     if (t < N) {
         s_wdiag[wv][t] = Wc[vp_pidx(N, t, t)].x;
-        s_linv[wv][t] = 1.0f / s_wdiag[wv][t];
+        s_nlinv[wv][t] = -(1.0f / s_wdiag[wv][t]);
         s_perm[wv][t] = perm[(size_t)sc * N + t];
     }
     __syncthreads();
@@ -349,7 +399,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
         float2 r[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = s_r0[wv][i];
-        const float ped = walk<N, true, false>(Wc, s_linv[wv], s_wdiag[wv], r, wd, VP_DEMAP_LUT, nullptr, nullptr);
+        const float ped = walk<N, kTierAny, false>(Wc, s_nlinv[wv], s_wdiag[wv], r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
         best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
     }
     if ((flags & VP_INCLUDE_ZERO) && t == 0) {
@@ -388,19 +438,19 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
     for (int i = 0; i < N; ++i) ra[i] = rb[i] = 0.f;
     if (k >= 0 && k < K) {
         const float2 *__restrict__ Wc = W + (size_t)sc * NP;
-        float linv[N], wdiag[N];
+        float nlinv[N], wdiag[N];
         float2 r[N];
         const float inv_tau = 1.0f / taus[sc];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             wdiag[i] = Wc[vp_pidx(N, i, i)].x;
-            linv[i] = 1.0f / wdiag[i];
+            nlinv[i] = -(1.0f / wdiag[i]);
             r[i] = stilde_over_tau<N>(Wc, pm, s, v, n_vec, i, inv_tau);
         }
         const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride + (size_t)k * N;
         unsigned long long wd = 0;
         for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
-        (void)walk<N, false, true>(Wc, linv, wdiag, r, wd, VP_DEMAP_LUT, ra, rb);
+        (void)walk<N, kTierLut, true>(Wc, nlinv, wdiag, r, wd, 0ull, VP_DEMAP_LUT, ra, rb);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -437,19 +487,19 @@ __global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict_
     for (int i = 0; i < N; ++i) ra[i] = rb[i] = 0.f;
     if (k >= 0 && k < K) {
         const float2 *__restrict__ Wc = W + (size_t)sc * NP;
-        float linv[N], wdiag[N];
+        float nlinv[N], wdiag[N];
         float2 r[N];
         const float inv_tau = 1.0f / taus[sc];
 #pragma unroll
         for (int i = 0; i < N; ++i) {
             wdiag[i] = Wc[vp_pidx(N, i, i)].x;
-            linv[i] = 1.0f / wdiag[i];
+            nlinv[i] = -(1.0f / wdiag[i]);
             r[i] = stilde_over_tau<N>(Wc, pm, s, v, n_vec, i, inv_tau);
         }
         const uint8_t *P = paths + (size_t)sc * pstride + (size_t)k * N;
         unsigned long long wd = 0;
         for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
-        (void)walk<N, false, true>(Wc, linv, wdiag, r, wd, VP_DEMAP_LUT, ra, rb);
+        (void)walk<N, kTierLut, true>(Wc, nlinv, wdiag, r, wd, 0ull, VP_DEMAP_LUT, ra, rb);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -470,7 +520,7 @@ void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s,
                           VecMask mask, float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
     if (order) {
-        const size_t smem = (size_t)K * sizeof(unsigned long long) + (size_t)(3 * K + 1) * sizeof(uint16_t);
+        const size_t smem = trie_lds_bytes(K);
         static const bool lds_ok = allow_dynamic_lds(k_search_trie<N, MASKED>, 64 * 1024);
         (void)lds_ok;
         const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);

@@ -35,11 +35,6 @@ __device__ __forceinline__ float2 stilde_over_tau(const float2 *__restrict__ Wc,
     return make_float2(re * inv_tau, im * inv_tau);
 }
 
-// Walk one path over levels [LO, HI).  r: residuals / tau (in: their values
-// after level LO-1, destroyed), linv_i = 1 / W_ii, wdiag_i = W_ii, ped: the
-// PED so far.  Returns ped + sum_{LO<=i<HI} |r_i + W_ii l_i|^2; with REC the
-// chosen offsets.  A walk split into consecutive ranges performs exactly the
-// arithmetic of the whole walk.
 // Hides a wave-uniform pointer from loop-invariant code motion, so that the W
 // column of each level is scalar-loaded where it is used instead of all 240
 // coefficients being hoisted (and spilled) at once.  Loads through the
@@ -54,25 +49,93 @@ __device__ __forceinline__ cfloat *opaque_uniform(const float2 *p, float after) 
     return (cfloat *)p;
 }
 
-template <int N, bool UNIFORM_TIERS, bool REC, int LO = 0, int HI = N>
-__device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float *linv, const float *wdiag, float2 (&r)[N],
-                                      unsigned long long word, const uint8_t *lut, float *ra, float *rb,
-                                      float ped = 0.f) {
+// How a walk picks its DEMAP variant at each level.
+enum : int {
+    kTierLut = 0,    // always the table (any rank): the re-walks that write l
+    kTierAny = 1,    // the cheapest variant serving every lane of the wave, found by wave votes
+    kTierTherm = 2   // from a wave-uniform thermometer word (rank_tiers below), no votes
+};
+
+// Per level i, bits 4i, 4i+1, 4i+2 of the result: the path's rank at that
+// level is >= 1, >= 2, >= 3.  The OR of these words over a wave's paths
+// tells, per level, the largest rank any lane needs there (capped at 3).
+// Formed on the two 32-bit halves (eight levels each).
+__device__ __forceinline__ uint32_t rank_tiers32(uint32_t w) {
+    constexpr uint32_t M = 0x11111111u;
+    const uint32_t w1 = w >> 1, w2 = w >> 2, w3 = w >> 3;
+    const uint32_t ge1 = (w | w1 | w2 | w3) & M;
+    const uint32_t ge2 = (w1 | w2 | w3) & M;
+    const uint32_t ge3 = (w2 | w3 | (w & w1)) & M;
+    return ge1 | (ge2 << 1) | (ge3 << 2);
+}
+
+__device__ __forceinline__ unsigned long long rank_tiers(unsigned long long w) {
+    return ((unsigned long long)rank_tiers32((uint32_t)(w >> 32)) << 32) | rank_tiers32((uint32_t)w);
+}
+
+// OR over each half (32 lanes) of a wave by DPP moves; lanes 31 and 63 end
+// with the OR of their half (the other lanes with partial results).
+__device__ __forceinline__ uint32_t half_wave_or(uint32_t x) {
+    const int v = (int)x;
+    int r = v;
+    r |= __builtin_amdgcn_update_dpp(0, r, 0xB1, 0xF, 0xF, false);    // quad_perm [1,0,3,2]
+    r |= __builtin_amdgcn_update_dpp(0, r, 0x4E, 0xF, 0xF, false);    // quad_perm [2,3,0,1]
+    r |= __builtin_amdgcn_update_dpp(0, r, 0x141, 0xF, 0xF, false);   // row_half_mirror
+    r |= __builtin_amdgcn_update_dpp(0, r, 0x140, 0xF, 0xF, false);   // row_mirror
+    r |= __builtin_amdgcn_update_dpp(0, r, 0x142, 0xA, 0xF, false);   // row_bcast:15 into rows 1, 3
+    return (uint32_t)r;
+}
+
+// OR over the 64 lanes of a wave, returned wave-uniform (in scalar registers).
+__device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
+    uint32_t lo = (uint32_t)x, hi = (uint32_t)(x >> 32);
+    lo = wave_reduce(lo, 0u, [](uint32_t p, uint32_t q) { return p | q; });
+    hi = wave_reduce(hi, 0u, [](uint32_t p, uint32_t q) { return p | q; });
+    return ((unsigned long long)__builtin_amdgcn_readfirstlane(hi) << 32) | __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Walk one path over levels [LO, HI).  r: residuals / tau (in: their values
+// after level LO-1, destroyed), nlinv_i = -1 / W_ii, wdiag_i = W_ii, ped: the
+// PED so far.  Returns ped + sum_{LO<=i<HI} |r_i + W_ii l_i|^2; with REC the
+// chosen offsets.  The level centre c_i = -r_i / W_ii enters DEMAP as
+// cp = c - 1/2, one fused multiply-add, and (above rank 0) as c.  A walk split
+// into consecutive ranges performs exactly the arithmetic of the whole walk,
+// and every tier mode gives the same bits.
+template <int N, int TIERS, bool REC, int LO = 0, int HI = N>
+__device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float *nlinv, const float *wdiag,
+                                      float2 (&r)[N], unsigned long long word, unsigned long long therm,
+                                      const uint8_t *lut, float *ra, float *rb, float ped = 0.f) {
     constexpr int CH = 4;   // W rows per scalar load (8 dwords)
 #pragma unroll
     for (int i = LO; i < HI; ++i) {
-        const int rank = (int)((word >> (4 * i)) & 15ull);
-        const float li = linv[i];
-        const float cx = -(r[i].x * li);
-        const float cy = -(r[i].y * li);
+        const float nl = nlinv[i];
+        const float cpx = fmaf(r[i].x, nl, -0.5f);
+        const float cpy = fmaf(r[i].y, nl, -0.5f);
         float a, b;
-        if (UNIFORM_TIERS) {   // the cheapest variant that serves every lane of the wave
-            if (!__any(rank != 0)) vp_demap0(cx, cy, a, b);
-            else if (!__any(rank > 1)) vp_demap1(cx, cy, rank, a, b);
-            else if (!__any(rank > 2)) vp_demap2(cx, cy, rank, a, b);
-            else vp_demapN(cx, cy, rank, lut, a, b);
+        if (TIERS == kTierTherm) {
+            const uint32_t th = (uint32_t)(therm >> (4 * i)) & 7u;   // wave-uniform
+            if (th == 0u) {
+                vp_demap0(cpx, cpy, a, b);
+            } else {
+                const int rank = (int)((word >> (4 * i)) & 15ull);
+                const float cx = r[i].x * nl, cy = r[i].y * nl;
+                if (th == 1u) vp_demap1(cpx, cpy, cx, cy, rank, a, b);
+                else if (th == 3u) vp_demap2(cpx, cpy, cx, cy, rank, a, b);
+                else vp_demapN(cpx, cpy, cx, cy, rank, lut, a, b);
+            }
+        } else if (TIERS == kTierAny) {
+            const int rank = (int)((word >> (4 * i)) & 15ull);
+            if (!__any(rank != 0)) {
+                vp_demap0(cpx, cpy, a, b);
+            } else {
+                const float cx = r[i].x * nl, cy = r[i].y * nl;
+                if (!__any(rank > 1)) vp_demap1(cpx, cpy, cx, cy, rank, a, b);
+                else if (!__any(rank > 2)) vp_demap2(cpx, cpy, cx, cy, rank, a, b);
+                else vp_demapN(cpx, cpy, cx, cy, rank, lut, a, b);
+            }
         } else {
-            vp_demapN(cx, cy, rank, lut, a, b);
+            const int rank = (int)((word >> (4 * i)) & 15ull);
+            vp_demapN(cpx, cpy, r[i].x * nl, r[i].y * nl, rank, lut, a, b);
         }
         if (REC) {
             ra[i] = a;
@@ -86,7 +149,7 @@ __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float
 #pragma unroll
         for (int m0 = i + 1; m0 < N; m0 += CH) {
             float2 w[CH];
-            if (UNIFORM_TIERS) {
+            if (TIERS != kTierLut) {
                 // chunk c may load once chunk c-1 has started at this level
                 const float dep = (m0 > i + 1) ? r[m0 - CH].y : a;
                 cfloat *Wk = opaque_uniform(W0, dep);
@@ -124,15 +187,22 @@ __device__ __forceinline__ unsigned long long wave_min(unsigned long long x) {
     return x;
 }
 
-// Rank nibbles of path k (level i at bits 4i..4i+3).
+// Rank nibbles of path k (level i at bits 4i..4i+3): each byte's low nibble.
+// For N = 16 the row is one 16-byte load; per dword the two ranks of each
+// byte pair are merged into one byte (t | t >> 4), and a byte permute
+// gathers bytes 0 and 2 of two such dwords into one dword.
 template <int N>
 __device__ __forceinline__ unsigned long long load_word(const uint8_t *__restrict__ P, int k) {
     unsigned long long wd = 0;
     if (N == 16 && ((reinterpret_cast<uintptr_t>(P) & 15) == 0)) {
         const uint4 q = *reinterpret_cast<const uint4 *>(P + (size_t)k * 16);
-        const uint32_t d[4] = {q.x, q.y, q.z, q.w};
-#pragma unroll
-        for (int i = 0; i < 16; ++i) wd |= (unsigned long long)((d[i >> 2] >> (8 * (i & 3))) & 15u) << (4 * i);
+        auto merge = [](uint32_t x) {
+            const uint32_t t = x & 0x0F0F0F0Fu;
+            return t | (t >> 4);   // byte 0: ranks 0 | 1 << 4, byte 2: ranks 2 | 3 << 4
+        };
+        const uint32_t lo = __builtin_amdgcn_perm(merge(q.y), merge(q.x), 0x06040200u);
+        const uint32_t hi = __builtin_amdgcn_perm(merge(q.w), merge(q.z), 0x06040200u);
+        wd = ((unsigned long long)hi << 32) | lo;
     } else {
 #pragma unroll
         for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[(size_t)k * N + i] & 15) << (4 * i);
