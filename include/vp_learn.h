@@ -190,6 +190,31 @@ int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, co
                        uint32_t flags, const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost,
                        int32_t *kidx, void *work, void *stream);
 
+/* Most vectors one call of vp_search_fallback_noalloc may serve. */
+#define VP_NOALLOC_MAX_VECTORS 65536
+
+/*
+ * vp_search_fallback_noalloc -- vp_search_fallback without the caller's
+ * workspace, for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ *
+ * Same arguments, results and errors as vp_search_fallback, minus `work`:
+ * the fixed search's per-vector cost and index live in a workspace the
+ * library holds in static device memory, one copy per GPU (512 KiB, held
+ * until the process ends; its address is looked up on the first call on
+ * each device).  The call allocates and frees nothing.  Limit: n_sc * n_sym
+ * <= VP_NOALLOC_MAX_VECTORS (a 100 MHz, 14-symbol slot of 3276 subcarriers
+ * fits), else VP_EUNSUPPORTED.  Every call on one GPU uses that GPU's one
+ * workspace, so calls that overlap in time on the same GPU (on different
+ * streams, or from several host threads) race and must be serialised by the
+ * caller; calls on one stream are ordered and safe.  A failed look-up of the
+ * workspace returns VP_ELAUNCH (see vp_last_hip_error()).
+ */
+int vp_search_fallback_noalloc(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau,
+                               const uint8_t *paths, const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc,
+                               int n_sym, int n_r, uint32_t flags, const float *mass, float theta, int32_t kidx_base,
+                               int8_t *l, float *cost, int32_t *kidx, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

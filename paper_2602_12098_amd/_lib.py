@@ -18,6 +18,7 @@ VP_PATHS_PER_VECTOR = 2
 VP_SE_EXACT = 0
 VP_SE_EXHAUSTED = 1
 VP_SE_NONE = 2
+VP_NOALLOC_MAX_VECTORS = 65536
 
 _lib = None
 
@@ -42,6 +43,8 @@ SIGNATURES = {
     "vp_search": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _P, _P, _P],
     "vp_search_fallback": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _F,
                            ctypes.c_int32, _P, _P, _P, _P, _P],
+    "vp_search_fallback_noalloc": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P,
+                                   _F, ctypes.c_int32, _P, _P, _P, _P],
     "vp_precode": [_P, _P, _P, _P, _P, _I, _I, _I, _I, _F, _P, _P],
     "vp_sphere_encode": [_P, _P, _P, _F, _I, _I, _I, _P, ctypes.c_int64, _P, _P, _P, _P, _P],
     "vp_strerror": [_I],

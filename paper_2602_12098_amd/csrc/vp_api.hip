@@ -19,6 +19,8 @@ int launch_status() {
     return VP_OK;
 }
 
+void record_hip_error(int code) { g_last_hip_error.store(code); }
+
 static bool k_exceeds_box(int K, int N) {   // K > 9^N ?
     long long cap = 1;
     for (int i = 0; i < N; ++i) {
@@ -86,6 +88,24 @@ int vp_search_fallback(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, co
     return launch_search_fallback((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K, paths_sc_stride,
                                   n_sc, n_sym, n_r, flags, mass, theta, kidx_base, l, cost, kidx, work,
                                   (hipStream_t)stream);
+}
+
+int vp_search_fallback_noalloc(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau,
+                               const uint8_t *paths, const uint16_t *order, int K, int64_t paths_sc_stride, int n_sc,
+                               int n_sym, int n_r, uint32_t flags, const float *mass, float theta, int32_t kidx_base,
+                               int8_t *l, float *cost, int32_t *kidx, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1) return VP_EINVAL;
+    if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
+    if ((int64_t)n_sc * n_sym > (int64_t)kNoAllocVectors) return VP_EUNSUPPORTED;   // beyond the fixed workspace
+    if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
+    if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;
+    if (flags & ~(uint32_t)VP_INCLUDE_ZERO) return VP_EINVAL;
+    if (isnan(theta) || kidx_base < 0) return VP_EINVAL;
+    if (n_sc == 0) return VP_OK;
+    if (!W || !perm || !s || !tau || !paths || !mass || !l || !cost || !kidx) return VP_EINVAL;
+    return launch_search_fallback_noalloc((const float2 *)W, perm, (const float2 *)s, tau, paths, order, K,
+                                          paths_sc_stride, n_sc, n_sym, n_r, flags, mass, theta, kidx_base, l, cost,
+                                          kidx, (hipStream_t)stream);
 }
 
 int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, const float *tau, const float *cost, int n_sc,
@@ -184,7 +204,7 @@ const char *vp_strerror(int code) {
     switch (code) {
         case VP_OK: return "ok";
         case VP_EINVAL: return "invalid argument";
-        case VP_EUNSUPPORTED: return "unsupported size";
+        case VP_EUNSUPPORTED: return "unsupported size (or beyond the fixed workspace of an allocation-free call)";
         case VP_ELAUNCH: return "HIP launch failure";
         default: return "unknown error";
     }

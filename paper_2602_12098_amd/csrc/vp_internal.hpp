@@ -11,11 +11,15 @@ namespace vp {
 
 // Records the first HIP error of a launch sequence; VP_ELAUNCH on failure.
 int launch_status();
+// Keeps a HIP error code for vp_last_hip_error().
+void record_hip_error(int code);
 
 constexpr int kMaxN = 16;
 constexpr int kMaxM = 64;
 constexpr int kMaxKSearch = 4096;
 constexpr int kMaxKMop = 1024;
+constexpr int kNoAllocVectors = VP_NOALLOC_MAX_VECTORS;   // vectors per call of the allocation-free fallback
+constexpr int kMaxDevices = 64;
 
 // Inclusive scan over the 64 lanes of a wave by DPP moves: shifts by 1 and 2
 // within each row of 16 lanes, by 4 and 8 into the upper banks of a row, then
@@ -84,6 +88,10 @@ int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s
                            const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, int N, uint32_t flags,
                            const float *mass, float theta, int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx,
                            void *work, hipStream_t st);
+int launch_search_fallback_noalloc(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau,
+                                   const uint8_t *paths, const uint16_t *order, int K, int64_t pstride, int n_sc,
+                                   int n_sym, int N, uint32_t flags, const float *mass, float theta,
+                                   int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx, hipStream_t st);
 int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost,
                    int n_sc, int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st);
 

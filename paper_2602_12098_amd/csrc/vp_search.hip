@@ -17,6 +17,8 @@
 //
 // k_search_finalize re-walks the winning path of each vector with the very
 // same arithmetic to materialise l in user order.
+#include <mutex>
+
 #include "vp_walk.hpp"
 
 namespace vp {
@@ -597,6 +599,57 @@ int launch_search_fallback(const float2 *W, const uint8_t *perm, const float2 *s
 #undef VP_CASE
         default: return VP_EUNSUPPORTED;
     }
+}
+
+// Workspace of the allocation-free fallback: the fixed-set search's cost and
+// path index per vector (8 bytes each), for up to kNoAllocVectors vectors.
+// One copy per GPU, alive until the process ends.  In host code `scratch` is
+// only a handle for hipGetSymbolAddress; its device address, which differs
+// per GPU, is looked up once per device and kept in g_scratch below.
+static __device__ __align__(256) unsigned char scratch[kNoAllocVectors * 8];
+
+namespace {
+std::mutex g_scratch_mutex;
+void *g_scratch[kMaxDevices];   // device address of `scratch` per device, nullptr until looked up
+}  // namespace
+
+// Device address of this GPU's workspace (the current device's), looked up
+// with that device current on the first call that needs it.
+static void *scratch_address(int *err) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= kMaxDevices) {
+        *err = (int)(e != hipSuccess ? e : hipErrorInvalidDevice);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            *err = (int)(e != hipSuccess ? e : hipErrorInvalidSymbol);
+            return nullptr;
+        }
+        g_scratch[dev] = p;
+    }
+    return g_scratch[dev];
+}
+
+int launch_search_fallback_noalloc(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau,
+                                   const uint8_t *paths, const uint16_t *order, int K, int64_t pstride, int n_sc,
+                                   int n_sym, int N, uint32_t flags, const float *mass, float theta,
+                                   int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx, hipStream_t st) {
+    if (n_sc == 0) return VP_OK;
+    int err = 0;
+    void *work = scratch_address(&err);
+    if (!work) {
+        record_hip_error(err);
+        return VP_ELAUNCH;
+    }
+    // every vector the fixed search serves writes its own cost and index
+    // before the merge reads them: nothing in the workspace must start at zero
+    return launch_search_fallback(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, N, flags, mass, theta,
+                                  kidx_base, l, cost, kidx, work, st);
 }
 
 }  // namespace vp

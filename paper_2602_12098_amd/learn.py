@@ -218,6 +218,32 @@ def search_fallback(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau, p
     return out
 
 
+def search_fallback_noalloc(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: torch.Tensor,
+                            paths: torch.Tensor, n_sym: int, mass: torch.Tensor, theta: float, out, kidx_base: int,
+                            order: Optional[torch.Tensor] = None, flags: int = VP_INCLUDE_ZERO):
+    """vp_search_fallback_noalloc: search_fallback without a workspace (the
+    library's static per-GPU one, at most VP_NOALLOC_MAX_VECTORS vectors per
+    call).  tau must already be a float32 device tensor [n_sc]: nothing is
+    allocated on this path.  Returns out."""
+    lib = _lib.load()
+    n_sc, K, N = paths.shape
+    n_vec = n_sc * n_sym
+    check(lib.vp_search_fallback_noalloc(_req(W, "W", torch.complex64, (n_sc, packed_size(N))),
+                                         _req(perm, "perm", torch.uint8, (n_sc, N)),
+                                         _req(s, "s", torch.complex64, (N, n_vec)),
+                                         _req(tau, "tau", torch.float32, (n_sc,)),
+                                         _req(paths, "paths", torch.uint8, (n_sc, K, N)),
+                                         _req(order, "order", torch.int16, (n_sc, 2, K)) if order is not None
+                                         else None,
+                                         int(K), int(K * N), n_sc, int(n_sym), N, int(flags),
+                                         _req(mass, "mass", torch.float32, (n_vec,)), float(theta), int(kidx_base),
+                                         _req(out.l, "l", torch.int8, (N, n_vec, 2)),
+                                         _req(out.cost, "cost", torch.float32, (n_vec,)),
+                                         _req(out.kidx, "kidx", torch.int32, (n_vec,)), _stream()),
+          "vp_search_fallback_noalloc")
+    return out
+
+
 # ---------------------------------------------------------------------------
 # the network
 # ---------------------------------------------------------------------------
