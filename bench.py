@@ -294,6 +294,87 @@ def bench_learned_fallback(vp, steps, warmup, wl, H, s, theta=0.3, K_mop=64, K_f
             "ms_per_step": ms, "stages_ms": stages, "gap_db": g}
 
 
+def bench_ablations(vp, dev="cuda:0"):
+    """Power-gap ablations standing in for the paper's coded-BER figures
+    (outside every timed region): sorted (Alg. 1) against unsorted
+    preprocessing at the same path count (the improved-SRQD comparison of
+    Sec. III-B), on the 16x16 slot (K = 512) and the 8x8 workloads at SNR 10,
+    20 and 30 dB (K = 64); and the path count K = 2..8 at 8x8 (the
+    most-promising-path count study).  Exact VP comes from the GPU sphere
+    encoder on the sorted factorisation (the optimum does not depend on the
+    factorisation), seeded with the smaller of the two costs."""
+    import torch
+    import vpgen
+
+    def run(wl, K, sorted_):
+        H = torch.from_numpy(wl.H).to(dev)
+        s = torch.from_numpy(wl.s).to(dev)
+        prep = vp.preprocess(H, wl.alpha, sorted=sorted_)
+        order = torch.empty((wl.n_sc, 2, K), dtype=torch.int16, device=dev)
+        paths = vp.paths_mop(prep.w2, K, order=order)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        out = vp.search(prep.W, prep.perm, s, wl.tau, paths, wl.n_sym, order=order)
+        e1.record()
+        torch.cuda.synchronize()
+        return prep, s, out, e0.elapsed_time(e1)
+
+    def exact(prep, s, tau, n_sym, cost):
+        se = vp.sphere_encode(prep.W, prep.perm, s, tau, n_sym, radius=cost * (1 + 1e-6))
+        return torch.where(torch.isfinite(se.cost), se.cost, cost).double()
+
+    def gap(c, ex):
+        return 10 * math.log10(float(c.double().sum()) / float(ex.sum()))
+
+    res = {"sorted_vs_unsorted": {}, "K_sweep_8x8": {}}
+    for wl in (vpgen.cfg3(512), vpgen.cfg2(10), vpgen.cfg2(20), vpgen.cfg2(30)):
+        K = wl.K
+        ps, s, os_, ts = run(wl, K, True)
+        pu, _, ou, tu = run(wl, K, False)
+        ex = exact(ps, s, wl.tau, wl.n_sym, torch.minimum(os_.cost, ou.cost))
+        res["sorted_vs_unsorted"][wl.name] = {
+            "K": K, "gap_db_sorted": gap(os_.cost, ex), "gap_db_unsorted": gap(ou.cost, ex),
+            "search_ms_sorted": ts, "search_ms_unsorted": tu, "vectors": wl.n_vec}
+    # one QAM order per user (4..256) on the 16x16 correlated workload: the
+    # per-user intervals (vp_apply_user_tau) against one common interval, the
+    # largest, for every user (also decodable, at more transmit power)
+    rng = np.random.default_rng(5)
+    wl = vpgen.cfg3(512, n_sc=1092)
+    Qu = np.array([4, 16, 64, 256])[rng.integers(0, 4, size=(wl.n_sc, wl.N))]
+    tau_u = torch.from_numpy((2 * np.sqrt(Qu)).astype(np.float32)).to(dev)
+    s_np = np.zeros_like(wl.s)
+    for sc in range(wl.n_sc):
+        for u in range(wl.N):
+            s_np[u, sc * wl.n_sym:(sc + 1) * wl.n_sym] = vpgen.draw_symbols(rng, 1, wl.n_sym, int(Qu[sc, u]))[0]
+    H = torch.from_numpy(wl.H).to(dev)
+    s = torch.from_numpy(s_np).to(dev)
+    prep = vp.preprocess(H, wl.alpha)
+    pc = vp.Prep(prep.W.clone(), prep.w2.clone(), prep.perm.clone(), prep.G.clone(), prep.status.clone())
+    sp = vp.apply_user_tau(prep, s, tau_u, wl.n_sym)
+    order = torch.empty((wl.n_sc, 2, 512), dtype=torch.int16, device=dev)
+    paths = vp.paths_mop(prep.w2, 512, order=order)
+    o = vp.search(prep.W, prep.perm, sp, 1.0, paths, wl.n_sym, order=order)
+    ex = exact(prep, sp, 1.0, wl.n_sym, o.cost)
+    paths_c = vp.paths_mop(pc.w2, 512, order=order)
+    oc = vp.search(pc.W, pc.perm, s, 32.0, paths_c, wl.n_sym, order=order)
+    res["per_user_tau"] = {
+        "workload": f"16x16 rho 0.5, {wl.n_sc} subcarriers x 14, QAM order per user uniform on 4..256, K = 512",
+        "gap_db": gap(o.cost, ex),
+        "power_common_tau_over_per_user_db": 10 * math.log10(float(oc.cost.double().sum()) /
+                                                             float(o.cost.double().sum()))}
+    for snr in (10, 20, 30):
+        wl = vpgen.cfg2(snr)
+        ref = None
+        row = {}
+        for K in (2, 3, 4, 5, 6, 7, 8, 16, 64):
+            p, s, o, _ = run(wl, K, True)
+            if ref is None:
+                ref = exact(p, s, wl.tau, wl.n_sym, o.cost)
+            row[str(K)] = gap(o.cost, ref)
+        res["K_sweep_8x8"][f"snr{snr}"] = row
+    return res
+
+
 # The workload the oracle workers read: built once in the parent before the
 # pool forks, so that no worker regenerates it inside the timed wall.
 _CPU_WL = None
@@ -534,6 +615,9 @@ def main():
                                          "ms_per_step": rp["wall_ms_per_step"], "stages_ms": rp["stages_ms"],
                                          "gap_db": g}
             del rp
+    if not args.no_extras:
+        print("ablations ...", file=sys.stderr, flush=True)
+        line["ablations"] = bench_ablations(vp, dev)
     l_host = None
     if not args.no_cpu:
         l_i8 = sout.l.cpu().numpy()

@@ -104,6 +104,17 @@ int vp_preprocess(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c
                   uint8_t *perm, vp_c32 *G, int32_t *status, void *stream);
 
 /*
+ * vp_preprocess_unsorted -- vp_preprocess without the sorting of Alg. 1: the
+ * plain Cholesky factorisation A = Lbar Lbar^H in the users' own order
+ * (perm = identity).  It is the unsorted reference against which Sec. III-B
+ * measures the gain of the improved sorted QR decomposition; the search,
+ * precoding and sphere encoder accept its outputs unchanged.  Arguments,
+ * outputs and errors as vp_preprocess.
+ */
+int vp_preprocess_unsorted(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c32 *W, float *w2,
+                           uint8_t *perm, vp_c32 *G, int32_t *status, void *stream);
+
+/*
  * vp_paths_mop -- most promising paths (Sec. III-A-2, eq_mop; Alg. 2
  * "MoP-Search").
  *
@@ -196,6 +207,32 @@ int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float
  */
 int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, const float *tau, const float *cost,
                int n_sc, int n_sym, int n_r, int n_t, float P_T, vp_c32 *x, void *stream);
+
+/*
+ * vp_apply_user_tau -- one perturbation interval per user (Sec. II-B with a
+ * QAM order per user; the paper's tau is one system constant).
+ *
+ * The search objective || W (s_pi + D l) ||^2 with D = diag(tau of the user
+ * at each level) equals || W' (s'_pi + l) ||^2 with W' = W D and s' = s / tau
+ * per user, so after this call the other entry points run unchanged with
+ * tau = 1 on every subcarrier: the per-level tau enters the walk through W'
+ * (centres c_i = -r_i / (tau_i W_ii), residual steps tau_i W_mi l_i) and the
+ * Metric-of-Promise weights become |W'_ii|^2 = tau_i^2 w2_i.  G' = G diag(tau)
+ * gives x = G' (s' + l) = G (s + tau l).  For QAM, tau = 2 sqrt(Q) is a power of
+ * two and every scaling here is exact in float32.
+ *
+ *  tau_user [n_sc][N]  per-user intervals (user order), finite and > 0
+ *  perm     [n_sc][N]  from vp_preprocess
+ *  W, w2    in/out: scaled in place (vp_preprocess outputs)
+ *  G        in/out or NULL: scaled in place
+ *  s        [N][n_vec] input symbols;  s_out [N][n_vec] output s' (may equal s)
+ *
+ * Errors: VP_EINVAL for NULL pointers or bad sizes; VP_EUNSUPPORTED for
+ * N > 16 or M > 64.  Run it once per slot, after vp_preprocess and before
+ * vp_paths_mop.
+ */
+int vp_apply_user_tau(const float *tau_user, const uint8_t *perm, int n_sc, int n_sym, int n_r, int n_t, vp_c32 *W,
+                      float *w2, vp_c32 *G, const vp_c32 *s, vp_c32 *s_out, void *stream);
 
 /*
  * vp_sphere_encode -- exact vector perturbation over the B = 1 box (eq:se,

@@ -143,19 +143,38 @@ def forward_inverse(L: np.ndarray) -> np.ndarray:
     return W
 
 
-def preprocess(H: np.ndarray, alpha: float, want_G: bool = True) -> Prep:
+def cholesky_unsorted(A: np.ndarray):
+    """A = L L^H without pivoting (users in their own order): the unsorted
+    factorisation that Sec. III-B compares the sorted one (Alg. 1) with.
+    Same returns as cholesky_minpivot; the margins are all inf (no choice)."""
+    A = np.asarray(A, dtype=np.complex128)
+    n = A.shape[0]
+    try:
+        L = np.linalg.cholesky(A)
+        status = STATUS_OK
+    except np.linalg.LinAlgError:
+        L = np.zeros((n, n), dtype=np.complex128)
+        status = STATUS_NOT_PD
+    pivots = np.abs(np.diag(L)) ** 2
+    floor = n * np.finfo(np.float64).eps * float(np.max(np.real(np.diag(A))))
+    if status == STATUS_OK and np.min(pivots) <= floor:
+        status = STATUS_NOT_PD
+    return L, np.arange(n), pivots, np.full(n, np.inf), status
+
+
+def preprocess(H: np.ndarray, alpha: float, want_G: bool = True, sort: bool = True) -> Prep:
     """Per-subcarrier preprocessing of Alg. 2's "regularise and factorise" step:
-    A = H H^H + alpha I, sorted factorisation (Alg. 1 via its Cholesky form),
-    W = Rbar^{-1}, MoP weights w_i = |W_ii|^2 (eq_mop) and the RZF matrix
-    G = H^H A^{-1} (Sec. II-A; equal to the Tikhonov pseudo-inverse of
-    Sec. III-A-1)."""
+    A = H H^H + alpha I, sorted factorisation (Alg. 1 via its Cholesky form;
+    with sort=False the plain one in user order), W = Rbar^{-1}, MoP weights
+    w_i = |W_ii|^2 (eq_mop) and the RZF matrix G = H^H A^{-1} (Sec. II-A;
+    equal to the Tikhonov pseudo-inverse of Sec. III-A-1)."""
     H = np.asarray(H, dtype=np.complex128)
     if not np.all(np.isfinite(H.view(np.float64))) or not math.isfinite(alpha):
         n = H.shape[0]
         return Prep(np.zeros((n, n), complex), np.zeros((n, n), complex), np.arange(n),
                     np.zeros(n), None, STATUS_NONFINITE, np.zeros(n), np.full(n, np.inf))
     A = gram(H, alpha)
-    L, perm, pivots, margins, status = cholesky_minpivot(A)
+    L, perm, pivots, margins, status = cholesky_minpivot(A) if sort else cholesky_unsorted(A)
     if status != STATUS_OK:
         n = H.shape[0]
         return Prep(L, np.zeros((n, n), complex), perm, np.zeros(n), None, status, pivots, margins)
@@ -250,24 +269,35 @@ class SearchResult:
     margin: np.ndarray     # [n_vec][K] smallest order margin met along each path
 
 
+def level_tau(tau, perm):
+    """tau per tree level: a scalar (the paper's one system constant, Sec. II-B)
+    or one value per user (a QAM order per user), taken in level order."""
+    t = np.asarray(tau, dtype=np.float64)
+    n = len(perm)
+    return np.full(n, float(t)) if t.ndim == 0 else t[np.asarray(perm)]
+
+
 def demap_walk(W, st, tau, ranks):
     """Walk the tree along position vectors for many (vector, path) pairs at once.
 
     st: complex [V][N] = W s_pi (s-tilde of the PED recursion); ranks: int
-    [P][N].  Returns (l [V][P][N], cost [V][P], margin [V][P]).  At level i the
-    centre is c_i = -r_i / (tau W_ii) where r_i is the running residual
-    s-tilde_i + tau sum_{j<i} W_ij l_j (the s-hat of Sec. III-A-2 with l = -t);
+    [P][N]; tau: a scalar or one value per level.  Returns (l [V][P][N],
+    cost [V][P], margin [V][P]).  At level i the centre is
+    c_i = -r_i / (tau_i W_ii) where r_i is the running residual
+    s-tilde_i + sum_{j<i} tau_j W_ij l_j (the s-hat of Sec. III-A-2 with l = -t);
     the child of rank p_i is the p_i-th box point in the (distance, j) order;
-    the PED grows by tau^2 |W_ii|^2 |c_i - l_i|^2 (Sec. II-B)."""
+    the PED grows by tau_i^2 |W_ii|^2 |c_i - l_i|^2 (Sec. II-B)."""
     V, n = st.shape
     P = ranks.shape[0]
+    taul = np.broadcast_to(np.asarray(tau, dtype=np.float64), (n,))
     resid = np.broadcast_to(st[:, None, :], (V, P, n)).copy()
     l = np.zeros((V, P, n), dtype=np.complex128)
     cost = np.zeros((V, P))
     margin = np.full((V, P), np.inf)
     for i in range(n):
         wii = W[i, i]
-        c = -resid[:, :, i] / (tau * wii)
+        ti = taul[i]
+        c = -resid[:, :, i] / (ti * wii)
         d = sqabs(c[:, :, None] - BOX[None, None, :])                    # [V][P][9]
         order = np.argsort(d, axis=2, kind="stable")                      # (d, j) order
         dsorted = np.take_along_axis(d, order, axis=2)
@@ -281,9 +311,9 @@ def demap_walk(W, st, tau, ranks):
         margin = np.minimum(margin, np.minimum(lo, hi))
         li = BOX[j]
         l[:, :, i] = li
-        cost += (tau ** 2) * (abs(wii) ** 2) * dch
+        cost += (ti ** 2) * (abs(wii) ** 2) * dch
         if i + 1 < n:
-            resid[:, :, i + 1:] += tau * W[None, None, i + 1:, i] * li[:, :, None]
+            resid[:, :, i + 1:] += ti * W[None, None, i + 1:, i] * li[:, :, None]
     return l, cost, margin
 
 
@@ -292,8 +322,9 @@ def search_paths(W, perm, s, tau, paths, include_zero: bool = True) -> SearchRes
     of s, user order) evaluate every path of the set, then take the argmin.
 
     W: complex [N][N] lower (search order); perm: level -> user; s: complex
-    [N][V] (user order); paths: int [K][N] ranks 0..8.  With include_zero, the
-    zero perturbation (plain RZF) is candidate index K."""
+    [N][V] (user order); tau: a scalar or one value per user; paths: int
+    [K][N] ranks 0..8.  With include_zero, the zero perturbation (plain RZF)
+    is candidate index K."""
     W = np.asarray(W, dtype=np.complex128)
     perm = np.asarray(perm, dtype=np.int64)
     s = np.asarray(s, dtype=np.complex128)
@@ -303,7 +334,7 @@ def search_paths(W, perm, s, tau, paths, include_zero: bool = True) -> SearchRes
     K, n = paths.shape
     s_pi = s[perm, :].T                     # [V][N] level order
     st = s_pi @ W.T                         # s-tilde = W s_pi, per vector
-    l, cost, margin = demap_walk(W, st, tau, paths)
+    l, cost, margin = demap_walk(W, st, level_tau(tau, perm), paths)
     if include_zero:
         c0 = np.sum(np.abs(st) ** 2, axis=1)
         cost_all = np.concatenate([cost, c0[:, None]], axis=1)
@@ -318,15 +349,16 @@ def search_paths(W, perm, s, tau, paths, include_zero: bool = True) -> SearchRes
     return SearchResult(l_sel, cost_all[np.arange(V), k], k, cost_all, l, margin)
 
 
-def cost_closed_form(A: np.ndarray, s: np.ndarray, l: np.ndarray, tau: float) -> float:
-    """u^H A^{-1} u with u = s + tau l (user order): the quantity eq:se minimises,
-    written with the RZF inverse (Sec. III-A-1)."""
+def cost_closed_form(A: np.ndarray, s: np.ndarray, l: np.ndarray, tau) -> float:
+    """u^H A^{-1} u with u = s + tau l (user order; tau a scalar or one value per
+    user): the quantity eq:se minimises, written with the RZF inverse
+    (Sec. III-A-1)."""
     u = np.asarray(s, np.complex128) + tau * np.asarray(l, np.complex128)
     return float(np.real(np.vdot(u, np.linalg.solve(A, u))))
 
 
 def cost_tri(W, perm, s, l, tau) -> float:
-    """|| W (s + tau l)_pi ||^2 (eq_qrse with l = -t)."""
+    """|| W (s + tau l)_pi ||^2 (eq_qrse with l = -t; tau a scalar or per user)."""
     u = np.asarray(s, np.complex128) + tau * np.asarray(l, np.complex128)
     return float(np.sum(np.abs(np.asarray(W, np.complex128) @ u[np.asarray(perm)]) ** 2))
 
@@ -337,13 +369,14 @@ def cost_tri(W, perm, s, l, tau) -> float:
 
 def brute_force(W, perm, s, tau):
     """Exact minimiser of eq:se over the whole box B^N (9^N candidates): the
-    smallest || W (s_pi + tau l) ||^2; ties -> lexicographically smallest box
-    index vector in level order.  Returns (l user order, cost)."""
+    smallest || W (s_pi + tau l) ||^2 (tau a scalar or one per user); ties ->
+    lexicographically smallest box index vector in level order.  Returns
+    (l user order, cost)."""
     W = np.asarray(W, np.complex128)
     n = W.shape[0]
     s_pi = np.asarray(s, np.complex128)[np.asarray(perm)]
     J = np.array(list(itertools.product(range(NBOX), repeat=n)), dtype=np.int64)   # lexicographic
-    U = s_pi[None, :] + tau * BOX[J]
+    U = s_pi[None, :] + level_tau(tau, perm)[None, :] * BOX[J]
     costs = np.sum(np.abs(U @ W.T) ** 2, axis=1)
     b = int(np.argmin(costs))
     l = np.zeros(n, dtype=np.complex128)
@@ -360,16 +393,17 @@ def sphere_encode(W, perm, s, tau, radius: float = math.inf):
     n = W.shape[0]
     s_pi = np.asarray(s, np.complex128)[np.asarray(perm)]
     st = W @ s_pi
+    taul = level_tau(tau, perm)
     best = [radius, None]
     nodes = [0]
     lvl_l = np.zeros(n, dtype=np.complex128)
 
     def rec(i, resid, ped):
         wii = W[i, i]
-        c = -resid[i] / (tau * wii)
+        c = -resid[i] / (taul[i] * wii)
         d = sqabs(c - BOX)
         for j in np.argsort(d, kind="stable"):
-            nped = ped + tau * tau * abs(wii) ** 2 * d[j]
+            nped = ped + taul[i] ** 2 * abs(wii) ** 2 * d[j]
             if nped >= best[0]:
                 break
             nodes[0] += 1
@@ -378,7 +412,7 @@ def sphere_encode(W, perm, s, tau, radius: float = math.inf):
                 best[0] = nped
                 best[1] = lvl_l.copy()
             else:
-                rec(i + 1, resid + tau * W[:, i] * BOX[j] * (np.arange(n) > i), nped)
+                rec(i + 1, resid + taul[i] * W[:, i] * BOX[j] * (np.arange(n) > i), nped)
 
     rec(0, st.copy(), 0.0)
     if best[1] is None:

@@ -39,6 +39,7 @@ _F = ctypes.c_float
 
 SIGNATURES = {
     "vp_preprocess": [_P, _I, _I, _I, _F, _P, _P, _P, _P, _P, _P],
+    "vp_preprocess_unsorted": [_P, _I, _I, _I, _F, _P, _P, _P, _P, _P, _P],
     "vp_paths_mop": [_P, _I, _I, _I, _P, _P, _P],
     "vp_search": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _P, _P, _P],
     "vp_search_fallback": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P, _F,
@@ -46,6 +47,7 @@ SIGNATURES = {
     "vp_search_fallback_noalloc": [_P, _P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, ctypes.c_uint32, _P,
                                    _F, ctypes.c_int32, _P, _P, _P, _P],
     "vp_precode": [_P, _P, _P, _P, _P, _I, _I, _I, _I, _F, _P, _P],
+    "vp_apply_user_tau": [_P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P],
     "vp_sphere_encode": [_P, _P, _P, _F, _I, _I, _I, _P, ctypes.c_int64, _P, _P, _P, _P, _P],
     "vp_strerror": [_I],
     "vp_last_hip_error": [],

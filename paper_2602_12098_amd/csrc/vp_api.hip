@@ -47,6 +47,17 @@ int vp_preprocess(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c
                              (hipStream_t)stream);
 }
 
+int vp_preprocess_unsorted(const vp_c32 *H, int n_sc, int n_r, int n_t, float alpha, vp_c32 *W, float *w2,
+                           uint8_t *perm, vp_c32 *G, int32_t *status, void *stream) {
+    if (n_sc < 0 || n_r < 1 || n_t < 1 || !(alpha >= 0.f) || !isfinite(alpha)) return VP_EINVAL;
+    if (n_r > kMaxN || n_t > kMaxM) return VP_EUNSUPPORTED;
+    if (alpha == 0.f && n_r > n_t) return VP_EINVAL;
+    if (n_sc == 0) return VP_OK;
+    if (!H || !W || !w2 || !perm || !status) return VP_EINVAL;
+    return launch_preprocess((const float2 *)H, n_sc, n_r, n_t, alpha, (float2 *)W, w2, perm, (float2 *)G, status,
+                             (hipStream_t)stream, false);
+}
+
 int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint16_t *order, void *stream) {
     if (n_sc < 0 || n_r < 1 || K < 1) return VP_EINVAL;
     if (n_r > kMaxN || K > kMaxKMop) return VP_EUNSUPPORTED;
@@ -117,6 +128,16 @@ int vp_precode(const vp_c32 *G, const vp_c32 *s, const int8_t *l, const float *t
     if (!G || !s || !l || !tau || !x || (P_T > 0.f && !cost)) return VP_EINVAL;
     return launch_precode((const float2 *)G, (const float2 *)s, l, tau, cost, n_sc, n_sym, n_r, n_t, P_T,
                           (float2 *)x, (hipStream_t)stream);
+}
+
+int vp_apply_user_tau(const float *tau_user, const uint8_t *perm, int n_sc, int n_sym, int n_r, int n_t, vp_c32 *W,
+                      float *w2, vp_c32 *G, const vp_c32 *s, vp_c32 *s_out, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || n_t < 1) return VP_EINVAL;
+    if (n_r > kMaxN || n_t > kMaxM) return VP_EUNSUPPORTED;
+    if (n_sc == 0) return VP_OK;
+    if (!tau_user || !perm || !W || !w2 || !s || !s_out) return VP_EINVAL;
+    return launch_user_tau(tau_user, perm, n_sc, n_sym, n_r, n_t, (float2 *)W, w2, (float2 *)G, (const float2 *)s,
+                           (float2 *)s_out, (hipStream_t)stream);
 }
 
 int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym,

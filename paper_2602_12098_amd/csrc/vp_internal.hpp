@@ -77,7 +77,7 @@ inline bool allow_dynamic_lds(K *kernel, size_t bytes) {
 
 // Launchers, one per kernel family (defined next to their kernels).
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
-                      uint8_t *perm, float2 *G, int32_t *status, hipStream_t st);
+                      uint8_t *perm, float2 *G, int32_t *status, hipStream_t st, bool sorted = true);
 int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st);
 int launch_mop_kbest(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t *order, hipStream_t st);
 int launch_search(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
@@ -92,6 +92,8 @@ int launch_search_fallback_noalloc(const float2 *W, const uint8_t *perm, const f
                                    const uint8_t *paths, const uint16_t *order, int K, int64_t pstride, int n_sc,
                                    int n_sym, int N, uint32_t flags, const float *mass, float theta,
                                    int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx, hipStream_t st);
+int launch_user_tau(const float *tau, const uint8_t *perm, int n_sc, int n_sym, int N, int M, float2 *W, float *w2,
+                    float2 *G, const float2 *s, float2 *s_out, hipStream_t st);
 int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost,
                    int n_sc, int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st);
 

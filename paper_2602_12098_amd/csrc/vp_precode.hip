@@ -6,6 +6,8 @@
 // subcarrier's G and the vectors' u = s + tau l are staged in LDS with
 // coalesced loads, then one lane per (vector, antenna), antennas fastest,
 // forms x = G u, so each vector's output row is written by consecutive lanes.
+#include <algorithm>
+
 #include "vp_internal.hpp"
 
 namespace vp {
@@ -58,7 +60,62 @@ __global__ __launch_bounds__(kT) void k_precode(const float2 *__restrict__ G, co
     }
 }
 
+// Per-user perturbation intervals (one QAM order per user): W's column i
+// times tau of the user at level i, w2 times its square, G's column u times
+// tau_u, and s's row u divided by tau_u.  One thread per entry of the largest
+// of those arrays for its subcarrier.
+__global__ __launch_bounds__(kT) void k_user_tau(const float *__restrict__ tau, const uint8_t *__restrict__ perm,
+                                                 int n_sc, int n_sym, int N, int M, float2 *__restrict__ W,
+                                                 float *__restrict__ w2, float2 *__restrict__ G,
+                                                 const float2 *__restrict__ s, float2 *__restrict__ s_out) {
+    const int NP = VP_PACKED(N);
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    const size_t i = (size_t)blockIdx.x * kT + threadIdx.x;
+    const size_t per_sc = (size_t)max(max(NP, M * N), N * n_sym);
+    if (i >= per_sc * n_sc) return;
+    const int sc = (int)(i / per_sc), e = (int)(i % per_sc);
+    const float *ts = tau + (size_t)sc * N;
+    const uint8_t *pm = perm + (size_t)sc * N;
+    if (e < NP) {   // packed column-major lower: entry e lies in column j
+        int j = 0, rem = e;
+        while (rem >= N - j) {
+            rem -= N - j;
+            ++j;
+        }
+        const int u = pm[j] < N ? pm[j] : N - 1;
+        float2 w = W[(size_t)sc * NP + e];
+        w.x *= ts[u];
+        w.y *= ts[u];
+        W[(size_t)sc * NP + e] = w;
+        if (rem == 0) w2[(size_t)sc * N + j] *= ts[u] * ts[u];
+    }
+    if (G && e < M * N) {   // G [M][N], user columns
+        float2 g = G[(size_t)sc * M * N + e];
+        const float t = ts[e % N];
+        g.x *= t;
+        g.y *= t;
+        G[(size_t)sc * M * N + e] = g;
+    }
+    if (e < N * n_sym) {   // s [N][n_vec]: user row, this subcarrier's symbols
+        const int u = e / n_sym, sym = e % n_sym;
+        const size_t o = (size_t)u * n_vec + (size_t)sc * n_sym + sym;
+        const float2 x = s[o];
+        const float r = 1.0f / ts[u];
+        s_out[o] = make_float2(x.x * r, x.y * r);
+    }
+}
+
 }  // namespace
+
+int launch_user_tau(const float *tau, const uint8_t *perm, int n_sc, int n_sym, int N, int M, float2 *W, float *w2,
+                    float2 *G, const float2 *s, float2 *s_out, hipStream_t st) {
+    if (n_sc == 0) return VP_OK;
+    const size_t per_sc = (size_t)std::max(std::max(VP_PACKED(N), M * N), N * n_sym);
+    const size_t total = per_sc * (size_t)n_sc;
+    hipLaunchKernelGGL(k_user_tau, dim3((unsigned)((total + kT - 1) / kT)), dim3(kT), 0, st, tau, perm, n_sc, n_sym,
+                       N, M, W, w2, G, s, s_out);
+    return launch_status();
+}
 
 int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost, int n_sc,
                    int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st) {

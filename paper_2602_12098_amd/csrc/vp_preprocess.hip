@@ -63,10 +63,12 @@ __device__ __forceinline__ void forward_column(int c, const int *sperm, const fl
 
 // One subcarrier: Hs its [N][M] channel; Wsc, w2sc, permsc, Gsc (or NULL),
 // status_sc its outputs; sH: LDS for N * M channel entries.
+// sorted = false: no pivoting, users in their own order (the unsorted
+// factorisation the sorted one is compared with in Sec. III-B).
 __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha,
                                                float2 *__restrict__ Wsc, float *__restrict__ w2sc,
                                                uint8_t *__restrict__ permsc, float2 *__restrict__ Gsc,
-                                               int32_t *__restrict__ status_sc, float2 *sH) {
+                                               int32_t *__restrict__ status_sc, float2 *sH, bool sorted = true) {
     __shared__ float2 S[kMaxN][kMaxN + 1];    // Schur complement, user indices; later A^{-1}
     __shared__ float2 Lc[kMaxN][kMaxN + 1];   // Lc[u][k]: user u's entry of factor column k
     __shared__ float2 Wl[kMaxN][kMaxN + 1];   // W = Lbar^{-1}, search order
@@ -142,8 +144,12 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
             d = take ? od : d;
             u = take ? ou : u;
         }
-        const int p = __builtin_amdgcn_readfirstlane(u);
+        int p = __builtin_amdgcn_readfirstlane(u);
         d = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(d)));
+        if (!sorted) {   // the next user in order, whatever its Schur diagonal
+            p = step;
+            d = S[step][step].x;
+        }
         if (!(d > floor_) && st == VP_STATUS_OK) st = VP_STATUS_NOT_PD;
         if (t == 0) sperm[step] = p;
         rem &= ~(1u << p);
@@ -263,12 +269,12 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
 __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H, int N, int M, float alpha,
                                                    float2 *__restrict__ Wout, float *__restrict__ w2out,
                                                    uint8_t *__restrict__ perm_out, float2 *__restrict__ Gout,
-                                                   int32_t *__restrict__ status_out) {
+                                                   int32_t *__restrict__ status_out, int sorted) {
     extern __shared__ float2 sH[];   // [N * M]
     const size_t sc = blockIdx.x;
     const size_t NM = (size_t)N * M;
     preprocess_one(H + sc * NM, N, M, alpha, Wout + sc * VP_PACKED(N), w2out + sc * N, perm_out + sc * N,
-                   Gout ? Gout + sc * NM : nullptr, status_out + sc, sH);
+                   Gout ? Gout + sc * NM : nullptr, status_out + sc, sH, sorted != 0);
 }
 
 // Batched: one wave per subcarrier of any group.
@@ -298,10 +304,10 @@ int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, i
 }
 
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
-                      uint8_t *perm, float2 *G, int32_t *status, hipStream_t st) {
+                      uint8_t *perm, float2 *G, int32_t *status, hipStream_t st, bool sorted) {
     if (n_sc == 0) return VP_OK;
     hipLaunchKernelGGL(k_preprocess, dim3(n_sc), dim3(kT), (size_t)N * M * sizeof(float2), st, H, N, M, alpha, W, w2,
-                       perm, G, status);
+                       perm, G, status, sorted ? 1 : 0);
     return launch_status();
 }
 

@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, VP_SE_EXACT, VP_SE_EXHAUSTED, VP_SE_NONE, check
 
-__all__ = ["Prep", "SearchOut", "SEOut", "tau_array", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
+__all__ = ["Prep", "SearchOut", "SEOut", "tau_array", "apply_user_tau", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
            "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "VP_SE_EXACT", "VP_SE_EXHAUSTED", "VP_SE_NONE", "version"]
 
 
@@ -62,8 +62,10 @@ class SearchOut(NamedTuple):
     kidx: torch.Tensor    # int32 [n_vec]
 
 
-def preprocess(H: torch.Tensor, alpha: float, want_G: bool = True, out: Optional[Prep] = None) -> Prep:
-    """vp_preprocess: H complex64 [n_sc][N][M] -> W, w2, perm, G, status."""
+def preprocess(H: torch.Tensor, alpha: float, want_G: bool = True, out: Optional[Prep] = None,
+               sorted: bool = True) -> Prep:
+    """vp_preprocess (sorted = False: vp_preprocess_unsorted): H complex64
+    [n_sc][N][M] -> W, w2, perm, G, status."""
     lib = _lib.load()
     n_sc, N, M = H.shape
     dev = H.device
@@ -79,7 +81,9 @@ def preprocess(H: torch.Tensor, alpha: float, want_G: bool = True, out: Optional
     pp = _req(out.perm, "perm", torch.uint8, (n_sc, N))
     pG = _req(out.G, "G", torch.complex64, (n_sc, M, N)) if out.G is not None else None
     ps = _req(out.status, "status", torch.int32, (n_sc,))
-    check(lib.vp_preprocess(pH, n_sc, N, M, float(alpha), pW, pw, pp, pG, ps, _stream()), "vp_preprocess")
+    fn = lib.vp_preprocess if sorted else lib.vp_preprocess_unsorted
+    check(fn(pH, n_sc, N, M, float(alpha), pW, pw, pp, pG, ps, _stream()),
+          "vp_preprocess" if sorted else "vp_preprocess_unsorted")
     return out
 
 
@@ -155,6 +159,29 @@ def precode(G: torch.Tensor, s: torch.Tensor, l: torch.Tensor, tau, cost: Option
     check(lib.vp_precode(pG, ps, pl, taus.data_ptr(), pc, n_sc, int(n_sym), N, M, float(P_T), px, _stream()),
           "vp_precode")
     return out
+
+
+def apply_user_tau(prep: Prep, s: torch.Tensor, tau_user: torch.Tensor, n_sym: int,
+                   s_out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """vp_apply_user_tau: scales prep.W, prep.w2 and prep.G in place for the
+    per-user intervals tau_user (float32 [n_sc][N], user order) and returns
+    s' = s / tau per user; then search, paths_mop, precode and sphere_encode
+    run with tau = 1."""
+    lib = _lib.load()
+    n_sc, N = prep.perm.shape
+    M = prep.G.shape[1] if prep.G is not None else 1
+    n_vec = n_sc * n_sym
+    if s_out is None:
+        s_out = torch.empty_like(s)
+    check(lib.vp_apply_user_tau(_req(tau_user, "tau_user", torch.float32, (n_sc, N)),
+                                _req(prep.perm, "perm", torch.uint8, (n_sc, N)), n_sc, int(n_sym), N, M,
+                                _req(prep.W, "W", torch.complex64, (n_sc, packed_size(N))),
+                                _req(prep.w2, "w2", torch.float32, (n_sc, N)),
+                                _req(prep.G, "G", torch.complex64, (n_sc, M, N)) if prep.G is not None else None,
+                                _req(s, "s", torch.complex64, (N, n_vec)), _req(s_out, "s_out", torch.complex64,
+                                                                                (N, n_vec)), _stream()),
+          "vp_apply_user_tau")
+    return s_out
 
 
 def version() -> str:

@@ -600,3 +600,78 @@ def test_sphere_encoder_budget_keeps_the_best_point(vp):
     torch.cuda.synchronize()
     assert np.all(host(tiny.status) == vp.VP_SE_NONE) and np.all(np.isnan(host(tiny.cost)))
     assert not np.any(host(tiny.l))
+
+
+def test_unsorted_preprocess_and_search(vp):
+    # the unsorted factorisation (Sec. III-B's reference for the improved
+    # sorted QR) against the oracle's, and the search on its W, same-input
+    for wl in (vpgen.cfg2(20, n_sc=24), vpgen.cfg3(512, n_sc=10)):
+        _say("unsorted", wl.name)
+        Hd, sd = _to_dev(wl.H), _to_dev(wl.s)
+        prep = vp.preprocess(Hd, wl.alpha, sorted=False)
+        order = torch.empty((wl.n_sc, 2, wl.K), dtype=torch.int16, device=DEV)
+        paths = vp.paths_mop(prep.w2, wl.K, order=order)
+        out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, wl.n_sym, order=order)
+        torch.cuda.synchronize()
+        assert np.all(host(prep.status) == 0)
+        perm = host(prep.perm)
+        assert np.all(perm == np.arange(wl.N)[None, :])
+        Wd = unpack_W(host(prep.W), wl.N)
+        G = host(prep.G)
+        w2 = host(prep.w2)
+        for sc in range(wl.n_sc):
+            ref = O.preprocess(wl.H[sc], wl.alpha, sort=False)
+            scale = np.abs(ref.W).max()
+            assert np.abs(Wd[sc] - ref.W).max() <= 2e-5 * scale * wl.N, sc
+            np.testing.assert_allclose(w2[sc], ref.w2, rtol=2e-5 * wl.N)
+            assert np.abs(G[sc] - ref.G).max() <= 2e-5 * np.abs(ref.G).max() * wl.N
+        rep = check_same_input(vp, wl, prep, paths, out, range(wl.n_sc), kind="unsorted")
+        _say(rep)
+        assert rep.ok(), rep.failures[:5]
+        assert rep.exact >= 0.99 * rep.n
+
+
+def test_per_user_tau(vp):
+    # one QAM order per user inside every subcarrier: the GPU rescales W, w2,
+    # G and s (vp_apply_user_tau) and then runs the unchanged path with
+    # tau = 1; the oracle walks the unscaled W with the per-level tau directly
+    rng = np.random.default_rng(2027)
+    N, M, n_sc, n_sym, K, alpha = 16, 16, 12, 14, 256, 0.16
+    Qu = np.array([4, 16, 64, 256])[rng.integers(0, 4, size=(n_sc, N))]
+    tau_u = (2 * np.sqrt(Qu)).astype(np.float32)                       # [n_sc][N], user order
+    H = vpgen.draw_correlated(rng, n_sc, N, M, 0.5)
+    s = np.zeros((N, n_sc * n_sym), np.complex64)
+    for sc in range(n_sc):
+        for u in range(N):
+            s[u, sc * n_sym:(sc + 1) * n_sym] = vpgen.draw_symbols(rng, 1, n_sym, int(Qu[sc, u]))[0]
+    Hd, sd = _to_dev(H), _to_dev(s)
+    prep = vp.preprocess(Hd, alpha)
+    W0, w20, G0 = host(prep.W).copy(), host(prep.w2).copy(), host(prep.G).astype(np.complex128)
+    sp = vp.apply_user_tau(prep, sd, _to_dev(tau_u), n_sym)
+    order = torch.empty((n_sc, 2, K), dtype=torch.int16, device=DEV)
+    paths = vp.paths_mop(prep.w2, K, order=order)
+    out = vp.search(prep.W, prep.perm, sp, 1.0, paths, n_sym, order=order)
+    x = host(vp.precode(prep.G, sp, out.l, 1.0, out.cost, n_sym))
+    torch.cuda.synchronize()
+    perm = host(prep.perm).astype(np.int64)
+    P = host(paths)
+    Wd = unpack_W(W0, N)
+    l = l_from_gpu(host(out.l))
+    cost, kidx = host(out.cost), host(out.kidx)
+    rep = ParityReport()
+    for sc in range(n_sc):
+        # Metric of Promise with per-level tau: tau_i^2 |W_ii|^2, bit-exact
+        w_tau = w20[sc].astype(np.float64) * tau_u[sc][perm[sc]].astype(np.float64) ** 2
+        assert np.array_equal(P[sc], O.mop_paths_kbest(w_tau, K)), sc
+        sl = slice(sc * n_sym, (sc + 1) * n_sym)
+        check_search_subcarrier(rep, Wd[sc], perm[sc], s[:, sl].astype(np.complex128), tau_u[sc].astype(np.float64),
+                                P[sc], True, l[sl], cost[sl], kidx[sl])
+        for v in range(sl.start, sl.stop):
+            u = s[:, v].astype(np.complex128) + tau_u[sc] * l[v]
+            np.testing.assert_allclose(O.mod_tau(u, tau_u[sc].astype(np.float64)), s[:, v], atol=1e-9)
+            xr = G0[sc] @ u
+            assert np.abs(x[v] - xr).max() <= 1e-5 * np.abs(xr).max() * 4, v
+    record("per-user-tau", rep)
+    _say("per-user tau", rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.99 * rep.n

@@ -122,3 +122,36 @@ def test_nonfinite_input_flagged():
     h = np.eye(3, dtype=np.complex64)
     h[1, 2] = np.nan
     assert O.preprocess(h, 0.1).status == O.STATUS_NONFINITE
+
+
+def test_unsorted_factorisation_pins():
+    """sort=False: A = L L^H with L lower and a positive real diagonal, the
+    identity order, W L = I; G does not depend on the ordering (it is
+    H^H A^{-1} either way); the exact VP optimum over the box -- a property of
+    u^H A^{-1} u alone -- is the same for both factorisations."""
+    import vpgen
+    wl = vpgen.cfg1(n_sc=3)
+    for sc in range(wl.n_sc):
+        H = wl.H[sc].astype(np.complex128)
+        alpha = 0.05
+        u = O.preprocess(H, alpha, sort=False)
+        srt = O.preprocess(H, alpha)
+        A = O.gram(H, alpha)
+        assert u.status == O.STATUS_OK
+        assert np.array_equal(u.perm, np.arange(wl.N))
+        assert np.allclose(u.L @ u.L.conj().T, A, atol=1e-12)
+        assert np.allclose(np.triu(u.L, 1), 0) and np.all(np.diag(u.L).real > 0)
+        assert np.allclose(u.W @ u.L, np.eye(wl.N), atol=1e-12)
+        assert np.allclose(u.G, srt.G, atol=1e-12)
+        for v in range(3):
+            s = wl.s[:, sc * wl.n_sym + v]
+            lu, cu = O.brute_force(u.W, u.perm, s, wl.tau)
+            ls, cs = O.brute_force(srt.W, srt.perm, s, wl.tau)
+            assert abs(cu - cs) <= 1e-9 * cs
+            assert abs(O.cost_closed_form(A, s, lu, wl.tau) - cu) <= 1e-9 * cu
+
+
+def test_unsorted_factorisation_flags_singular():
+    # two equal user rows under zero forcing: not positive definite
+    H = np.array([[1, 2j], [1, 2j]], dtype=np.complex128)
+    assert O.preprocess(H, 0.0, sort=False).status == O.STATUS_NOT_PD

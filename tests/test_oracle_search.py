@@ -203,3 +203,45 @@ def test_complexity_count():
     # Sec. III-B: N_r N_t + N_t^2 + K N_t (1 + (N_t + 1)/2) complex multiplications.
     assert O.complexity_cm(16, 16, 512) == 256 + 256 + 512 * 16 * 19 // 2 == 78336
     assert O.complexity_cm(4, 4, 32) == 16 + 16 + 32 * 4 * 7 // 2
+
+
+def test_per_user_tau_pins():
+    """One perturbation interval per user (a QAM order per user).  Pinned by:
+    equal intervals reproduce the scalar-tau results; the search over all 9^N
+    paths and the sphere encoder both equal the brute-force optimum of
+    || W (s_pi + tau l) ||^2 with per-user tau; the reported cost is the closed
+    form u^H A^{-1} u with u = s + tau l; the receiver modulo of each user's
+    own tau recovers s; and the walk with per-level tau equals the plain walk
+    on the rescaled problem W diag(tau_pi), s / tau, tau = 1 (a different
+    route to the same objective)."""
+    import itertools
+    rng = np.random.default_rng(77)
+    N = 3
+    Qs = np.array([4, 64, 16])
+    tau = np.array([2 * np.sqrt(q) for q in Qs])
+    H = (rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N))) / np.sqrt(2)
+    p = O.preprocess(H, 0.05)
+    A = O.gram(H, 0.05)
+    allp = np.array(list(itertools.product(range(9), repeat=N)))
+    for v in range(6):
+        s = np.array([(rng.integers(0, int(np.sqrt(q))) * 2 - (np.sqrt(q) - 1)) +
+                      1j * (rng.integers(0, int(np.sqrt(q))) * 2 - (np.sqrt(q) - 1)) for q in Qs])
+        lb, cb = O.brute_force(p.W, p.perm, s, tau)
+        res = O.search_paths(p.W, p.perm, s[:, None], tau, allp, include_zero=False)
+        assert abs(res.cost[0] - cb) <= 1e-9 * cb
+        lse, cse, _ = O.sphere_encode(p.W, p.perm, s, tau)
+        assert abs(cse - cb) <= 1e-9 * cb
+        assert abs(O.cost_closed_form(A, s, res.l[0], tau) - res.cost[0]) <= 1e-9 * cb
+        np.testing.assert_allclose(O.mod_tau(s + tau * res.l[0], tau), s, atol=1e-9)
+        # rescaled problem: W' = W diag(tau_pi), s' = s / tau, tau = 1
+        Wr = p.W * tau[p.perm][None, :]
+        paths = O.mop_paths_kbest(np.abs(np.diag(Wr)) ** 2, 40)
+        a = O.search_paths(p.W, p.perm, s[:, None], tau, paths)
+        b = O.search_paths(Wr, p.perm, (s / tau)[:, None], 1.0, paths)
+        assert np.array_equal(a.l, b.l) and abs(a.cost[0] - b.cost[0]) <= 1e-9 * a.cost[0]
+    # equal intervals reproduce the scalar results
+    s = rng.integers(-3, 4, size=(N, 5)) * 2 + 1 + 1j * (rng.integers(-3, 4, size=(N, 5)) * 2 + 1)
+    paths = O.mop_paths_kbest(p.w2, 30)
+    a = O.search_paths(p.W, p.perm, s, 16.0, paths)
+    b = O.search_paths(p.W, p.perm, s, np.full(N, 16.0), paths)
+    assert np.array_equal(a.l, b.l) and np.array_equal(a.cost, b.cost)

@@ -65,8 +65,10 @@ def l_from_gpu(l_i8: np.ndarray) -> np.ndarray:
 
 def relaxed_walks(W, st, tau, ranks, eps=TIE_EPS, limit=64):
     """Every l (level order) the walk of `ranks` can produce when each near-tied
-    DEMAP decision may go either way.  Returns a list of (l, cost)."""
+    DEMAP decision may go either way (tau a scalar or one value per level).
+    Returns a list of (l, cost)."""
     n = W.shape[0]
+    taul = np.broadcast_to(np.asarray(tau, dtype=np.float64), (n,))
     out = []
 
     def rec(i, resid, l, cost):
@@ -75,7 +77,7 @@ def relaxed_walks(W, st, tau, ranks, eps=TIE_EPS, limit=64):
         if i == n:
             out.append((l.copy(), cost))
             return
-        c = -resid[i] / (tau * W[i, i])
+        c = -resid[i] / (taul[i] * W[i, i])
         d = O.sqabs(c - O.BOX)
         order = np.argsort(d, kind="stable")
         dr = d[order[ranks[i]]]
@@ -84,8 +86,8 @@ def relaxed_walks(W, st, tau, ranks, eps=TIE_EPS, limit=64):
             if abs(d[j] - dr) <= eps * (1.0 + abs(c)) ** 2:
                 l[i] = O.BOX[j]
                 nres = resid.copy()
-                nres[i + 1:] += tau * W[i + 1:, i] * O.BOX[j]
-                rec(i + 1, nres, l, cost + tau * tau * abs(W[i, i]) ** 2 * d[j])
+                nres[i + 1:] += taul[i] * W[i + 1:, i] * O.BOX[j]
+                rec(i + 1, nres, l, cost + taul[i] ** 2 * abs(W[i, i]) ** 2 * d[j])
         l[i] = 0
 
     rec(0, st.copy(), np.zeros(n, dtype=np.complex128), 0.0)
@@ -146,14 +148,15 @@ def check_search_subcarrier(rep: ParityReport, W, perm, s_user, tau, paths, incl
         lg_level = lg[perm]
         ok = False
         if 0 <= kg < K:
-            walks = relaxed_walks(W, st, tau, paths[kg])
+            walks = relaxed_walks(W, st, O.level_tau(tau, perm), paths[kg])
             ok = any(np.array_equal(w[0], lg_level) for w in walks)
         elif kg == K and include_zero:
             ok = not np.any(lg)
         if ok:
             bound = math.inf
             for k in range(K):
-                ws = relaxed_walks(W, st, tau, paths[k]) if res.margin[v, k] <= 100 * TIE_EPS else None
+                ws = (relaxed_walks(W, st, O.level_tau(tau, perm), paths[k])
+                      if res.margin[v, k] <= 100 * TIE_EPS else None)
                 if ws is None:
                     bound = min(bound, float(res.path_cost[v, k]))
                 else:
