@@ -477,7 +477,7 @@ def exact_vp_host(wl, l_gpu, n_vec=4096):
             "wall_s": wall}
 
 
-def run_plain(vp, wl, K, steps, warmup, dev="cuda:0"):
+def run_plain(vp, wl, K, steps, warmup, dev="cuda:0", flags=None):
     """Time the plain path (preprocess, MoP paths with their orders, search,
     precode) on workload wl with K paths: inputs resident in HBM, outputs
     preallocated.  Returns the timings and the buffers of the last step."""
@@ -505,7 +505,8 @@ def run_plain(vp, wl, K, steps, warmup, dev="cuda:0"):
         if ev: ev[1].record()
         vp.paths_mop(prep.w2, K, out=paths, order=order)
         if ev: ev[2].record()
-        vp.search(prep.W, prep.perm, s, tau, paths, n_sym, out=sout, order=order)
+        vp.search(prep.W, prep.perm, s, tau, paths, n_sym, out=sout, order=order,
+                  flags=vp.VP_INCLUDE_ZERO if flags is None else flags)
         if ev: ev[3].record()
         vp.precode(prep.G, s, sout.l, tau, sout.cost, n_sym, P_T=1.0, out=x)
         if ev: ev[4].record()
@@ -618,6 +619,18 @@ def main():
     if not args.no_extras:
         print("ablations ...", file=sys.stderr, flush=True)
         line["ablations"] = bench_ablations(vp, dev)
+    if not args.no_extras:
+        # the paper's region-table DEMAP against the exact child order, same slot
+        print("region-table DEMAP ...", file=sys.stderr, flush=True)
+        line["region_demap"] = {}
+        for Kp in (K, 256):
+            rr = run_plain(vp, vpgen.cfg3(Kp), Kp, args.steps, args.warmup, dev,
+                           flags=vp.VP_INCLUDE_ZERO | vp.VP_DEMAP_REGION)
+            g, _ = gap_to_exact(vp, rr["prep"], rr["s"], wl.tau, n_sym, rr["sout"].cost)
+            line["region_demap"][str(Kp)] = {"value": rr["value"], "unit": "vectors/s",
+                                             "ms_per_step": rr["wall_ms_per_step"], "stages_ms": rr["stages_ms"],
+                                             "gap_db": g}
+            del rr
     l_host = None
     if not args.no_cpu:
         l_i8 = sout.l.cpu().numpy()

@@ -57,8 +57,10 @@ enum {
 
 /* flags for vp_search */
 enum {
-    VP_INCLUDE_ZERO = 1,    /* also evaluate l = 0 (plain RZF) as candidate index K */
-    VP_PATHS_PER_VECTOR = 2 /* one [K][N] table per vector (paths + v * paths_sc_stride) */
+    VP_INCLUDE_ZERO = 1,     /* also evaluate l = 0 (plain RZF) as candidate index K */
+    VP_PATHS_PER_VECTOR = 2, /* one [K][N] table per vector (paths + v * paths_sc_stride) */
+    VP_DEMAP_REGION = 4      /* children of rank >= 1 from the paper's region table (Sec. III-A-2 DEMAP),
+                                an approximation of the exact order; rank 0 is the same */
 };
 
 /* per-vector status written by vp_sphere_encode */
@@ -156,7 +158,11 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  * || W (s_pi + tau l) ||^2.  The result is the k with the smallest cost (ties
  * -> smaller k); with VP_INCLUDE_ZERO the zero perturbation competes as index
  * K.  cost is gamma_VP of Alg. 2 (the squared norm that sets the transmit
- * normalisation).
+ * normalisation).  With VP_DEMAP_REGION the child of rank >= 1 comes instead
+ * from the paper's region-indexed table: the centre relative to its nearest
+ * box point, folded by the square's symmetries, selects one of 78 cells of a
+ * 1/8 grid, each holding the offset order of its representative point; rank
+ * p > 0 is the p-th stored offset that stays inside the box.
  *
  *  W, perm  from vp_preprocess (W's diagonal must be real and > 0)
  *  s        [N][n_vec]  symbols, structure of arrays (user-major), user order

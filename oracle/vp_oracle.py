@@ -41,6 +41,8 @@ from __future__ import annotations
 import itertools
 import math
 from dataclasses import dataclass
+from fractions import Fraction
+from functools import lru_cache
 from typing import Optional
 
 import numpy as np
@@ -269,6 +271,94 @@ class SearchResult:
     margin: np.ndarray     # [n_vec][K] smallest order margin met along each path
 
 
+# ---------------------------------------------------------------------------
+# The paper's region-table DEMAP (Sec. III-A-2 DEMAP paragraph; Alg. 2 "Demap")
+# ---------------------------------------------------------------------------
+# Reading (the FlexCore construction the paper defers to is not available):
+# the centre c is taken relative to its anchor n, the box point nearest to it
+# (the rank-0 child of the exact order); delta = c - n is folded by the
+# symmetries of the square lattice -- sign flips of both axes, then the swap
+# that makes |dx| >= |dy| -- into 0 <= w <= u; the cell (iu, iw) of that point
+# on a grid of step 1/8 (iu capped at 11, iw at iu) is the region; its order
+# of the 25 lattice offsets of [-2, 2]^2 is the distance order from the cell's
+# representative point (the cell centre, or the centroid of the lower triangle
+# for diagonal cells), equal distances by the folded index 5 (dx+2) + (dy+2).
+# Rank 0 is the anchor; rank p > 0 is the p-th offset of that order, other
+# than (0, 0), whose point lies in the box once unfolded.
+
+REGION_STEP = Fraction(1, 8)
+REGION_UCELLS = 12
+_OFFSETS25 = [(dx, dy) for dx in range(-2, 3) for dy in range(-2, 3)]
+
+
+def region_representative(iu: int, iw: int):
+    """Representative point (u, w) of region (iu, iw), exact rationals."""
+    if iw < iu:
+        return (iu + Fraction(1, 2)) * REGION_STEP, (iw + Fraction(1, 2)) * REGION_STEP
+    return (iu + Fraction(2, 3)) * REGION_STEP, (iu + Fraction(1, 3)) * REGION_STEP
+
+
+@lru_cache(maxsize=None)
+def region_ranks(iu: int, iw: int, mx: int, my: int):
+    """Folded offsets of ranks 0..8 in region (iu, iw) for the folded anchor
+    (mx, my): (0, 0) first, then the region's distance order restricted to
+    the offsets that keep the anchor inside the box."""
+    u, w = region_representative(iu, iw)
+    dist = [((u - dx) ** 2 + (w - dy) ** 2, 5 * (dx + 2) + (dy + 2)) for dx, dy in _OFFSETS25]
+    order = sorted(range(25), key=lambda j: dist[j])
+    out = [(0, 0)]
+    for j in order:
+        dx, dy = _OFFSETS25[j]
+        if (dx, dy) != (0, 0) and abs(mx + dx) <= 1 and abs(my + dy) <= 1:
+            out.append((dx, dy))
+    return tuple(out)
+
+
+def fold_region(delta: complex):
+    """Region (iu, iw) and fold (flip x, flip y, swap) of an offset from the anchor."""
+    fx, fy = delta.real < 0, delta.imag < 0
+    ax, ay = abs(delta.real), abs(delta.imag)
+    sw = ay > ax
+    u, w = (ay, ax) if sw else (ax, ay)
+    iu = min(int(math.floor(u / float(REGION_STEP))), REGION_UCELLS - 1)
+    iw = min(int(math.floor(w / float(REGION_STEP))), iu)
+    return iu, iw, fx, fy, sw
+
+
+def folded_ranks_at(u: float, w: float, mx: int, my: int):
+    """As region_ranks, with the order taken at the folded point (u, w) itself:
+    the table a region-table DEMAP would hold if its regions were points."""
+    dist = [((u - dx) ** 2 + (w - dy) ** 2, 5 * (dx + 2) + (dy + 2)) for dx, dy in _OFFSETS25]
+    out = [(0, 0)]
+    for j in sorted(range(25), key=lambda j: dist[j]):
+        dx, dy = _OFFSETS25[j]
+        if (dx, dy) != (0, 0) and abs(mx + dx) <= 1 and abs(my + dy) <= 1:
+            out.append((dx, dy))
+    return tuple(out)
+
+
+def demap_region(c: complex, rank: int, exact_point: bool = False) -> complex:
+    """The box point of the given rank for centre c under the region-table
+    DEMAP (exact_point: the order of the folded point itself instead of its
+    region's representative)."""
+    d = sqabs(c - BOX)
+    n = BOX[int(np.argsort(d, kind="stable")[0])]      # anchor: the exact rank-0 child
+    if rank == 0:
+        return n
+    iu, iw, fx, fy, sw = fold_region(c - n)
+    mx, my = int(-n.real if fx else n.real), int(-n.imag if fy else n.imag)
+    if sw:
+        mx, my = my, mx
+    if exact_point:
+        ax, ay = abs((c - n).real), abs((c - n).imag)
+        ranks = folded_ranks_at(max(ax, ay), min(ax, ay), mx, my)
+    else:
+        ranks = region_ranks(iu, iw, mx, my)
+    ox, oy = ranks[rank]
+    ux, uy = (oy, ox) if sw else (ox, oy)             # unswap, then unflip
+    return n + complex(-ux if fx else ux, -uy if fy else uy)
+
+
 def level_tau(tau, perm):
     """tau per tree level: a scalar (the paper's one system constant, Sec. II-B)
     or one value per user (a QAM order per user), taken in level order."""
@@ -277,7 +367,7 @@ def level_tau(tau, perm):
     return np.full(n, float(t)) if t.ndim == 0 else t[np.asarray(perm)]
 
 
-def demap_walk(W, st, tau, ranks):
+def demap_walk(W, st, tau, ranks, demap: str = "exact"):
     """Walk the tree along position vectors for many (vector, path) pairs at once.
 
     st: complex [V][N] = W s_pi (s-tilde of the PED recursion); ranks: int
@@ -309,7 +399,15 @@ def demap_walk(W, st, tau, ranks):
         lo = np.where(r[:, :, 0] > 0, dch - dlo, np.inf)
         hi = np.where(r[:, :, 0] < NBOX - 1, dhi - dch, np.inf)
         margin = np.minimum(margin, np.minimum(lo, hi))
-        li = BOX[j]
+        if demap in ("region", "region-exact-point"):   # the paper's region-table DEMAP instead of the exact order
+            ep = demap == "region-exact-point"
+            li = BOX[j].copy()                             # rank 0: the nearest box point, as the exact order
+            for b in np.nonzero(ranks[:, i] > 0)[0]:
+                for a in range(V):
+                    li[a, b] = demap_region(complex(c[a, b]), int(ranks[b, i]), ep)
+            dch = sqabs(c - li)
+        else:
+            li = BOX[j]
         l[:, :, i] = li
         cost += (ti ** 2) * (abs(wii) ** 2) * dch
         if i + 1 < n:
@@ -317,14 +415,15 @@ def demap_walk(W, st, tau, ranks):
     return l, cost, margin
 
 
-def search_paths(W, perm, s, tau, paths, include_zero: bool = True) -> SearchResult:
+def search_paths(W, perm, s, tau, paths, include_zero: bool = True, demap: str = "exact") -> SearchResult:
     """Alg. 2's data-dependent part for one subcarrier: for every vector (columns
     of s, user order) evaluate every path of the set, then take the argmin.
 
     W: complex [N][N] lower (search order); perm: level -> user; s: complex
     [N][V] (user order); tau: a scalar or one value per user; paths: int
     [K][N] ranks 0..8.  With include_zero, the zero perturbation (plain RZF)
-    is candidate index K."""
+    is candidate index K.  demap = "region" walks with the paper's region-table
+    DEMAP (demap_region) instead of the exact child order."""
     W = np.asarray(W, dtype=np.complex128)
     perm = np.asarray(perm, dtype=np.int64)
     s = np.asarray(s, dtype=np.complex128)
@@ -334,7 +433,7 @@ def search_paths(W, perm, s, tau, paths, include_zero: bool = True) -> SearchRes
     K, n = paths.shape
     s_pi = s[perm, :].T                     # [V][N] level order
     st = s_pi @ W.T                         # s-tilde = W s_pi, per vector
-    l, cost, margin = demap_walk(W, st, level_tau(tau, perm), paths)
+    l, cost, margin = demap_walk(W, st, level_tau(tau, perm), paths, demap=demap)
     if include_zero:
         c0 = np.sum(np.abs(st) ** 2, axis=1)
         cost_all = np.concatenate([cost, c0[:, None]], axis=1)

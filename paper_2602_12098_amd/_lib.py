@@ -15,6 +15,7 @@ VP_EUNSUPPORTED = -2
 VP_ELAUNCH = -3
 VP_INCLUDE_ZERO = 1
 VP_PATHS_PER_VECTOR = 2
+VP_DEMAP_REGION = 4
 VP_SE_EXACT = 0
 VP_SE_EXHAUSTED = 1
 VP_SE_NONE = 2

@@ -74,7 +74,7 @@ int vp_search(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float
     if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
     if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
     if (order && paths_sc_stride != (int64_t)K * n_r) return VP_EINVAL;   // one order per subcarrier table
-    if (flags & ~(uint32_t)(VP_INCLUDE_ZERO | VP_PATHS_PER_VECTOR)) return VP_EINVAL;
+    if (flags & ~(uint32_t)(VP_INCLUDE_ZERO | VP_PATHS_PER_VECTOR | VP_DEMAP_REGION)) return VP_EINVAL;
     if ((flags & VP_PATHS_PER_VECTOR) && (order || paths_sc_stride != (int64_t)K * n_r)) return VP_EINVAL;
     if (n_sc == 0) return VP_OK;
     if (!W || !perm || !s || !tau || !paths || !l || !cost || !kidx) return VP_EINVAL;

@@ -19,6 +19,7 @@
 #endif
 
 #include "demap_lut.h"
+#include "region_lut.h"
 
 // Offset of element (i, j), i >= j, in LAPACK column-major lower packed storage.
 VP_HD constexpr int vp_pidx(int n, int i, int j) { return j * n - (j * (j - 1)) / 2 + (i - j); }
@@ -154,6 +155,39 @@ VP_HD void vp_demapN(float cpx, float cpy, float cx, float cy, int rank, const u
     const int cell = lut[sig * 9 + (rank < 8 ? rank : 8)];   // a rank beyond the box must not leave the table
     a = vp_pick_offset(X.o0, X.o1, X.o2, cell & 3);
     b = vp_pick_offset(Y.o0, Y.o1, Y.o2, cell >> 2);
+}
+
+// The paper's DEMAP (Sec. III-A-2, Alg. 2 "Demap", after FlexCore): the
+// centre c is taken relative to its anchor n, the box point nearest to it
+// (the rank-0 child, from cp); delta = c - n is folded by the symmetries of
+// the square lattice (sign flips, then the swap that makes |dx| >= |dy|) and
+// its cell on a grid of step 1/8 (12 cells along the larger coordinate)
+// selects a stored order of the lattice offsets, the order of the cell's
+// representative point (region_lut.h, generated by gen_region_lut.py).  Rank
+// p is the anchor for p = 0, else the p-th stored offset that keeps the point
+// inside the box.  An approximation of the exact order, exact at rank 0.
+VP_HD void vp_demap_region(float cpx, float cpy, float cx, float cy, int rank, const uint8_t *rlut, float &a,
+                           float &b) {
+    const float nx = vp_o0(cpx), ny = vp_o0(cpy);
+    const float dx = cx - nx, dy = cy - ny;
+    const bool fx = dx < 0.0f, fy = dy < 0.0f;
+    const float ax = fabsf(dx), ay = fabsf(dy);
+    const bool sw = ay > ax;
+    const float u = sw ? ay : ax, w = sw ? ax : ay;
+    const int iu = (int)fminf(u * (float)VP_REGION_STEP_INV, (float)(VP_REGION_UCELLS - 1));
+    const int iw0 = (int)(w * (float)VP_REGION_STEP_INV);
+    const int iw = iw0 < iu ? iw0 : iu;
+    const int reg = iu * (iu + 1) / 2 + iw;
+    // the anchor under the same fold
+    const float mx0 = fx ? -nx : nx, my0 = fy ? -ny : ny;
+    const float mx = sw ? my0 : mx0, my = sw ? mx0 : my0;
+    const int an = 3 * ((int)mx + 1) + ((int)my + 1);
+    const int r = rank < 8 ? rank : 8;
+    const int e = rlut[(reg * 9 + an) * 9 + r];
+    const float ox = (float)((e & 15) - 2), oy = (float)((e >> 4) - 2);   // folded offset
+    const float ux = sw ? oy : ox, uy = sw ? ox : oy;                     // unswap, then unflip
+    a = nx + (fx ? -ux : ux);
+    b = ny + (fy ? -uy : uy);
 }
 
 // Box code of a perturbation symbol: j = 3 (a + 1) + (b + 1).

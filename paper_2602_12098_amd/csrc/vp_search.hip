@@ -36,7 +36,7 @@ struct VecMask {
     __device__ __forceinline__ bool on(size_t v) const { return !mass || !(mass[v] >= theta); }
 };
 
-template <int N, bool MASKED>
+template <int N, bool MASKED, bool RLUT>
 __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
                                                const float2 *__restrict__ s, const float *__restrict__ taus,
                                                const uint8_t *__restrict__ paths, int K, long long pstride,
@@ -80,7 +80,7 @@ __global__ __launch_bounds__(kT) void k_search(const float2 *__restrict__ W, con
         float2 r[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = s_r0[i];
-        const float ped = walk<N, kTierAny, false>(Wc, s_nlinv, s_wdiag, r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
+        const float ped = walk<N, kTierAny, false, 0, N, RLUT>(Wc, s_nlinv, s_wdiag, r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
         best = umin64(best, ((unsigned long long)__float_as_uint(ped * (tau * tau)) << 32) | (unsigned)k);
     }
     if ((flags & VP_INCLUDE_ZERO) && t == 0) {
@@ -147,7 +147,7 @@ __device__ __forceinline__ unsigned long long wave_min_by_parity(unsigned long l
     return x;
 }
 
-template <int N, bool MASKED>
+template <int N, bool MASKED, bool RLUT>
 __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves))) void k_search_trie(
     const float2 *__restrict__ W, const uint8_t *__restrict__ perm, const float2 *__restrict__ s,
     const float *__restrict__ taus, const uint8_t *__restrict__ paths, const uint16_t *__restrict__ order, int K,
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
             float2 r[N];
 #pragma unroll
             for (int i = 0; i < N; ++i) r[i] = s_r0[hh][i];
-            const float ped = walk<N, kTierAny, false, 0, P1>(Wc, s_nlinv, s_wdiag, r,
+            const float ped = walk<N, kTierAny, false, 0, P1, RLUT>(Wc, s_nlinv, s_wdiag, r,
                                                              s_words[s_k[s_first[base + pp]]], 0ull, VP_DEMAP_LUT,
                                                              nullptr, nullptr);
             float *st = s_state[hh] + pp * SW;
@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
                 for (int i = 0; i < P1; ++i) r[i] = make_float2(0.f, 0.f);
 #pragma unroll
                 for (int i = P1; i < N; ++i) r[i] = make_float2(st[2 * (i - P1)], st[2 * (i - P1) + 1]);
-                const float ped = walk<N, kTierTherm, false, P1, N>(Wc, s_nlinv, s_wdiag, r, wd, therm,
+                const float ped = walk<N, kTierTherm, false, P1, N, RLUT>(Wc, s_nlinv, s_wdiag, r, wd, therm,
                                                                     VP_DEMAP_LUT, nullptr, nullptr, st[SW - 1]);
                 best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
             }
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
 constexpr int kWV = 4;          // vectors (waves) per workgroup
 constexpr int kWaveMaxK = 192;  // tables up to this size use one wave per vector
 
-template <int N, bool MASKED>
+template <int N, bool MASKED, bool RLUT>
 __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restrict__ W,
                                                           const uint8_t *__restrict__ perm,
                                                           const float2 *__restrict__ s,
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
         float2 r[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = s_r0[wv][i];
-        const float ped = walk<N, kTierAny, false>(Wc, s_nlinv[wv], s_wdiag[wv], r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
+        const float ped = walk<N, kTierAny, false, 0, N, RLUT>(Wc, s_nlinv[wv], s_wdiag[wv], r, wd, 0ull, VP_DEMAP_LUT, nullptr, nullptr);
         best = umin64(best, ((unsigned long long)__float_as_uint(ped * tau2) << 32) | (unsigned)k);
     }
     if ((flags & VP_INCLUDE_ZERO) && t == 0) {
@@ -419,7 +419,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     }
 }
 
-template <int N>
+template <int N, bool RLUT>
 __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict__ W,
                                                         const uint8_t *__restrict__ perm,
                                                         const float2 *__restrict__ s,
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(kT) void k_search_finalize(const float2 *__restrict
         const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride + (size_t)k * N;
         unsigned long long wd = 0;
         for (int i = 0; i < N; ++i) wd |= (unsigned long long)(P[i] & 15) << (4 * i);
-        (void)walk<N, kTierLut, true>(Wc, nlinv, wdiag, r, wd, 0ull, VP_DEMAP_LUT, ra, rb);
+        (void)walk<N, kTierLut, true, 0, N, RLUT>(Wc, nlinv, wdiag, r, wd, 0ull, VP_DEMAP_LUT, ra, rb);
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
@@ -516,37 +516,49 @@ __global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict_
 
 // The search kernel for a table shape: prefix sharing with orders, one wave
 // per vector for short tables, else one workgroup per vector.
-template <int N, bool MASKED>
+template <int N, bool MASKED, bool RLUT>
 void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                           const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags,
                           VecMask mask, float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
     if (order) {
         const size_t smem = trie_lds_bytes(K);
-        static const bool lds_ok = allow_dynamic_lds(k_search_trie<N, MASKED>, 64 * 1024);
+        static const bool lds_ok = allow_dynamic_lds(k_search_trie<N, MASKED, RLUT>, 64 * 1024);
         (void)lds_ok;
         const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);
-        hipLaunchKernelGGL((k_search_trie<N, MASKED>), dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths, order, K,
-                           (long long)pstride, n_sym, n_vec, flags, cost, kidx, mask);
+        hipLaunchKernelGGL((k_search_trie<N, MASKED, RLUT>), dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths,
+                           order, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx, mask);
     } else if (K <= kWaveMaxK) {
-        hipLaunchKernelGGL((k_search_wave<N, MASKED>), dim3((unsigned)((n_vec + kWV - 1) / kWV)), dim3(64 * kWV), 0, st, W,
-                           perm, s, tau, paths, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx, mask);
+        hipLaunchKernelGGL((k_search_wave<N, MASKED, RLUT>), dim3((unsigned)((n_vec + kWV - 1) / kWV)), dim3(64 * kWV),
+                           0, st, W, perm, s, tau, paths, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx,
+                           mask);
     } else {
-        hipLaunchKernelGGL((k_search<N, MASKED>), dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths, K,
-                           (long long)pstride, n_sym, flags, cost, kidx, mask);
+        hipLaunchKernelGGL((k_search<N, MASKED, RLUT>), dim3((unsigned)n_vec), dim3(kT), 0, st, W, perm, s, tau, paths,
+                           K, (long long)pstride, n_sym, flags, cost, kidx, mask);
     }
+}
+
+template <int N, bool RLUT>
+int launch_search_nr(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
+                     const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
+                     float *cost, int32_t *kidx, hipStream_t st) {
+    const size_t n_vec = (size_t)n_sc * n_sym;
+    launch_search_kernel<N, false, RLUT>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags,
+                                         VecMask{nullptr, 0.f}, cost, kidx, st);
+    hipLaunchKernelGGL((k_search_finalize<N, RLUT>), dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W,
+                       perm, s, tau, paths, K, (long long)pstride, n_sc, n_sym, flags, kidx, l);
+    return launch_status();
 }
 
 template <int N>
 int launch_search_n(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                     const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags, int8_t *l,
                     float *cost, int32_t *kidx, hipStream_t st) {
-    const size_t n_vec = (size_t)n_sc * n_sym;
-    launch_search_kernel<N, false>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags,
-                                   VecMask{nullptr, 0.f}, cost, kidx, st);
-    hipLaunchKernelGGL(k_search_finalize<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
-                       tau, paths, K, (long long)pstride, n_sc, n_sym, flags, kidx, l);
-    return launch_status();
+    if (flags & VP_DEMAP_REGION)
+        return launch_search_nr<N, true>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, l, cost,
+                                         kidx, st);
+    return launch_search_nr<N, false>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, l, cost, kidx,
+                                      st);
 }
 
 template <int N>
@@ -558,8 +570,8 @@ int launch_fallback_n(const float2 *W, const uint8_t *perm, const float2 *s, con
     float *cost_fix = static_cast<float *>(work);
     int32_t *kidx_fix = reinterpret_cast<int32_t *>(cost_fix + n_vec);
     const VecMask mask{mass, theta};
-    launch_search_kernel<N, true>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, mask, cost_fix,
-                                  kidx_fix, st);
+    launch_search_kernel<N, true, false>(W, perm, s, tau, paths, order, K, pstride, n_sc, n_sym, flags, mask,
+                                         cost_fix, kidx_fix, st);
     hipLaunchKernelGGL(k_fallback_merge<N>, dim3((unsigned)((n_vec + kT - 1) / kT)), dim3(kT), 0, st, W, perm, s,
                        tau, paths, K, (long long)pstride, n_sc, n_sym, mask, cost_fix, kidx_fix, kidx_base, l, cost,
                        kidx);

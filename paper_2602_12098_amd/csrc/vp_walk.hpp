@@ -101,7 +101,9 @@ __device__ __forceinline__ unsigned long long wave_or64(unsigned long long x) {
 // cp = c - 1/2, one fused multiply-add, and (above rank 0) as c.  A walk split
 // into consecutive ranges performs exactly the arithmetic of the whole walk,
 // and every tier mode gives the same bits.
-template <int N, int TIERS, bool REC, int LO = 0, int HI = N>
+// RLUT: the children of rank >= 1 come from the paper's region table
+// (vp_demap_region) instead of the exact order; rank 0 is the same in both.
+template <int N, int TIERS, bool REC, int LO = 0, int HI = N, bool RLUT = false>
 __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float *nlinv, const float *wdiag,
                                       float2 (&r)[N], unsigned long long word, unsigned long long therm,
                                       const uint8_t *lut, float *ra, float *rb, float ped = 0.f) {
@@ -119,7 +121,8 @@ __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float
             } else {
                 const int rank = (int)((word >> (4 * i)) & 15ull);
                 const float cx = r[i].x * nl, cy = r[i].y * nl;
-                if (th == 1u) vp_demap1(cpx, cpy, cx, cy, rank, a, b);
+                if (RLUT) vp_demap_region(cpx, cpy, cx, cy, rank, VP_REGION_LUT, a, b);
+                else if (th == 1u) vp_demap1(cpx, cpy, cx, cy, rank, a, b);
                 else if (th == 3u) vp_demap2(cpx, cpy, cx, cy, rank, a, b);
                 else vp_demapN(cpx, cpy, cx, cy, rank, lut, a, b);
             }
@@ -129,13 +132,15 @@ __device__ __forceinline__ float walk(const float2 *__restrict__ W0, const float
                 vp_demap0(cpx, cpy, a, b);
             } else {
                 const float cx = r[i].x * nl, cy = r[i].y * nl;
-                if (!__any(rank > 1)) vp_demap1(cpx, cpy, cx, cy, rank, a, b);
+                if (RLUT) vp_demap_region(cpx, cpy, cx, cy, rank, VP_REGION_LUT, a, b);
+                else if (!__any(rank > 1)) vp_demap1(cpx, cpy, cx, cy, rank, a, b);
                 else if (!__any(rank > 2)) vp_demap2(cpx, cpy, cx, cy, rank, a, b);
                 else vp_demapN(cpx, cpy, cx, cy, rank, lut, a, b);
             }
         } else {
             const int rank = (int)((word >> (4 * i)) & 15ull);
-            vp_demapN(cpx, cpy, r[i].x * nl, r[i].y * nl, rank, lut, a, b);
+            if (RLUT) vp_demap_region(cpx, cpy, r[i].x * nl, r[i].y * nl, rank, VP_REGION_LUT, a, b);
+            else vp_demapN(cpx, cpy, r[i].x * nl, r[i].y * nl, rank, lut, a, b);
         }
         if (REC) {
             ra[i] = a;

@@ -11,10 +11,10 @@ from typing import NamedTuple, Optional
 import torch
 
 from . import _lib
-from ._lib import VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, VP_SE_EXACT, VP_SE_EXHAUSTED, VP_SE_NONE, check
+from ._lib import VP_DEMAP_REGION, VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, VP_SE_EXACT, VP_SE_EXHAUSTED, VP_SE_NONE, check
 
 __all__ = ["Prep", "SearchOut", "SEOut", "tau_array", "apply_user_tau", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
-           "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "VP_SE_EXACT", "VP_SE_EXHAUSTED", "VP_SE_NONE", "version"]
+           "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "VP_DEMAP_REGION", "VP_SE_EXACT", "VP_SE_EXHAUSTED", "VP_SE_NONE", "version"]
 
 
 def packed_size(n: int) -> int:

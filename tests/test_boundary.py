@@ -245,3 +245,30 @@ def test_learned_argument_validation():
     assert lib.vp_learned_paths(P, 10, 4, P, 4000, P, 200, 200, 2, 14, P, None) == VP_EUNSUPPORTED
     assert lib.vp_learned_paths(P, 10, 4, P, 0, P, 8, 0, 2, 14, P, None) == VP_EINVAL     # empty table
     assert lib.vp_learned_paths(P, 10, 4, None, 64, P, 8, 8, 2, 14, P, None) == VP_EINVAL
+
+
+def test_region_demap_device_code_matches_oracle_definition():
+    """The device region-table DEMAP (host build, with the table generated by
+    gen_region_lut.py) against the oracle's own construction of the same
+    definition, at every rank: random float32 centres, and a grid of
+    sixteenths where the fold, the cells and the anchor meet exact
+    boundaries."""
+    run = _host_demap()
+    rng = np.random.default_rng(11)
+    cx = rng.uniform(-3, 3, 4000).astype(np.float32)
+    cy = rng.uniform(-3, 3, 4000).astype(np.float32)
+    g = (np.arange(-40, 41) / 16.0).astype(np.float32)
+    gx, gy = np.meshgrid(g, g)
+    cx = np.concatenate([cx, gx.ravel()])
+    cy = np.concatenate([cy, gy.ravel()])
+    for r in range(9):
+        a, b = run(cx, cy, np.full(len(cx), r), 4)
+        for k in range(len(cx)):
+            want = O.demap_region(complex(float(cx[k]), float(cy[k])), r)
+            assert (a[k], b[k]) == (want.real, want.imag), (r, cx[k], cy[k], a[k], b[k], want)
+
+
+def test_region_table_is_generated():
+    gen = os.path.join(PKG, "csrc", "gen_region_lut.py")
+    out = subprocess.run([sys.executable, gen], capture_output=True, text=True, check=True).stdout
+    assert out == open(os.path.join(PKG, "csrc", "region_lut.h")).read()

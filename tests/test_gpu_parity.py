@@ -675,3 +675,36 @@ def test_per_user_tau(vp):
     _say("per-user tau", rep)
     assert rep.ok(), rep.failures[:5]
     assert rep.exact >= 0.99 * rep.n
+
+
+@pytest.mark.parametrize("cfg,K,shared,n_sc", [("cfg3", 512, True, 6), ("cfg3", 256, False, 4),
+                                               ("cfg2", 64, True, 12), ("cfg2", 64, False, 12),
+                                               ("cfg1", 32, True, 16)])
+def test_region_demap_search(vp, cfg, K, shared, n_sc):
+    # the paper's region-table DEMAP (VP_DEMAP_REGION) against the oracle's
+    # walk with its own construction of the same table
+    from tests.vp_parity import check_search_subcarrier_region
+    wl = {"cfg1": lambda: vpgen.cfg1(n_sc=n_sc), "cfg2": lambda: vpgen.cfg2(20, n_sc=n_sc),
+          "cfg3": lambda: vpgen.cfg3(K, n_sc=n_sc)}[cfg]()
+    _say("region demap", wl.name, K, "shared" if shared else "plain")
+    Hd, sd = _to_dev(wl.H), _to_dev(wl.s)
+    prep = vp.preprocess(Hd, wl.alpha)
+    order = torch.empty((wl.n_sc, 2, K), dtype=torch.int16, device=DEV) if shared else None
+    paths = vp.paths_mop(prep.w2, K, order=order)
+    out = vp.search(prep.W, prep.perm, sd, wl.tau, paths, wl.n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_DEMAP_REGION,
+                    order=order)
+    torch.cuda.synchronize()
+    Wd = unpack_W(host(prep.W), wl.N)
+    perm = host(prep.perm).astype(np.int64)
+    P = host(paths)
+    l = l_from_gpu(host(out.l))
+    cost, kidx = host(out.cost), host(out.kidx)
+    rep = ParityReport()
+    for sc in range(wl.n_sc):
+        sl = slice(sc * wl.n_sym, (sc + 1) * wl.n_sym)
+        check_search_subcarrier_region(rep, Wd[sc], perm[sc], wl.s[:, sl].astype(np.complex128), wl.tau, P[sc],
+                                       True, l[sl], cost[sl], kidx[sl])
+    record("region-demap", rep)
+    _say(rep)
+    assert rep.ok(), rep.failures[:5]
+    assert rep.exact >= 0.98 * rep.n

@@ -7,6 +7,7 @@ per-coordinate rounding (the rank-0 / Babai point), the RZF closed form
 u^H A^{-1} u, hand-worked examples, the receiver modulo and the zero-forcing
 identity H x = u."""
 import itertools
+import os
 import math
 
 import numpy as np
@@ -245,3 +246,72 @@ def test_per_user_tau_pins():
     a = O.search_paths(p.W, p.perm, s, 16.0, paths)
     b = O.search_paths(p.W, p.perm, s, np.full(N, 16.0), paths)
     assert np.array_equal(a.l, b.l) and np.array_equal(a.cost, b.cost)
+
+
+def _golden_region_cases():
+    path = os.path.join(os.path.dirname(__file__), "golden", "region_demap_cases.txt")
+    for line in open(path):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        f = line.split()
+        c = complex(float(f[0]), float(f[1]))
+        pts = [complex(*map(float, t.split(","))) for t in f[2:]]
+        yield c, pts
+
+
+def test_region_demap_worked_cases():
+    """The region-table DEMAP against cases worked by hand (tests/golden)."""
+    n = 0
+    for c, pts in _golden_region_cases():
+        got = [O.demap_region(c, r) for r in range(9)]
+        assert got == pts, (c, got)
+        n += 1
+    assert n == 3
+
+
+def test_region_demap_properties():
+    """Rank 0 is the exact nearest box point; ranks 0..8 are nine distinct box
+    points; with the order taken at the folded point itself (a table whose
+    regions are points) the region DEMAP is the exact (distance, j) order at
+    every rank; at a region's representative point the stored order is the
+    exact one."""
+    rng = np.random.default_rng(8)
+    cs = rng.uniform(-2.5, 2.5, 3000) + 1j * rng.uniform(-2.5, 2.5, 3000)
+    for c in cs:
+        d = O.sqabs(c - O.BOX)
+        exact = O.BOX[np.argsort(d, kind="stable")]
+        got = [O.demap_region(c, r) for r in range(9)]
+        assert got[0] == exact[0]
+        assert len(set(got)) == 9 and all(abs(g.real) <= 1 and abs(g.imag) <= 1 for g in got)
+        assert [O.demap_region(c, r, exact_point=True) for r in range(9)] == list(exact)
+    for iu in range(4):
+        for iw in range(iu + 1):
+            u, w = O.region_representative(iu, iw)
+            for fx in (1, -1):
+                for fy in (1, -1):
+                    for sw in (False, True):
+                        x, y = (float(w), float(u)) if sw else (float(u), float(w))
+                        c = complex(fx * x, fy * y)
+                        d = O.sqabs(c - O.BOX)
+                        srt = np.sort(d)
+                        got = [O.demap_region(c, r) for r in range(9)]
+                        # equal to the exact order wherever that order has no tie
+                        for r in range(9):
+                            tie = (r > 0 and srt[r] - srt[r - 1] < 1e-12) or (r < 8 and srt[r + 1] - srt[r] < 1e-12)
+                            if not tie:
+                                assert got[r] == O.BOX[np.argsort(d, kind="stable")[r]], (iu, iw, r)
+
+
+def test_region_demap_search_with_point_orders_is_the_exact_search():
+    """A region table filled with exact orders (demap 'region-exact-point')
+    reproduces the exact same-path-set search bit for bit."""
+    wl = vpgen.cfg2(20, n_sc=2)
+    for sc in range(2):
+        p = O.preprocess(wl.H[sc], wl.alpha)
+        paths = O.mop_paths_kbest(p.w2, 24)
+        sl = slice(sc * wl.n_sym, sc * wl.n_sym + 4)
+        a = O.search_paths(p.W, p.perm, wl.s[:, sl], wl.tau, paths)
+        b = O.search_paths(p.W, p.perm, wl.s[:, sl], wl.tau, paths, demap="region-exact-point")
+        assert np.array_equal(a.l, b.l) and np.array_equal(a.kidx, b.kidx)
+        np.testing.assert_allclose(a.path_cost, b.path_cost, rtol=1e-12)

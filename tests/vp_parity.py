@@ -169,3 +169,86 @@ def check_search_subcarrier(rep: ParityReport, W, perm, s_user, tau, paths, incl
         else:
             rep.failures.append((v, "l", lg.tolist(), res.l[v].tolist(), kg, int(res.kidx[v]), c64_g, c_orc))
     return res
+
+
+def region_relaxed_walks(W, st, tau, ranks, eps=1e-5, limit=64):
+    """Every l (level order) the region-table DEMAP walk of `ranks` can produce
+    when float32 may put a centre on either side of a boundary within eps
+    (relative) of it -- the anchor's rounding, the fold or a cell edge: the
+    region DEMAP is evaluated at the centre and at eight points around it.
+    Returns a list of (l, cost)."""
+    n = W.shape[0]
+    taul = np.broadcast_to(np.asarray(tau, dtype=np.float64), (n,))
+    around = [0, 1, -1, 1j, -1j, 1 + 1j, 1 - 1j, -1 + 1j, -1 - 1j]
+    out = []
+
+    def rec(i, resid, l, cost):
+        if len(out) >= limit:
+            return
+        if i == n:
+            out.append((l.copy(), cost))
+            return
+        c = -resid[i] / (taul[i] * W[i, i])
+        e = eps * (1.0 + abs(c))
+        seen = []
+        for z in around:
+            t = O.demap_region(c + e * z, int(ranks[i]))
+            if t not in seen:
+                seen.append(t)
+        for t in seen:
+            l[i] = t
+            nres = resid.copy()
+            nres[i + 1:] += taul[i] * W[i + 1:, i] * t
+            rec(i + 1, nres, l, cost + taul[i] ** 2 * abs(W[i, i]) ** 2 * O.sqabs(c - t))
+        l[i] = 0
+
+    rec(0, st.copy(), np.zeros(n, dtype=np.complex128), 0.0)
+    return out
+
+
+def check_search_subcarrier_region(rep: ParityReport, W, perm, s_user, tau, paths, include_zero,
+                                   l_gpu, cost_gpu, kidx_gpu):
+    """As check_search_subcarrier, for the region-table DEMAP: the oracle walks
+    with it too; a differing l must be a cost tie, or a boundary tie -- the
+    GPU's path, re-walked with boundary decisions relaxed, reaches l_gpu, and
+    l_gpu costs no more than every path's relaxed outcomes."""
+    W = np.asarray(W, np.complex128)
+    perm = np.asarray(perm, np.int64)
+    paths = np.asarray(paths, np.int64)
+    K, n = paths.shape
+    res = O.search_paths(W, perm, s_user, tau, paths, include_zero=include_zero, demap="region")
+    s_user = np.asarray(s_user, np.complex128)
+    taul = O.level_tau(tau, perm)
+    for v in range(s_user.shape[1]):
+        rep.n += 1
+        lg = l_gpu[v]
+        c64_g = O.cost_tri(W, perm, s_user[:, v], lg, tau)
+        rel = abs(float(cost_gpu[v]) - c64_g) / max(c64_g, 1e-30)
+        rep.max_cost_rel_err = max(rep.max_cost_rel_err, rel)
+        if not rel <= COST_RTOL:
+            rep.failures.append((v, "cost", float(cost_gpu[v]), c64_g))
+            continue
+        c_orc = float(res.cost[v])
+        if np.array_equal(lg, res.l[v]):
+            rep.exact += 1
+            continue
+        if abs(c64_g - c_orc) <= COST_RTOL * c_orc:
+            rep.cost_ties += 1
+            continue
+        kg = int(kidx_gpu[v])
+        st = W @ s_user[perm, v]
+        ok = False
+        if 0 <= kg < K:
+            ok = any(np.array_equal(w[0], lg[perm]) for w in region_relaxed_walks(W, st, taul, paths[kg]))
+        elif kg == K and include_zero:
+            ok = not np.any(lg)
+        if ok:
+            bound = min(max(w[1] for w in region_relaxed_walks(W, st, taul, paths[k])) for k in range(K))
+            if include_zero:
+                bound = min(bound, float(np.sum(np.abs(st) ** 2)))
+            ok = c64_g <= bound * (1 + COST_RTOL)
+        if ok:
+            rep.order_ties += 1
+        else:
+            rep.failures.append((v, "l", lg.tolist(), res.l[v].tolist(), kg, int(res.kidx[v]), c64_g, c_orc))
+    return res
