@@ -522,6 +522,102 @@ def sphere_encode(W, perm, s, tau, radius: float = math.inf):
 
 
 # ---------------------------------------------------------------------------
+# The path walk in 16-bit fixed point (the accelerator's number format,
+# Sec. V "Precision and Numerical Accuracy": signed 16 bits, F = 8..13
+# fractional bits)
+# ---------------------------------------------------------------------------
+# Reading (the paper fixes only the word width and the fractional bits): the
+# walk's state is the level centre c_m = -r_m / (tau W_mm); a level's child
+# moves the centres below it by V_mi l_i with V_mi = -W_mi / W_mm, and its PED
+# is tau^2 W_ii^2 |l_i - c_i|^2.  Centres, V and the weights
+# w_i = W_ii^2 / max_j W_jj^2 are signed 16-bit numbers with F fractional bits
+# (round to nearest, ties to even, saturating); squared distances are formed
+# from differences saturated to 16 bits, and the PED sum sum_i w_i d_i is kept
+# exactly (64 bits), as a DSP accumulator would.
+
+FX_MIN, FX_MAX = -32768, 32767
+
+
+def fx_quantize(x, frac_bits: int):
+    """Real values to signed 16-bit integers with frac_bits fractional bits."""
+    return np.clip(np.rint(np.asarray(x, dtype=np.float64) * 2.0 ** frac_bits), FX_MIN, FX_MAX).astype(np.int64)
+
+
+def fx_inputs(W, perm, s, tau, frac_bits: int):
+    """The fixed-point inputs of the walk for one subcarrier: start centres
+    c0 [V][N] (complex as [..., 2] int), step coefficients V [N][N] (lower, [..., 2])
+    and weights w [N], from float64 W, perm, symbols s [N][V] (user order)."""
+    W = np.asarray(W, np.complex128)
+    n = W.shape[0]
+    st = (np.asarray(s, np.complex128)[np.asarray(perm), :]).T @ W.T        # [V][N] = (W s_pi)^T
+    d = np.real(np.diag(W))
+    c0 = -st / (tau * d[None, :])
+    Vm = -W / d[:, None]                                                     # V_mi = -W_mi / W_mm
+    w = d ** 2 / np.max(d ** 2)
+    def q(z):
+        return np.stack([fx_quantize(np.real(z), frac_bits), fx_quantize(np.imag(z), frac_bits)], axis=-1)
+
+    Vq = q(Vm)
+    Vq[np.triu_indices(n)] = 0          # only the strictly lower part (m > i) is used
+    return q(c0), Vq, fx_quantize(w, frac_bits)
+
+
+def fx_sat(x):
+    return np.clip(x, FX_MIN, FX_MAX)
+
+
+def fx_demap(cx: int, cy: int, rank: int, frac_bits: int):
+    """Box point of the given rank for a fixed-point centre: the nine squared
+    distances from differences saturated to 16 bits, ordered by (distance, j)."""
+    one = 1 << frac_bits
+    d = []
+    for j, b in enumerate(BOX):
+        ex = int(fx_sat(cx - int(b.real) * one))
+        ey = int(fx_sat(cy - int(b.imag) * one))
+        d.append((ex * ex + ey * ey, j))
+    d.sort()
+    dist, j = d[rank]
+    return int(BOX[j].real), int(BOX[j].imag), dist
+
+
+def fx_search(c0, Vq, wq, paths, frac_bits: int, include_zero: bool = True):
+    """The same-path-set search in fixed point for one subcarrier.  c0 [V][N][2],
+    Vq [N][N][2] (lower), wq [N] from fx_inputs; paths [K][N].  Returns
+    (l level order [V][N] complex, ped [V] int, kidx [V]); the zero perturbation,
+    with include_zero, is candidate K with PED sum_i w_i |c0_i|^2."""
+    c0 = np.asarray(c0, np.int64)
+    n = c0.shape[1]
+    K = len(paths)
+    Vn = c0.shape[0]
+    l_out = np.zeros((Vn, n), dtype=np.complex128)
+    ped_out = np.zeros(Vn, dtype=object)
+    k_out = np.zeros(Vn, dtype=np.int64)
+    for v in range(Vn):
+        best = None
+        for k in range(K + (1 if include_zero else 0)):
+            c = c0[v].copy()
+            ped = 0
+            l = np.zeros(n, dtype=np.complex128)
+            for i in range(n):
+                if k == K:
+                    a, b = 0, 0
+                    ex, ey = int(fx_sat(c[i, 0])), int(fx_sat(c[i, 1]))
+                    dist = ex * ex + ey * ey
+                else:
+                    a, b, dist = fx_demap(int(c[i, 0]), int(c[i, 1]), int(paths[k][i]), frac_bits)
+                l[i] = complex(a, b)
+                ped += int(wq[i]) * dist
+                for m in range(i + 1, n):   # c_m += V_mi l_i, l_i in the box: additions
+                    vx, vy = int(Vq[m, i, 0]), int(Vq[m, i, 1])
+                    c[m, 0] = fx_sat(c[m, 0] + a * vx - b * vy)
+                    c[m, 1] = fx_sat(c[m, 1] + a * vy + b * vx)
+            if best is None or ped < best[0]:
+                best = (ped, k, l)
+        ped_out[v], k_out[v], l_out[v] = best
+    return l_out, ped_out, k_out
+
+
+# ---------------------------------------------------------------------------
 # Precoding, receiver modulo, power gap (Alg. 2 output, eq:postproc)
 # ---------------------------------------------------------------------------
 

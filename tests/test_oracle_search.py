@@ -315,3 +315,64 @@ def test_region_demap_search_with_point_orders_is_the_exact_search():
         b = O.search_paths(p.W, p.perm, wl.s[:, sl], wl.tau, paths, demap="region-exact-point")
         assert np.array_equal(a.l, b.l) and np.array_equal(a.kidx, b.kidx)
         np.testing.assert_allclose(a.path_cost, b.path_cost, rtol=1e-12)
+
+
+def test_fixed_point_walk_pins():
+    """The 16-bit fixed-point walk (Sec. V precision study).  Pinned by: on
+    the same quantised inputs it picks what the float64 walk (demap_walk, an
+    independent code path) picks on the problem those integers represent --
+    W~ with W~_mm = sqrt(w_m), W~_mj = -V_mj W~_mm and s~_m = -c0_m tau W~_mm --
+    except at near ties, with a PED equal to that walk's cost scaled by
+    2^(3F) / tau^2; saturation of a centre beyond the 16-bit range; and a
+    quantisation error that shrinks with the fractional bits."""
+    wl = vpgen.cfg2(20, n_sc=3)
+    for F in (8, 13):
+        for sc in range(3):
+            p = O.preprocess(wl.H[sc], wl.alpha)
+            paths = O.mop_paths_kbest(p.w2, 16)
+            sl = slice(sc * wl.n_sym, sc * wl.n_sym + 5)
+            c0, Vq, wq = O.fx_inputs(p.W, p.perm, wl.s[:, sl], wl.tau, F)
+            lf, ped, kf = O.fx_search(c0, Vq, wq, paths, F, include_zero=False)
+            one = 2.0 ** F
+            Wt = np.zeros((wl.N, wl.N), complex)
+            d = np.sqrt(wq / one)
+            for m in range(wl.N):
+                Wt[m, m] = d[m]
+                for j in range(m):
+                    Wt[m, j] = -(Vq[m, j, 0] + 1j * Vq[m, j, 1]) / one * d[m]
+            st = -((c0[..., 0] + 1j * c0[..., 1]) / one) * wl.tau * d[None, :]      # [V][N]
+            l64, cost64, margin = O.demap_walk(Wt, st, wl.tau, paths)
+            for v in range(st.shape[0]):
+                k = int(np.argmin(cost64[v]))
+                if np.min(margin[v]) < 1e-6:
+                    continue                         # a near tie: float64 and the integers may part
+                assert k == kf[v] and np.array_equal(l64[v, k], lf[v]), (F, sc, v)
+                assert abs(float(ped[v]) / one ** 3 - cost64[v, k] / wl.tau ** 2) <= 1e-9 * float(ped[v]) / one ** 3
+    # saturation: a centre of 5 at 13 fractional bits is held at the largest value
+    assert O.fx_quantize(5.0, 13) == 32767 and O.fx_quantize(-5.0, 13) == -32768
+    assert O.fx_demap(32767, 0, 0, 13)[:2] == (1, 0)
+    # saturated steps and differences, worked by hand at F = 13 (one = 8192):
+    # c0 = (32767, 0), (32000, 0); V_10 = 1.0; w = 1.0 each.  Level 0 takes
+    # a = 1 (distance 24575^2); the step 32000 + 8192 = 40192 is held at 32767,
+    # so level 1 sees the same centre and distance: PED = 8192 * 2 * 24575^2.
+    # The zero candidate's distances are 32767^2 and 32000^2.
+    c0 = np.array([[[32767, 0], [32000, 0]]])
+    Vq = np.zeros((2, 2, 2), dtype=np.int64)
+    Vq[1, 0] = (8192, 0)
+    wq = np.array([8192, 8192])
+    l, ped, k = O.fx_search(c0, Vq, wq, [[0, 0], [1, 0]], 13, include_zero=True)
+    assert k[0] == 0 and list(l[0]) == [1, 1] and ped[0] == 8192 * 2 * 24575 ** 2
+    # rank 1 at level 0 from a centre of 32767: (1, 1) and (1, -1) tie at
+    # 24575^2 + 8192^2; the smaller box index 3 (re + 1) + (im + 1) wins: (1, -1)
+    assert O.fx_demap(32767, 0, 1, 13) == (1, -1, 24575 ** 2 + 8192 ** 2)
+    # a difference below -32768 saturates: centre -32768, box point +1
+    assert O.fx_demap(-32768, 0, 8, 13)[2] == 32768 ** 2 + 8192 ** 2
+    # the quantisation error of the inputs halves with every fractional bit
+    p = O.preprocess(wl.H[0], wl.alpha)
+    errs = []
+    for F in (8, 10, 12):
+        c0, _, _ = O.fx_inputs(p.W, p.perm, wl.s[:, :14], wl.tau, F)
+        st = (wl.s[:, :14][p.perm, :]).T @ p.W.T
+        exact = -st / (wl.tau * np.real(np.diag(p.W)))[None, :]
+        errs.append(np.max(np.abs(c0[..., 0] / 2.0 ** F - exact.real)))
+    assert errs[0] > errs[1] > errs[2] and errs[2] <= 2.0 ** -13
