@@ -105,20 +105,68 @@ def gap_to_exact(vp, prep, s, tau, n_sym, cost, counts=None):
     return 10 * math.log10(float(cost.double().sum()) / float(exact.sum())), exact
 
 
-def rzf_powers(prep, s, n_sym):
-    """gamma of linear RZF (l = 0) per vector: ||W s_pi||^2, from the packed
-    lower W (column-major) and the level order, in complex128 (a reported
-    reference, outside every timed region)."""
+def vp_powers(prep, s, n_sym, l=None, tau=0.0):
+    """gamma = ||W (s_pi + tau l_pi)||^2 per vector, from the packed lower W
+    (column-major), the level order and l (int8 [N][n_vec][2], user order; None
+    for l = 0, linear RZF), in complex128 (a reported reference, outside every
+    timed region)."""
     import torch
     n_sc, N = prep.perm.shape
     cols = [j for j in range(N) for _ in range(j, N)]
     rows = [i for j in range(N) for i in range(j, N)]
     Wd = torch.zeros((n_sc, N, N), dtype=torch.complex128, device=prep.W.device)
     Wd[:, rows, cols] = prep.W.to(torch.complex128)
-    S = s.to(torch.complex128).t().reshape(n_sc, n_sym, N)
+    u = s.to(torch.complex128)
+    if l is not None:
+        u = u + tau * torch.complex(l[..., 0].double(), l[..., 1].double())
+    S = u.t().reshape(n_sc, n_sym, N)
     Sp = torch.gather(S, 2, prep.perm.long()[:, None, :].expand(n_sc, n_sym, N)).contiguous()
     Y = torch.matmul(Sp, Wd.transpose(1, 2).contiguous())
     return (Y.abs() ** 2).sum(dim=2).reshape(-1)
+
+
+def rzf_powers(prep, s, n_sym):
+    return vp_powers(prep, s, n_sym)
+
+
+def bench_fixed_point(vp, dev="cuda:0"):
+    """The 16-bit fixed-point walk (vp_fx_quantize + vp_fx_search) against the
+    float32 walk, for F = 8..13 fractional bits: power gap to exact VP of the
+    perturbations either one chooses, every power evaluated in complex128 from
+    the chosen l (outside every timed region), and the fixed-point search's
+    kernel time (an emulation, not a tuned path)."""
+    import torch
+    import vpgen
+    res = {}
+    for wl in (vpgen.cfg3(512, n_sc=546), vpgen.cfg2(20, n_sc=546)):
+        H = torch.from_numpy(wl.H).to(dev)
+        s = torch.from_numpy(wl.s).to(dev)
+        prep = vp.preprocess(H, wl.alpha)
+        order = torch.empty((wl.n_sc, 2, wl.K), dtype=torch.int16, device=dev)
+        paths = vp.paths_mop(prep.w2, wl.K, order=order)
+        of = vp.search(prep.W, prep.perm, s, wl.tau, paths, wl.n_sym, order=order)
+        pf = vp_powers(prep, s, wl.n_sym, of.l, wl.tau)
+        rows, fx = {}, {}
+        for F in range(8, 14):
+            q = vp.fx_quantize(prep.W, prep.perm, s, wl.tau, wl.n_sym, F)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            o = vp.fx_search(q, prep.perm, paths, wl.n_sym)
+            e1.record()
+            torch.cuda.synchronize()
+            fx[F] = (vp_powers(prep, s, wl.n_sym, o.l, wl.tau), o.l, e0.elapsed_time(e1))
+        radius = torch.minimum(pf, torch.stack([v[0] for v in fx.values()]).min(dim=0).values)
+        se = vp.sphere_encode(prep.W, prep.perm, s, wl.tau, wl.n_sym, radius=(radius * (1 + 1e-6)).float())
+        pe = torch.where(torch.isfinite(se.cost), vp_powers(prep, s, wl.n_sym, se.l, wl.tau), radius)
+        pe = torch.minimum(pe, radius)
+        den = float(pe.sum())
+        for F, (p, l, ms) in fx.items():
+            rows[str(F)] = {"gap_db": 10 * math.log10(float(p.sum()) / den),
+                            "same_l_as_float32": float((l == of.l).all(dim=2).all(dim=0).double().mean()),
+                            "search_ms": ms}
+        res[wl.name] = {"K": wl.K, "vectors": wl.n_vec, "gap_db_float32": 10 * math.log10(float(pf.sum()) / den),
+                        "fixed_point": rows}
+    return res
 
 
 def bench_batched(vp, steps, warmup):
@@ -540,7 +588,7 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the gap, K points, batched and learned forms")
     ap.add_argument("--no-forms", action="store_true", help="keep the gap and K points, skip the batched and "
                                                             "learned forms")
-    ap.add_argument("--only", choices=("batched", "learned"), default=None,
+    ap.add_argument("--only", choices=("batched", "learned", "fixed"), default=None,
                     help="run one further form alone (for profiling) and print its record")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -555,6 +603,9 @@ def main():
     dev = "cuda:0"
     if args.only == "batched":
         print(json.dumps({"batched": bench_batched(vp, args.steps, args.warmup)}), flush=True)
+        return
+    if args.only == "fixed":
+        print(json.dumps({"fixed_point_16bit": bench_fixed_point(vp, dev)}), flush=True)
         return
     wl = vpgen.cfg3(args.K)
     N, M, n_sc, n_sym, K = wl.N, wl.M, wl.n_sc, wl.n_sym, args.K
@@ -619,6 +670,8 @@ def main():
     if not args.no_extras:
         print("ablations ...", file=sys.stderr, flush=True)
         line["ablations"] = bench_ablations(vp, dev)
+        print("16-bit fixed-point walk ...", file=sys.stderr, flush=True)
+        line["ablations"]["fixed_point_16bit"] = bench_fixed_point(vp, dev)
     if not args.no_extras:
         # the paper's region-table DEMAP against the exact child order, same slot
         print("region-table DEMAP ...", file=sys.stderr, flush=True)

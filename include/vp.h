@@ -268,6 +268,58 @@ int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, floa
                      int n_r, const float *radius, int64_t max_nodes, int8_t *l, float *cost, int64_t *nodes,
                      uint8_t *status, void *stream);
 
+/*
+ * vp_fx_quantize -- the walk's inputs in signed 16-bit fixed point with
+ * frac_bits fractional bits (the number format of the accelerator, Sec. V
+ * precision study: 16-bit words, F = 8..13 fractional bits).
+ *
+ * The fixed-point walk follows the level centres c_m = -r_m / (tau W_mm)
+ * instead of the residuals: the child l_i of level i moves every centre below
+ * it by V_mi l_i with V_mi = -W_mi / W_mm, and adds w_i |l_i - c_i|^2 to the
+ * PED, w_i = W_ii^2 / max_j W_jj^2 (the PED of the float walk divided by
+ * tau^2 max_j W_jj^2, which orders paths the same way).  Every value is
+ * rounded to nearest (ties to even) after scaling by 2^frac_bits and
+ * saturated to [-32768, 32767]; the arithmetic before rounding is float32.
+ *
+ *  W, perm, s, tau, n_sc, n_sym, n_r  as in vp_search; tau finite and > 0
+ *  c0  [n_vec][N][2] output int16: start centres (re, im) in level order
+ *  V   [n_sc][N(N-1)/2][2] output int16: V_mi for m > i, entry m(m-1)/2 + i
+ *  w   [n_sc][N] output int16
+ *
+ * Non-finite values (a failed vp_preprocess) quantise to 0 (NaN) or
+ * saturate (infinities).  Errors: VP_EINVAL for NULL pointers, bad sizes or
+ * frac_bits outside 8..13; VP_EUNSUPPORTED for N > 16.
+ */
+int vp_fx_quantize(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau, int n_sc, int n_sym,
+                   int n_r, int frac_bits, int16_t *c0, int16_t *V, int16_t *w, void *stream);
+
+/*
+ * vp_fx_search -- the same-path-set search (Alg. 2) walked in 16-bit fixed
+ * point on the outputs of vp_fx_quantize.
+ *
+ * Every path's walk is integer arithmetic: the nine squared distances to the
+ * box points come from differences saturated to 16 bits (each < 2^31), the
+ * path's rank picks the box point in (distance, box index) order with box
+ * index 3 (re + 1) + (im + 1), the PED sum_i w_i d_i is exact in 64 bits, and
+ * each centre step c_m + V_mi l_i is saturated to 16 bits.  With
+ * VP_INCLUDE_ZERO the zero perturbation is candidate K.  The chosen path has
+ * the smallest (PED, path index).
+ *
+ *  c0, V, w   from vp_fx_quantize (same n_sc, n_sym, n_r, frac_bits)
+ *  perm       [n_sc][N] from vp_preprocess (writes l in user order)
+ *  paths, K, paths_sc_stride  as in vp_search (no order, no per-vector paths)
+ *  flags      0 or VP_INCLUDE_ZERO
+ *  l          [N][n_vec][2] output int8, user order
+ *  ped        [n_vec] output int64: the chosen path's fixed-point PED
+ *  kidx       [n_vec] output: chosen path (K = zero perturbation)
+ *
+ * Errors: VP_EINVAL for NULL pointers, bad sizes or strides, unknown flags,
+ * frac_bits outside 8..13; VP_EUNSUPPORTED for N > 16 or K > 4096.
+ */
+int vp_fx_search(const int16_t *c0, const int16_t *V, const int16_t *w, const uint8_t *perm, const uint8_t *paths,
+                 int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r, int frac_bits, uint32_t flags,
+                 int8_t *l, int64_t *ped, int32_t *kidx, void *stream);
+
 /* Human-readable text for a return code. */
 const char *vp_strerror(int code);
 

@@ -50,6 +50,8 @@ SIGNATURES = {
     "vp_precode": [_P, _P, _P, _P, _P, _I, _I, _I, _I, _F, _P, _P],
     "vp_apply_user_tau": [_P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P],
     "vp_sphere_encode": [_P, _P, _P, _F, _I, _I, _I, _P, ctypes.c_int64, _P, _P, _P, _P, _P],
+    "vp_fx_quantize": [_P, _P, _P, _P, _I, _I, _I, _I, _P, _P, _P, _P],
+    "vp_fx_search": [_P, _P, _P, _P, _P, _I, ctypes.c_int64, _I, _I, _I, _I, ctypes.c_uint32, _P, _P, _P, _P],
     "vp_strerror": [_I],
     "vp_last_hip_error": [],
     "vp_version": [],

@@ -151,6 +151,30 @@ int vp_sphere_encode(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, floa
                          status, (long long)max_nodes, (hipStream_t)stream);
 }
 
+int vp_fx_quantize(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, const float *tau, int n_sc, int n_sym,
+                   int n_r, int frac_bits, int16_t *c0, int16_t *V, int16_t *w, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || frac_bits < 8 || frac_bits > 13) return VP_EINVAL;
+    if (n_r > kMaxN) return VP_EUNSUPPORTED;
+    if (n_sc == 0) return VP_OK;
+    if (!W || !perm || !s || !tau || !c0 || !w || (n_r > 1 && !V)) return VP_EINVAL;
+    return launch_fx_quantize((const float2 *)W, perm, (const float2 *)s, tau, n_sc, n_sym, n_r, frac_bits, c0, V, w,
+                              (hipStream_t)stream);
+}
+
+int vp_fx_search(const int16_t *c0, const int16_t *V, const int16_t *w, const uint8_t *perm, const uint8_t *paths,
+                 int K, int64_t paths_sc_stride, int n_sc, int n_sym, int n_r, int frac_bits, uint32_t flags,
+                 int8_t *l, int64_t *ped, int32_t *kidx, void *stream) {
+    if (n_sc < 0 || n_sym < 1 || n_r < 1 || K < 1 || frac_bits < 8 || frac_bits > 13) return VP_EINVAL;
+    if (n_r > kMaxN || K > kMaxKSearch) return VP_EUNSUPPORTED;
+    if (paths_sc_stride < 0 || (paths_sc_stride > 0 && paths_sc_stride < (int64_t)K * n_r)) return VP_EINVAL;
+    if (flags & ~(uint32_t)VP_INCLUDE_ZERO) return VP_EINVAL;
+    if (n_sc == 0) return VP_OK;
+    if ((int64_t)n_sc * n_sym > 0x7fffffffLL) return VP_EUNSUPPORTED;   // one workgroup per vector
+    if (!c0 || !w || (n_r > 1 && !V) || !perm || !paths || !l || !ped || !kidx) return VP_EINVAL;
+    return launch_fx_search(c0, V, w, perm, paths, K, paths_sc_stride, n_sc, n_sym, n_r, frac_bits, flags, l, ped,
+                            kidx, (hipStream_t)stream);
+}
+
 int vp_mlp_features(const vp_c32 *W, const uint8_t *perm, const vp_c32 *s, float tau, int n_sc, int n_sym, int n_r,
                     uint32_t kind, uint16_t *feat, void *stream) {
     if (n_sc < 0 || n_sym < 1 || n_r < 1 || !(tau > 0.f) || !isfinite(tau)) return VP_EINVAL;

@@ -94,6 +94,11 @@ int launch_search_fallback_noalloc(const float2 *W, const uint8_t *perm, const f
                                    int32_t kidx_base, int8_t *l, float *cost, int32_t *kidx, hipStream_t st);
 int launch_user_tau(const float *tau, const uint8_t *perm, int n_sc, int n_sym, int N, int M, float2 *W, float *w2,
                     float2 *G, const float2 *s, float2 *s_out, hipStream_t st);
+int launch_fx_quantize(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, int n_sc, int n_sym,
+                       int N, int frac_bits, int16_t *c0, int16_t *Vq, int16_t *wq, hipStream_t st);
+int launch_fx_search(const int16_t *c0, const int16_t *Vq, const int16_t *wq, const uint8_t *perm,
+                     const uint8_t *paths, int K, int64_t pstride, int n_sc, int n_sym, int N, int frac_bits,
+                     uint32_t flags, int8_t *l, int64_t *ped, int32_t *kidx, hipStream_t st);
 int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost,
                    int n_sc, int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st);
 

@@ -13,7 +13,7 @@ import torch
 from . import _lib
 from ._lib import VP_DEMAP_REGION, VP_INCLUDE_ZERO, VP_PATHS_PER_VECTOR, VP_SE_EXACT, VP_SE_EXHAUSTED, VP_SE_NONE, check
 
-__all__ = ["Prep", "SearchOut", "SEOut", "tau_array", "apply_user_tau", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
+__all__ = ["Prep", "SearchOut", "SEOut", "FxInputs", "FxOut", "fx_quantize", "fx_search", "tau_array", "apply_user_tau", "preprocess", "paths_mop", "search", "precode", "sphere_encode", "packed_size",
            "VP_INCLUDE_ZERO", "VP_PATHS_PER_VECTOR", "VP_DEMAP_REGION", "VP_SE_EXACT", "VP_SE_EXHAUSTED", "VP_SE_NONE", "version"]
 
 
@@ -219,4 +219,72 @@ def sphere_encode(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau: flo
     pst = _req(out.status, "status", torch.uint8, (n_vec,))
     check(lib.vp_sphere_encode(pW, pp, ps, float(tau), n_sc, int(n_sym), N, pr, int(max_nodes), pl, pc, pn, pst,
                                _stream()), "vp_sphere_encode")
+    return out
+
+
+class FxInputs(NamedTuple):
+    c0: torch.Tensor      # int16 [n_vec][N][2] start centres, level order
+    V: torch.Tensor       # int16 [n_sc][N(N-1)/2][2] steps V_mi (m > i) at m(m-1)/2 + i
+    w: torch.Tensor       # int16 [n_sc][N] PED weights
+    frac_bits: int
+
+
+class FxOut(NamedTuple):
+    l: torch.Tensor       # int8 [N][n_vec][2]
+    ped: torch.Tensor     # int64 [n_vec] fixed-point PED of the chosen path
+    kidx: torch.Tensor    # int32 [n_vec]
+
+
+def fx_quantize(W: torch.Tensor, perm: torch.Tensor, s: torch.Tensor, tau, n_sym: int, frac_bits: int,
+                out: Optional[FxInputs] = None) -> FxInputs:
+    """vp_fx_quantize: the walk's inputs in 16-bit fixed point with frac_bits
+    fractional bits (8..13)."""
+    lib = _lib.load()
+    n_sc = W.shape[0]
+    N = perm.shape[1]
+    n_vec = n_sc * n_sym
+    dev = W.device
+    nv = N * (N - 1) // 2
+    if out is None:
+        out = FxInputs(torch.empty((n_vec, N, 2), dtype=torch.int16, device=dev),
+                       torch.empty((n_sc, nv, 2), dtype=torch.int16, device=dev),
+                       torch.empty((n_sc, N), dtype=torch.int16, device=dev), int(frac_bits))
+    taus = tau_array(tau, n_sc, dev)
+    check(lib.vp_fx_quantize(_req(W, "W", torch.complex64, (n_sc, packed_size(N))),
+                             _req(perm, "perm", torch.uint8, (n_sc, N)),
+                             _req(s, "s", torch.complex64, (N, n_vec)), taus.data_ptr(), n_sc, int(n_sym), N,
+                             int(frac_bits), _req(out.c0, "c0", torch.int16, (n_vec, N, 2)),
+                             _req(out.V, "V", torch.int16, (n_sc, nv, 2)) if nv else None,
+                             _req(out.w, "w", torch.int16, (n_sc, N)), _stream()), "vp_fx_quantize")
+    return out._replace(frac_bits=int(frac_bits))
+
+
+def fx_search(q: FxInputs, perm: torch.Tensor, paths: torch.Tensor, n_sym: int, flags: int = VP_INCLUDE_ZERO,
+              out: Optional[FxOut] = None) -> FxOut:
+    """vp_fx_search: the path walk in 16-bit fixed point; paths is [K][N] (one
+    table) or [n_sc][K][N]."""
+    lib = _lib.load()
+    n_sc, N = perm.shape
+    n_vec = n_sc * n_sym
+    if paths.dim() == 2:
+        K, stride = paths.shape[0], 0
+    else:
+        if paths.shape[0] != n_sc:
+            raise ValueError(f"paths: first dimension must be {n_sc}")
+        K, stride = paths.shape[1], paths.shape[1] * paths.shape[2]
+    if paths.shape[-1] != N:
+        raise ValueError("paths: last dimension must be N")
+    dev = perm.device
+    nv = N * (N - 1) // 2
+    if out is None:
+        out = FxOut(torch.empty((N, n_vec, 2), dtype=torch.int8, device=dev),
+                    torch.empty((n_vec,), dtype=torch.int64, device=dev),
+                    torch.empty((n_vec,), dtype=torch.int32, device=dev))
+    check(lib.vp_fx_search(_req(q.c0, "c0", torch.int16, (n_vec, N, 2)),
+                           _req(q.V, "V", torch.int16, (n_sc, nv, 2)) if nv else None,
+                           _req(q.w, "w", torch.int16, (n_sc, N)), _req(perm, "perm", torch.uint8, (n_sc, N)),
+                           _req(paths, "paths", torch.uint8), int(K), int(stride), n_sc, int(n_sym), N,
+                           int(q.frac_bits), int(flags), _req(out.l, "l", torch.int8, (N, n_vec, 2)),
+                           _req(out.ped, "ped", torch.int64, (n_vec,)), _req(out.kidx, "kidx", torch.int32, (n_vec,)),
+                           _stream()), "vp_fx_search")
     return out

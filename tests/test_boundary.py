@@ -34,7 +34,7 @@ def test_header_symbols_exported(lib):
     names = declared_functions()
     assert {"vp_preprocess", "vp_paths_mop", "vp_search", "vp_precode", "vp_strerror", "vp_sphere_encode",
             "vp_mlp_features", "vp_path_ranks", "vp_gemm_bf16", "vp_topk64", "vp_softmax_xent", "vp_colsum_bf16",
-            "vp_learned_paths", "vp_search_fallback"} <= set(names)
+            "vp_learned_paths", "vp_search_fallback", "vp_fx_quantize", "vp_fx_search"} <= set(names)
     for n in names:
         assert hasattr(lib, n), n
     out = subprocess.run(["nm", "-D", "--defined-only", os.path.join(PKG, "libvp.so")],
@@ -108,6 +108,27 @@ def test_argument_validation(lib):
     assert lib.vp_precode(P, P, P, None, P, 1, 14, 4, 4, 1.0, P, None) == VP_EINVAL       # NULL tau
     assert lib.vp_precode(None, None, None, P, None, 1, 14, 4, 4, -1.0, None, None) == VP_EINVAL
     assert lib.vp_precode(None, None, None, P, None, 1, 14, 17, 4, 0.0, None, None) == VP_EUNSUPPORTED
+    # vp_fx_quantize / vp_fx_search: frac_bits in 8..13, the vp_search checks
+    assert lib.vp_fx_quantize(None, None, None, P, 0, 14, 4, 12, None, None, None, None) == VP_OK
+    assert lib.vp_fx_quantize(P, P, P, P, 1, 14, 4, 14, P, P, P, None) == VP_EINVAL
+    assert lib.vp_fx_quantize(P, P, P, P, 1, 14, 4, 7, P, P, P, None) == VP_EINVAL
+    assert lib.vp_fx_quantize(P, P, P, None, 1, 14, 4, 12, P, P, P, None) == VP_EINVAL      # NULL tau
+    assert lib.vp_fx_quantize(P, P, P, P, 1, 14, 4, 12, P, None, P, None) == VP_EINVAL      # NULL V, N > 1
+    assert lib.vp_fx_quantize(P, P, P, P, 1, 14, 17, 12, P, P, P, None) == VP_EUNSUPPORTED
+
+    def fx(Q=P, **kw):
+        a = dict(dict(K=32, stride=0, n_sc=1, n_sym=14, N=4, F=12, flags=1), **kw)
+        return lib.vp_fx_search(Q, Q, Q, Q, Q, a["K"], a["stride"], a["n_sc"], a["n_sym"], a["N"], a["F"],
+                                a["flags"], Q, Q, Q, None)
+    assert fx(None) == VP_EINVAL
+    assert fx(None, n_sc=0) == VP_OK
+    assert fx(F=14) == VP_EINVAL
+    assert fx(flags=4) == VP_EINVAL                 # no region DEMAP in fixed point
+    assert fx(flags=2) == VP_EINVAL                 # no per-vector paths
+    assert fx(stride=5) == VP_EINVAL
+    assert fx(K=0) == VP_EINVAL
+    assert fx(K=4097) == VP_EUNSUPPORTED
+    assert fx(N=17) == VP_EUNSUPPORTED
     assert lib.vp_strerror(VP_EINVAL) == b"invalid argument"
     assert lib.vp_last_hip_error() == 0
     _ = F
