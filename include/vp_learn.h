@@ -122,6 +122,32 @@ int vp_gemm_bf16(int m, int n, int k, const uint16_t *A, int64_t lda, int trans_
 int vp_topk64(const float *scores, int rows, int C, int32_t *idx, float *mass, void *stream);
 
 /*
+ * vp_logits_top64 -- the network's last layer fused with vp_topk64.
+ *
+ * idx and mass are what vp_topk64 gives for the logits
+ * z = X Wt^T + bias (float32, as vp_gemm_bf16 computes them with trans_b:
+ * bf16 products summed on the matrix cores in increasing k, then the bias),
+ * but z is never written to memory: a first pass over the vocabulary bounds
+ * each row's 64th largest logit from below, a second keeps the logits at or
+ * above that bound, which are then ranked exactly.
+ *
+ *  X     bf16 [rows][256], 16-byte aligned (the second hidden layer)
+ *  Wt    bf16 [V][256], 16-byte aligned;  bias float32 [V]
+ *  V     a multiple of 128, 256 <= V <= VP_MAX_VOCAB
+ *  idx   int32 [rows][64];  mass float32 [rows] or NULL
+ *  work  device memory of vp_logits_top64_work_bytes(rows) bytes owned by
+ *        the caller, 256-byte aligned (bounds, candidate lists, partial sums)
+ *
+ * Errors: VP_EINVAL for rows < 0 or NULL / misaligned pointers;
+ * VP_EUNSUPPORTED for a V outside the range above.
+ */
+int vp_logits_top64(const uint16_t *X, int rows, const uint16_t *Wt, const float *bias, int V, int32_t *idx,
+                    float *mass, void *work, void *stream);
+
+/* Workspace bytes vp_logits_top64 needs for `rows` rows (about 2.1 KB each). */
+int64_t vp_logits_top64_work_bytes(int rows);
+
+/*
  * vp_softmax_xent -- softmax cross-entropy and its gradient (training).
  *
  * Per row: loss = logsumexp(z) - z[label]; dz = (softmax(z) - onehot(label))

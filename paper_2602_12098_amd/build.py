@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libvp.so")
 HOSTLIB = os.path.join(HERE, "libvphost.so")
 
 HIP_SOURCES = ["vp_api.hip", "vp_preprocess.hip", "vp_mop.hip", "vp_search.hip", "vp_precode.hip", "vp_se.hip",
-               "vp_learn.hip", "vp_batch.hip", "vp_fixed.hip"]
+               "vp_learn.hip", "vp_batch.hip", "vp_fixed.hip",
+               "vp_logits_topk.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-fPIC", "-std=c++17", "-ffp-contract=off",

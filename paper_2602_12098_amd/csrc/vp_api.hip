@@ -211,6 +211,20 @@ int vp_gemm_bf16(int m, int n, int k, const uint16_t *A, int64_t lda, int trans_
                        (hipStream_t)stream);
 }
 
+int vp_logits_top64(const uint16_t *X, int rows, const uint16_t *Wt, const float *bias, int V, int32_t *idx,
+                    float *mass, void *work, void *stream) {
+    if (rows < 0) return VP_EINVAL;
+    if (V < 256 || V > VP_MAX_VOCAB || V % 128 != 0) return VP_EUNSUPPORTED;
+    if (rows == 0) return VP_OK;
+    if (!X || !Wt || !bias || !idx || !work) return VP_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(X) & 15) || (reinterpret_cast<uintptr_t>(Wt) & 15) ||
+        (reinterpret_cast<uintptr_t>(work) & 255))
+        return VP_EINVAL;
+    return launch_logits_top64(X, rows, Wt, bias, V, idx, mass, work, (hipStream_t)stream);
+}
+
+int64_t vp_logits_top64_work_bytes(int rows) { return (int64_t)logits_top64_work_bytes(rows); }
+
 int vp_topk64(const float *scores, int rows, int C, int32_t *idx, float *mass, void *stream) {
     if (rows < 0 || C < VP_TOPK) return VP_EINVAL;
     if (C > VP_MAX_VOCAB) return VP_EUNSUPPORTED;

@@ -99,6 +99,9 @@ int launch_fx_quantize(const float2 *W, const uint8_t *perm, const float2 *s, co
 int launch_fx_search(const int16_t *c0, const int16_t *Vq, const int16_t *wq, const uint8_t *perm,
                      const uint8_t *paths, int K, int64_t pstride, int n_sc, int n_sym, int N, int frac_bits,
                      uint32_t flags, int8_t *l, int64_t *ped, int32_t *kidx, hipStream_t st);
+size_t logits_top64_work_bytes(int rows);
+int launch_logits_top64(const uint16_t *X, int rows, const uint16_t *Wt, const float *bias, int V, int32_t *idx,
+                        float *mass, void *work, hipStream_t st);
 int launch_precode(const float2 *G, const float2 *s, const int8_t *l, const float *tau, const float *cost,
                    int n_sc, int n_sym, int N, int M, float P_T, float2 *x, hipStream_t st);
 

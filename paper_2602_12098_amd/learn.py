@@ -25,7 +25,7 @@ from ._lib import check
 from .vp import VP_INCLUDE_ZERO, _req, _stream, packed_size, tau_array
 
 __all__ = ["VP_EPI_RELU", "VP_PATHS_PER_VECTOR", "N_FEATURES", "TOPK", "mlp_features", "path_ranks", "gemm_bf16",
-           "topk64", "softmax_xent", "colsum_bf16", "learned_paths", "MLPParams", "MLPFunction", "mlp_logits",
+           "topk64", "logits_top64", "logits_top64_work", "softmax_xent", "colsum_bf16", "learned_paths", "MLPParams", "MLPFunction", "mlp_logits",
            "pack_ranks", "Proposer", "load_proposer"]
 
 VP_EPI_RELU = 1
@@ -49,6 +49,8 @@ SIGNATURES = {
     "vp_softmax_xent": [_P, _I, _I, _P, _F, _P, _P, _P],
     "vp_colsum_bf16": [_P, _I, _I, _P, _P],
     "vp_learned_paths": [_P, _I, _I, _P, _I, _P, _I, _I, _I, _I, _P, _P],
+    "vp_logits_top64": [_P, _I, _P, _P, _I, _P, _P, _P, _P],
+    "vp_logits_top64_work_bytes": [_I],
 }
 _bound = False
 
@@ -61,6 +63,7 @@ def _load():
             fn = getattr(lib, name)
             fn.argtypes = argtypes
             fn.restype = _I
+        lib.vp_logits_top64_work_bytes.restype = _I64
         _bound = True
     return lib
 
@@ -145,6 +148,36 @@ def topk64(scores: torch.Tensor, with_mass: bool = True):
     mass = torch.empty((rows,), dtype=torch.float32, device=scores.device) if with_mass else None
     check(lib.vp_topk64(_req(scores, "scores", torch.float32), rows, C, idx.data_ptr(),
                         mass.data_ptr() if mass is not None else None, _stream()), "vp_topk64")
+    return idx, mass
+
+
+def logits_top64_work(rows: int, device) -> torch.Tensor:
+    """Workspace for logits_top64 on `rows` rows (uint8, 256-byte aligned)."""
+    n = int(_load().vp_logits_top64_work_bytes(int(rows)))
+    return torch.empty((n,), dtype=torch.uint8, device=device)
+
+
+def logits_top64(X: torch.Tensor, Wt: torch.Tensor, bias: torch.Tensor, with_mass: bool = True,
+                 work: Optional[torch.Tensor] = None):
+    """vp_logits_top64: the top-64 (idx int32 [rows][64]) and softmax mass of
+    X Wt^T + bias without writing the logits; X bf16 [rows][256], Wt bf16
+    [V][256], bias float32 [V]."""
+    lib = _load()
+    rows = X.shape[0]
+    V = Wt.shape[0]
+    _req(X, "X", torch.bfloat16, (rows, HIDDEN))
+    _req(Wt, "Wt", torch.bfloat16, (V, HIDDEN))
+    _req(bias, "bias", torch.float32, (V,))
+    idx = torch.empty((rows, TOPK), dtype=torch.int32, device=X.device)
+    mass = torch.empty((rows,), dtype=torch.float32, device=X.device) if with_mass else None
+    need = int(lib.vp_logits_top64_work_bytes(rows))
+    if work is None:
+        work = torch.empty((need,), dtype=torch.uint8, device=X.device)
+    elif work.numel() * work.element_size() < need:
+        raise ValueError(f"work: need {need} bytes")
+    check(lib.vp_logits_top64(X.data_ptr(), rows, Wt.data_ptr(), bias.data_ptr(), V, idx.data_ptr(),
+                              mass.data_ptr() if mass is not None else None, _req(work, "work", work.dtype),
+                              _stream()), "vp_logits_top64")
     return idx, mass
 
 
@@ -337,13 +370,21 @@ class Proposer:
         self.vocab = vocab.contiguous()   # uint8 [V][N]
 
     @torch.no_grad()
-    def propose(self, W, perm, s, tau, n_sym, fixed_paths=None, K_fixed=8):
-        """Features -> logits -> top-64 -> table [n_vec][64 + K_fixed][N].
-        Returns (table, mass)."""
+    def propose(self, W, perm, s, tau, n_sym, fixed_paths=None, K_fixed=8, fused=True, work=None):
+        """Features -> hidden layers -> top-64 of the logits -> table
+        [n_vec][64 + K_fixed][N].  Returns (table, mass).  fused: the last layer
+        and the top-64 in one pass that never writes the logits
+        (logits_top64); else the logits GEMM and topk64 (same result)."""
         n_sc = perm.shape[0]
         x = mlp_features(W, perm, s, tau, n_sym, kind=self.kind)
-        z = MLPFunction.forward(_NoCtx(), x, *self.p)
-        top, mass = topk64(z)
+        p = self.p
+        if fused and self.vocab.shape[0] % 128 == 0 and self.vocab.shape[0] >= 256:
+            h1 = gemm_bf16(x, p.W1, trans_b=True, bias=p.b1, relu=True, out_f32=False, out_bf16=True)
+            h2 = gemm_bf16(h1, p.W2, trans_b=True, bias=p.b2, relu=True, out_f32=False, out_bf16=True)
+            top, mass = logits_top64(h2, p.W3, p.b3, work=work)
+        else:
+            z = MLPFunction.forward(_NoCtx(), x, *p)
+            top, mass = topk64(z)
         table = learned_paths(self.vocab, top, fixed_paths, K_fixed if fixed_paths is not None else 0, n_sc, n_sym)
         return table, mass
 

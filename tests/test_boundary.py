@@ -266,6 +266,19 @@ def test_learned_argument_validation():
     assert lib.vp_learned_paths(P, 10, 4, P, 4000, P, 200, 200, 2, 14, P, None) == VP_EUNSUPPORTED
     assert lib.vp_learned_paths(P, 10, 4, P, 0, P, 8, 0, 2, 14, P, None) == VP_EINVAL     # empty table
     assert lib.vp_learned_paths(P, 10, 4, None, 64, P, 8, 8, 2, 14, P, None) == VP_EINVAL
+    # fused last layer + top-64: vocabulary a multiple of 128 in 256..4096,
+    # 16-byte aligned operands, a 256-byte aligned workspace, a bias
+    A = ctypes.c_void_p(4096)
+    assert lib.vp_logits_top64(A, 10, A, A, 200, A, None, A, None) == VP_EUNSUPPORTED
+    assert lib.vp_logits_top64(A, 10, A, A, 128, A, None, A, None) == VP_EUNSUPPORTED
+    assert lib.vp_logits_top64(A, 10, A, A, 4224, A, None, A, None) == VP_EUNSUPPORTED
+    assert lib.vp_logits_top64(A, -1, A, A, 4096, A, None, A, None) == VP_EINVAL
+    assert lib.vp_logits_top64(None, 0, None, None, 4096, None, None, None, None) == VP_OK
+    assert lib.vp_logits_top64(A, 10, A, None, 4096, A, None, A, None) == VP_EINVAL      # no bias
+    assert lib.vp_logits_top64(ctypes.c_void_p(4098), 10, A, A, 4096, A, None, A, None) == VP_EINVAL
+    assert lib.vp_logits_top64(A, 10, A, A, 4096, A, None, ctypes.c_void_p(4096 + 64), None) == VP_EINVAL
+    assert lib.vp_logits_top64_work_bytes(0) >= 0
+    assert lib.vp_logits_top64_work_bytes(1000) > 1000 * 2048
 
 
 def test_region_demap_device_code_matches_oracle_definition():
