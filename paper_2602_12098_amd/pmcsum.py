@@ -29,5 +29,46 @@ def summarize(db_path: str) -> str:
     return "\n".join(out)
 
 
+def valu_record(db_path: str, regex: str, vectors: int, sources) -> dict:
+    """Clock and VALU issue of one kernel from a run with SQ_INSTS_VALU and
+    GRBM_GUI_ACTIVE: the shader clock is GRBM_GUI_ACTIVE (summed over the 8
+    XCDs) / 8 over the dispatch's duration; VALU busy is SQ_INSTS_VALU x 4
+    cycles (a wave64 VALU instruction occupies a SIMD16 for 4 cycles) over
+    1024 SIMDs x those cycles."""
+    import hashlib
+    db = sqlite3.connect(db_path)
+    rows = db.execute("select kernel_name, dispatch_id, counter_name, sum(value), avg(duration) "
+                      "from counters_collection group by kernel_name, dispatch_id, counter_name").fetchall()
+    per = defaultdict(dict)
+    for kname, did, cname, val, d in rows:
+        if re.search(regex, kname):
+            per[did][cname] = val
+            per[did]["duration_ns"] = d
+    if not per:
+        raise SystemExit(f"no dispatch of /{regex}/ in {db_path}")
+    n = len(per)
+    mean = lambda c: sum(v[c] for v in per.values()) / n
+    dur = mean("duration_ns") * 1e-9
+    cycles = mean("GRBM_GUI_ACTIVE") / 8.0
+    valu = mean("SQ_INSTS_VALU")
+    h = hashlib.sha256()
+    for f in sources:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return {"kernel_regex": regex, "dispatches": n, "duration_us": dur * 1e6, "sclk_ghz": cycles / dur / 1e9,
+            "valu_instr": valu, "valu_busy": valu * 4.0 / (1024.0 * cycles),
+            "valu_instr_per_vector": valu / vectors, "vectors": vectors, "source_files": list(sources),
+            "source_sha256": h.hexdigest()}
+
+
 if __name__ == "__main__":
-    print(summarize(sys.argv[1]))
+    if len(sys.argv) > 2 and sys.argv[1] == "--valu-json":
+        # --valu-json OUT DB REGEX VECTORS SOURCE...
+        import json
+        out, db, regex, vec = sys.argv[2:6]
+        rec = valu_record(db, regex, int(vec), sys.argv[6:])
+        with open(out, "w") as f:
+            json.dump(rec, f, indent=1)
+        print(json.dumps(rec, indent=1))
+    else:
+        print(summarize(sys.argv[1]))

@@ -360,6 +360,35 @@ def test_shared_path_table_and_no_zero(vp):
     assert np.all(host(out.kidx) < 64)
 
 
+def test_path_order_does_not_change_the_result(vp):
+    # the search is a minimum over the path set (Alg. 2): shuffling the rows of
+    # every subcarrier's table leaves each vector's cost and perturbation as
+    # they are, and the chosen index follows the shuffle (equal costs of two
+    # different paths, where the smaller index decides, are counted and must
+    # be rare)
+    wl = vpgen.cfg3(512, n_sc=8)
+    K = 512
+    Hd, sd = _to_dev(wl.H), _to_dev(wl.s)
+    prep = vp.preprocess(Hd, wl.alpha)
+    paths = vp.paths_mop(prep.w2, K)
+    rng = np.random.default_rng(17)
+    shuf = np.stack([rng.permutation(K) for _ in range(wl.n_sc)])          # new row i = old row shuf[sc][i]
+    P = host(paths)
+    Ps = np.ascontiguousarray(np.take_along_axis(P, shuf[:, :, None], axis=1))
+    a = vp.search(prep.W, prep.perm, sd, wl.tau, paths, wl.n_sym)
+    b = vp.search(prep.W, prep.perm, sd, wl.tau, _to_dev(Ps), wl.n_sym)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(host(a.cost), host(b.cost))
+    la, lb = host(a.l), host(b.l)
+    ka, kb = host(a.kidx), host(b.kidx)
+    same = np.all(la == lb, axis=(0, 2))
+    assert same.mean() >= 0.999, same.mean()
+    sc = np.arange(wl.n_vec) // wl.n_sym
+    mapped = np.where(kb == K, K, shuf[sc, np.minimum(kb, K - 1)])
+    assert np.all(mapped[same] == ka[same])
+    record("path-order", ParityReport(n=int(wl.n_vec), exact=int(same.sum()), cost_ties=int((~same).sum())))
+
+
 def test_failed_subcarriers_and_degenerate_inputs(vp):
     rng = np.random.default_rng(3)
     N, n_sc, n_sym = 4, 6, 3
