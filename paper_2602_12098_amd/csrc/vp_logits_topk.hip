@@ -8,10 +8,13 @@
 //   pass 1  the vocabulary is split four ways by 32-row blocks (split q takes
 //           blocks b with b % 4 == q) and, inside a split, into 32 groups by
 //           the row within the block: 128 disjoint groups per row.  Every
-//           group's two largest logits are kept (256 distinct entries).
-//   bound   per row, the 64th largest of those 256 values: at least 64 logits
-//           are at or above it, so no logit below it is among the 64 largest.
-//           Also the row's maximum.
+//           group's two largest logits are kept (256 distinct entries) and
+//           stored as 16-bit truncated order keys.
+//   bound   per row, the value of the 64th largest of those 256 keys: a
+//           truncated key is never above its value's key, so at least 64
+//           logits are at or above it and no logit below it is among the 64
+//           largest.  Also the row's maximum (at the top of its truncation
+//           interval).
 //   pass 2  the logits again: sum of exp(z - max) per split, and every logit
 //           at or above the bound (or NaN) appended to the split's candidate
 //           list (about 65 per row on trained and on random logits).
@@ -27,7 +30,9 @@
 // k-steps summed in increasing order as the unfused GEMM does.  A wave keeps
 // the B fragments of its 64 rows of X (two 32-column tiles, k = 256) in
 // registers for the whole pass; the four waves of a workgroup share each
-// 32 x 256 vocabulary block through LDS, double-buffered.
+// 32 x 256 vocabulary block through a ring of four LDS slots, and each
+// matrix-core instruction runs beside one value of the previous block's
+// epilogue.
 #include <math.h>
 #include "vp_internal.hpp"
 #include "vp_learn.h"
