@@ -225,7 +225,47 @@ def bench_batched(vp, steps, warmup):
 
     ms_per_size_plain = timed(per_size)
     ms_per_size_shared = timed(lambda: per_size(64))
-    ms_per_size = min(ms_per_size_plain, ms_per_size_shared)
+    ms_per_size_eager = min(ms_per_size_plain, ms_per_size_shared)
+
+    # the same per-size launches without per-call host work: outputs allocated
+    # once, the whole sequence captured in one HIP graph and replayed (no
+    # library call in it clears memory with a memset)
+    def per_size_graph(min_K_sharing):
+        bufs = []
+        for H, sg, tau, alpha, K, _ in per:
+            prep = vp.preprocess(H, alpha)
+            share = min_K_sharing is not None and K >= min_K_sharing
+            order = torch.empty((H.shape[0], 2, K), dtype=torch.int16, device="cuda:0") if share else None
+            paths = vp.paths_mop(prep.w2, K, order=order)
+            o = vp.search(prep.W, prep.perm, sg, tau, paths, wl.n_sym, order=order)
+            x = vp.precode(prep.G, sg, o.l, tau, o.cost, wl.n_sym, P_T=1.0)
+            bufs.append((prep, order, paths, o, x))
+        eager_cost = [o.cost.clone() for _, _, _, o, _ in bufs]
+
+        def launches():
+            for (H, sg, tau, alpha, K, _), (prep, order, paths, o, x) in zip(per, bufs):
+                vp.preprocess(H, alpha, out=prep)
+                vp.paths_mop(prep.w2, K, out=paths, order=order)
+                vp.search(prep.W, prep.perm, sg, tau, paths, wl.n_sym, out=o, order=order)
+                vp.precode(prep.G, sg, o.l, tau, o.cost, wl.n_sym, P_T=1.0, out=x)
+
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            launches()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            launches()
+        ms = timed(g.replay)
+        same = all(torch.equal(c, o.cost) for c, (_, _, _, o, _) in zip(eager_cost, bufs))
+        del g
+        return ms, same
+
+    ms_graph_plain, same_plain = per_size_graph(None)
+    ms_graph_shared, same_shared = per_size_graph(64)
+    ms_per_size = min(ms_graph_plain, ms_graph_shared)
     num = den = 0.0
     for (H, sg, _, alpha, K, tau), (prep, o) in zip(per, per_size()):
         g, exact = gap_to_exact(vp, prep, sg, tau, wl.n_sym, o.cost)
@@ -234,7 +274,13 @@ def bench_batched(vp, steps, warmup):
     n_vec = b.n_vec
     res = {"workload": f"{wl.n_rbg} RBGs x {wl.sc_per_rbg} sc x {wl.n_sym} sym, U 4..16, QAM 4..256, M {wl.M}",
            "n_vec": n_vec, "K_by_U": kcal, "value": n_vec / (ms_tuned * 1e-3), "unit": "vectors/s",
-           "ms_graph_default": ms_default, "ms_graph_tuned": ms_tuned, "ms_per_size_launches": ms_per_size,
+           "ms_graph_default": ms_default, "ms_graph_tuned": ms_tuned,
+           "ms_per_size_launches": ms_per_size,
+           "per_size_reference": "the per-call API per (U, QAM) group, all launches captured in one HIP graph "
+                                 "(outputs preallocated), the faster of plain and prefix sharing for K >= 64",
+           "ms_per_size_graph_plain": ms_graph_plain, "ms_per_size_graph_prefix_sharing_K64": ms_graph_shared,
+           "per_size_graph_matches_eager": bool(same_plain and same_shared),
+           "ms_per_size_eager_python_loop": ms_per_size_eager,
            "ms_per_size_plain": ms_per_size_plain, "ms_per_size_prefix_sharing_K64": ms_per_size_shared,
            "per_size_launch_groups": len(per), "speedup_vs_per_size": ms_per_size / ms_tuned,
            "gap_db": 10 * math.log10(num / den), "tuning": info}
