@@ -36,33 +36,64 @@ __device__ __forceinline__ float row_xchg_f(float v, int step) {
     return __int_as_float(row_xchg_i(__float_as_int(v), step));
 }
 
-// Column c of W = Lbar^{-1}: W_rc = (delta_rc - sum_{c<=k<r} Lbar_rk W_kc) / Lbar_rr,
-// row r of Lbar being user perm[r]'s factor row Lc[perm[r]][.].
+// Row stride (in entries) of the channel staged in LDS: odd, so that the 16
+// rows a Gram step reads at once (one column k of every row j) fall in
+// distinct LDS banks instead of all in one for M a multiple of 16.
+__host__ __device__ constexpr int h_stride(int M) { return M | 1; }
+
+// W = Lbar^{-1} by forward substitution, W_rc = (delta_rc - sum_{c<=k<r}
+// Lbar_rk W_kc) / Lbar_rr, row r of Lbar being user perm[r]'s factor row
+// Lc[perm[r]][.], with the whole wave: lane c + 16 s holds W_rc for the rows
+// r = s + 4 q (q = 0..3) in registers and the steps k = 0..N-1 sweep the
+// rows: row k is complete after step k-1, is scaled by 1/Lbar_kk (the
+// reciprocal the factorisation formed, which also makes W_kk exactly that
+// reciprocal) and is handed to every lane of its column, which subtracts
+// Lbar_rk W_kc from its rows r > k.  Each W_rc takes the same operations in
+// the same order as a row-by-row substitution (k ascending from c), but the
+// chain of dependent steps is N long instead of N(N-1)/2.
 template <int NN>
-__device__ __forceinline__ void forward_column(int c, const int *sperm, const float2 (*Lc)[kMaxN + 1],
-                                               float2 (*Wl)[kMaxN + 1]) {
-    float2 w[NN];
+__device__ __forceinline__ void forward_all(const int *sperm, const float2 (*Lc)[kMaxN + 1], const float *linv,
+                                            float2 (*Wl)[kMaxN + 1]) {
+    static_assert(kMaxN == 16 && kT == 64, "lane c + 16 s holds rows s + 4 q of column c");
+    const int lane = threadIdx.x & 63;
+    const int c = lane & 15, s = lane >> 4;
+    float2 w[4];
+    int ur[4];
 #pragma unroll
-    for (int r = 0; r < NN; ++r) {
-        const int ur = sperm[r];
-        float re = (r == c) ? 1.f : 0.f, im = 0.f;
-#pragma unroll
-        for (int k = 0; k < r; ++k) {   // - Lbar_rk W_kc, k >= c
-            if (k >= c) {
-                const float2 a = Lc[ur][k], b = w[k];
-                re = fmaf(-a.x, b.x, fmaf(a.y, b.y, re));
-                im = fmaf(-a.x, b.y, fmaf(-a.y, b.x, im));
-            }
-        }
-        const float d = Lc[ur][r].x;
-        w[r] = (r < c) ? make_float2(0.f, 0.f) : make_float2(re / d, im / d);
+    for (int q = 0; q < 4; ++q) {
+        const int r = s + 4 * q;
+        w[q] = make_float2(r == c ? 1.f : 0.f, 0.f);
+        ur[q] = r < NN ? sperm[r] : 0;
     }
 #pragma unroll
-    for (int r = 0; r < NN; ++r) Wl[r][c] = w[r];
+    for (int k = 0; k < NN; ++k) {
+        const int qk = k >> 2, sk = k & 3;
+        if (s == sk) {   // row k is complete: W_kc = acc / Lbar_kk (0 above the diagonal)
+            const float di = linv[k];
+            w[qk] = (k < c) ? make_float2(0.f, 0.f) : make_float2(w[qk].x * di, w[qk].y * di);
+        }
+        // W_kc from lane c + 16 sk, register qk (the same register in every lane)
+        const int src = c + 16 * sk;
+        const float2 b = make_float2(__shfl(w[qk].x, src), __shfl(w[qk].y, src));
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int r = s + 4 * q;
+            if (r > k && r < NN && k >= c) {   // - Lbar_rk W_kc
+                const float2 a = Lc[ur[q]][k];
+                w[q].x = fmaf(-a.x, b.x, fmaf(a.y, b.y, w[q].x));
+                w[q].y = fmaf(-a.x, b.y, fmaf(-a.y, b.x, w[q].y));
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int r = s + 4 * q;
+        if (r < NN && c < NN) Wl[r][c] = w[q];
+    }
 }
 
 // One subcarrier: Hs its [N][M] channel; Wsc, w2sc, permsc, Gsc (or NULL),
-// status_sc its outputs; sH: LDS for N * M channel entries.
+// status_sc its outputs; sH: LDS for N rows of h_stride(M) channel entries.
 // sorted = false: no pivoting, users in their own order (the unsorted
 // factorisation the sorted one is compared with in Sec. III-B).
 __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, int N, int M, float alpha,
@@ -73,15 +104,17 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     __shared__ float2 Lc[kMaxN][kMaxN + 1];   // Lc[u][k]: user u's entry of factor column k
     __shared__ float2 Wl[kMaxN][kMaxN + 1];   // W = Lbar^{-1}, search order
     __shared__ int sperm[kMaxN];
+    __shared__ float slinv[kMaxN];            // 1 / Lbar_kk of step k
 
     const int t = threadIdx.x;
     const int NM = N * M;
     const int NN = N * N;
+    const int HS = h_stride(M);
 
     int bad = 0;
     for (int idx = t; idx < NM; idx += kT) {
         const float2 h = Hs[idx];
-        sH[idx] = h;
+        sH[(idx / M) * HS + idx % M] = h;
         bad |= !(isfinite(h.x) && isfinite(h.y));
     }
     int st = __any(bad) ? VP_STATUS_NONFINITE : VP_STATUS_OK;   // the same in every lane
@@ -104,7 +137,7 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
             float re = 0.f, im = 0.f;
 #pragma unroll 8
             for (int k = 0; k < M; ++k) {   // A_ij = sum_k H_ik conj(H_jk)
-                const float2 a = sH[i * M + k], b = sH[j * M + k];
+                const float2 a = sH[i * HS + k], b = sH[j * HS + k];
                 re = fmaf(a.x, b.x, fmaf(a.y, b.y, re));
                 im = fmaf(a.y, b.x, fmaf(-a.x, b.y, im));
             }
@@ -128,12 +161,16 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     // users only.  The workgroup is one wave, so the barrier that ends a step
     // costs only the wait for its LDS writes.
     uint32_t rem = (N >= 32) ? ~0u : (1u << N) - 1u;   // users not yet pivoted (the same in every lane)
+    // lane t < N keeps user t's Schur diagonal in a register, updated with the
+    // very operations of the lane that holds S_tt, so that a step's pivot
+    // search needs no LDS read
+    float dg = t < N ? S[t][t].x : 0.f;
     for (int step = 0; step < N; ++step) {
         // smallest remaining Schur diagonal, ties to the smaller user, over the
         // 16 lanes of row 0 (N <= 16); a NaN diagonal (only from non-finite or
         // overflowing input, which fails the subcarrier) never beats a number
         const bool cand = (t < N) && ((rem >> t) & 1u);
-        float d = cand ? S[t][t].x : 0.f;
+        float d = cand ? dg : 0.f;
         int u = cand ? t : 0x7fffffff;
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -148,13 +185,14 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         d = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(d)));
         if (!sorted) {   // the next user in order, whatever its Schur diagonal
             p = step;
-            d = S[step][step].x;
+            d = __shfl(dg, step);
         }
         if (!(d > floor_) && st == VP_STATUS_OK) st = VP_STATUS_NOT_PD;
         if (t == 0) sperm[step] = p;
         rem &= ~(1u << p);
         const float lpp = sqrtf(fmaxf(d, 0.f));
         const float inv = lpp > 0.f ? 1.0f / lpp : 0.f;   // L_up = S_up / L_pp
+        if (t == 0) slinv[step] = inv;
         // every read of the step first (rows beyond N read row 0: discarded),
         // so that they overlap, then the arithmetic, then the writes
         const int tr = t < N ? t : 0;
@@ -171,8 +209,13 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
             for (int q = 0; q < kPer; ++q) sj[q] = S[ej[q]][p];
         }
         if (t < N) {
-            if (t == p) Lc[t][step] = make_float2(lpp, 0.f);
-            else if ((rem >> t) & 1u) Lc[t][step] = make_float2(st_.x * inv, st_.y * inv);
+            if (t == p) {
+                Lc[t][step] = make_float2(lpp, 0.f);
+            } else if ((rem >> t) & 1u) {
+                const float2 a = make_float2(st_.x * inv, st_.y * inv);
+                Lc[t][step] = a;
+                dg = fmaf(-a.x, a.x, fmaf(-a.y, a.y, dg));   // S_tt -= |L_t|^2, as the update below forms it
+            }
         }
 #pragma unroll
         for (int q = 0; q < kPer; ++q) {   // S_ij -= L_i conj(L_j)
@@ -203,17 +246,14 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         return;
     }
 
-    // W = Lbar^{-1}: lane c solves Lbar x = e_c by forward substitution,
-    // its column held in registers.
-    if (t < N) {
-        switch (N) {
+    // W = Lbar^{-1} (forward substitution by the whole wave)
+    switch (N) {
 #define VP_CASE(n) \
-    case n: forward_column<n>(t, sperm, Lc, Wl); break;
-            VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
-            VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
+    case n: forward_all<n>(sperm, Lc, slinv, Wl); break;
+        VP_CASE(1) VP_CASE(2) VP_CASE(3) VP_CASE(4) VP_CASE(5) VP_CASE(6) VP_CASE(7) VP_CASE(8)
+        VP_CASE(9) VP_CASE(10) VP_CASE(11) VP_CASE(12) VP_CASE(13) VP_CASE(14) VP_CASE(15) VP_CASE(16)
 #undef VP_CASE
-            default: break;
-        }
+        default: break;
     }
     __syncthreads();
 
@@ -256,7 +296,7 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
             float re = 0.f, im = 0.f;
 #pragma unroll 8
             for (int v = 0; v < N; ++v) {
-                const float2 h = sH[v * M + m], a = S[v][u];
+                const float2 h = sH[v * HS + m], a = S[v][u];
                 re = fmaf(h.x, a.x, fmaf(h.y, a.y, re));
                 im = fmaf(h.x, a.y, fmaf(-h.y, a.x, im));
             }
@@ -270,7 +310,7 @@ __global__ __launch_bounds__(kT) void k_preprocess(const float2 *__restrict__ H,
                                                    float2 *__restrict__ Wout, float *__restrict__ w2out,
                                                    uint8_t *__restrict__ perm_out, float2 *__restrict__ Gout,
                                                    int32_t *__restrict__ status_out, int sorted) {
-    extern __shared__ float2 sH[];   // [N * M]
+    extern __shared__ float2 sH[];   // [N][h_stride(M)]
     const size_t sc = blockIdx.x;
     const size_t NM = (size_t)N * M;
     preprocess_one(H + sc * NM, N, M, alpha, Wout + sc * VP_PACKED(N), w2out + sc * N, perm_out + sc * N,
@@ -283,7 +323,7 @@ __global__ __launch_bounds__(kT) void k_batch_preprocess(const BatchGroup *__res
                                                          const float2 *__restrict__ H, float2 *__restrict__ W,
                                                          float *__restrict__ w2, uint8_t *__restrict__ perm,
                                                          float2 *__restrict__ G, int32_t *__restrict__ status) {
-    extern __shared__ float2 sH[];   // [kMaxN * M]
+    extern __shared__ float2 sH[];   // [kMaxN][h_stride(M)]
     const int sc = blockIdx.x;
     const BatchGroup g = groups[sc_group[sc]];
     const long long j = sc - g.sc0;
@@ -298,7 +338,7 @@ int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, i
                             const float2 *H, float2 *W, float *w2, uint8_t *perm, float2 *G, int32_t *status,
                             hipStream_t st) {
     if (n_sc_total == 0) return VP_OK;
-    hipLaunchKernelGGL(k_batch_preprocess, dim3(n_sc_total), dim3(kT), (size_t)kMaxN * M * sizeof(float2), st, groups,
+    hipLaunchKernelGGL(k_batch_preprocess, dim3(n_sc_total), dim3(kT), (size_t)kMaxN * h_stride(M) * sizeof(float2), st, groups,
                        sc_group, M, H, W, w2, perm, G, status);
     return launch_status();
 }
@@ -306,7 +346,7 @@ int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, i
 int launch_preprocess(const float2 *H, int n_sc, int N, int M, float alpha, float2 *W, float *w2,
                       uint8_t *perm, float2 *G, int32_t *status, hipStream_t st, bool sorted) {
     if (n_sc == 0) return VP_OK;
-    hipLaunchKernelGGL(k_preprocess, dim3(n_sc), dim3(kT), (size_t)N * M * sizeof(float2), st, H, N, M, alpha, W, w2,
+    hipLaunchKernelGGL(k_preprocess, dim3(n_sc), dim3(kT), (size_t)N * h_stride(M) * sizeof(float2), st, H, N, M, alpha, W, w2,
                        perm, G, status, sorted ? 1 : 0);
     return launch_status();
 }
