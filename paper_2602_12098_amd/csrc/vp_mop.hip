@@ -343,6 +343,10 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int n_
 
 // Exclusive scan of one value per thread across the workgroup; returns the
 // prefix and writes the total to *total.
+// With FENCE = false the closing barrier (which lets the next scan reuse
+// `scratch`) is left out: the caller then alternates two scratch buffers and
+// has a barrier of its own between two scans on the same one.
+template <bool FENCE = true>
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratch, uint32_t *total) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t incl = wave_scan_incl(v);
@@ -356,7 +360,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratc
         tot += x;
     }
     *total = tot;
-    __syncthreads();
+    if (FENCE) __syncthreads();
     return base + incl - v;
 }
 
@@ -499,6 +503,29 @@ __device__ double product_set_bound(const double *w, int N, int K) {
     return U;
 }
 
+// A cheaper bound of the same kind when K <= 2^N: the box with limit 1 on
+// the m = ceil(log2 K) levels of smallest weight holds 2^m >= K vectors, so
+// the K-th smallest M is at most the sum of those m weights.  One step for
+// the whole wave instead of the greedy's chain of dependent ones; looser (it
+// never raises a limit to 2), which only widens the counting grid.  Wave 0
+// only (all 64 lanes active); returns the bound in every lane.
+__device__ double smallest_weights_bound(const double *w, int N, int m) {
+    const int lane = threadIdx.x & 63;
+    double x = 0.0;
+    if (lane < N) {
+        const double wl = w[lane];
+        int rank = 0;   // position of this level among the weights (ties: smaller level first)
+        for (int j = 0; j < N; ++j) {
+            const double wj = w[j];
+            rank += (wj < wl || (wj == wl && j < lane)) ? 1 : 0;
+        }
+        x = rank < m ? wl : 0.0;
+    }
+#pragma unroll
+    for (int off = 1; off < 16; off <<= 1) x += __shfl_xor(x, off);   // levels live in lanes 0..15
+    return __shfl(x, 0);
+}
+
 template <int CAP>
 struct ThrSmem {
     // fm and fw, adjacent, first hold the counting recursion's two buffers
@@ -510,6 +537,7 @@ struct ThrSmem {
     double w[kMaxN];
     int dtab[kMaxN][9];           // bin shifts of the counting recursion
     uint32_t scan[kT / 64];
+    uint32_t lscan[2][kT / 64];   // the enumeration's scans, alternating by level
     int best;
     double ubound;
 
@@ -550,7 +578,9 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     // K-th smallest is typically U / 2.5), and the guaranteed [0, 1.25 U] only
     // when that one never reaches K.
     if (t < 64) {
-        const double U0 = product_set_bound(S.w, N, K);
+        int m = 0;   // ceil(log2 K)
+        while ((1 << m) < K) ++m;
+        const double U0 = m <= N ? smallest_weights_bound(S.w, N, m) : product_set_bound(S.w, N, K);
         if (t == 0) S.ubound = U0;
     }
     __syncthreads();
@@ -599,7 +629,10 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             }
         }
         uint32_t total;
-        uint32_t off = block_scan_excl(cnt, S.scan, &total);   // also a barrier: all reads done
+        // (its barrier also orders this level's frontier reads before the
+        // children's writes; the barrier closing the level separates two
+        // scans on one buffer)
+        uint32_t off = block_scan_excl<false>(cnt, S.lscan[l & 1], &total);
         if (total > (uint32_t)CAP) {
             fail = true;
             break;
