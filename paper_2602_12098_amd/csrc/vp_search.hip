@@ -197,31 +197,51 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const uint8_t *P = paths + (size_t)sc * pstride;
     const uint16_t *LX = order + (size_t)sc * 2 * K;        // lexicographic
     const uint16_t *SX = LX + K;                            // deepest level most significant
+    // every global read of the set-up is issued here, before the first
+    // barrier: the start residuals (W, perm and s), the table, and both orders
+    // (the deepest-level-first positions t + kTB it are the ones the tier words
+    // below take, kept in registers)
+    {   // start residuals: thread (h, i) for vector h, level i
+        const int h = t / kTT, i = t % kTT;
+        if (i < N && h < nlive)
+            s_r0[h][i] = stilde_over_tau<N>(Wc, perm + (size_t)sc * N, s, vbase + h, n_vec, i, 1.0f / tau);
+    }
     if (t < N) {
         s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
         s_nlinv[t] = -(1.0f / s_wdiag[t]);
         s_perm[t] = perm[(size_t)sc * N + t];
     }
-    for (int j = t; j < K; j += kTB) {
+    constexpr int kPre = 2;   // deepest-level-first positions t + kTB it, it < kPre, read here
+    int sx[kPre];
+#pragma unroll
+    for (int it = 0; it < kPre; ++it) sx[it] = 0;
+    for (int j = t, it = 0; j < K; j += kTB, ++it) {
         int k = LX[j];
         k = k < K ? k : K - 1;   // a corrupt order must not index out of bounds
         s_k[j] = (uint16_t)k;
         s_words[j] = load_word<N>(P, j);
+        if (it < kPre) {
+            k = SX[j];
+            k = k < K ? k : K - 1;
+            if (it == 0) sx[0] = k;
+            else sx[1] = k;
+        }
     }
     __syncthreads();
-    {   // start residuals: thread (h, i) for vector h, level i
-        const int h = t / kTT, i = t % kTT;
-        if (i < N && h < nlive) s_r0[h][i] = stilde_over_tau<N>(Wc, s_perm, s, vbase + h, n_vec, i, 1.0f / tau);
-    }
     // stage-2 tier words: batch b holds the paths at positions [32 b, 32 b + 32)
     // of the deepest-level-first order; OR of their per-level rank thermometers
-    static_assert(kBatch == 32, "a batch is one half of a wave");
-    for (int b0 = 0; b0 < NB; b0 += kTB / kBatch) {
-        const int b = b0 + t / kBatch, q = b * kBatch + t % kBatch;
+    static_assert(kBatch == 32 && kTB % kBatch == 0, "a batch is one half of a wave");
+    for (int b0 = 0, it = 0; b0 < NB; b0 += kTB / kBatch, ++it) {
+        const int b = b0 + t / kBatch, q = b * kBatch + t % kBatch;   // q = t + kTB it
         unsigned long long w = 0ull;
         if (q < K) {
-            int k = SX[q];
-            k = k < K ? k : K - 1;
+            int k;
+            if (it < kPre) {
+                k = it == 0 ? sx[0] : sx[1];
+            } else {
+                k = SX[q];
+                k = k < K ? k : K - 1;
+            }
             w = s_words[k];
         }
         const uint32_t lo = half_wave_or(rank_tiers32((uint32_t)w));
