@@ -4,8 +4,12 @@
 // One wave (a 64-thread workgroup) per subcarrier, so that no step needs a
 // workgroup barrier: the N x N Gram matrix lives in LDS, each lane updating
 // up to four entries, and the channel rows are staged in dynamically sized
-// LDS (N x M), which keeps a workgroup at about 9 KiB for 16 x 16 and lets a
-// CU hold all its subcarriers at once.  Alg. 1's sorted Gram-Schmidt on the rows of
+// LDS (N rows of an odd stride >= M), which keeps a workgroup at about 9 KiB
+// for 16 x 16 and lets a CU hold all its subcarriers at once.  The kernel is a
+// chain of dependent steps per wave with every subcarrier's wave resident
+// from the start, so its time is that chain's length: LDS accesses are laid
+// out free of bank conflicts, the forward substitution runs on all 64 lanes,
+// and the pivot search reads registers.  Alg. 1's sorted Gram-Schmidt on the rows of
 // [H, lambda I] is carried out in its equivalent Cholesky form: the squared
 // row norms that Alg. 1 downdates are exactly the Schur-complement diagonals
 // of A = H H^H + lambda^2 I, so the pivot is the smallest remaining one and the
