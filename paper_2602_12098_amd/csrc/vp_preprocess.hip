@@ -161,9 +161,8 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     for (int u = 0; u < N; ++u) floor_ = fmaxf(floor_, S[u][u].x);
     floor_ *= (float)N * 1.1920929e-7f;
 
-    // Column p of S is only read during step p: the update touches remaining
-    // users only.  The workgroup is one wave, so the barrier that ends a step
-    // costs only the wait for its LDS writes.
+    // Column p of S is only read during step p.  The workgroup is one wave,
+    // so the barrier that ends a step costs only the wait for its LDS writes.
     uint32_t rem = (N >= 32) ? ~0u : (1u << N) - 1u;   // users not yet pivoted (the same in every lane)
     // lane t < N keeps user t's Schur diagonal in a register, updated with the
     // very operations of the lane that holds S_tt, so that a step's pivot
@@ -173,20 +172,18 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         // smallest remaining Schur diagonal, ties to the smaller user, over the
         // 16 lanes of row 0 (N <= 16); a NaN diagonal (only from non-finite or
         // overflowing input, which fails the subcarrier) never beats a number
+        // (the minimum over the row by four DPP moves -- fminf returns the
+        // number when one operand is NaN -- then the smallest candidate lane
+        // that holds it; with only NaN left, the first candidate, whose NaN
+        // then fails the subcarrier below)
         const bool cand = (t < N) && ((rem >> t) & 1u);
-        float d = cand ? dg : 0.f;
-        int u = cand ? t : 0x7fffffff;
+        float d = cand ? dg : __int_as_float(0x7f800000);
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const float od = row_xchg_f(d, s);
-            const int ou = row_xchg_i(u, s);
-            const bool ovalid = ou != 0x7fffffff, valid = u != 0x7fffffff;
-            const bool take = ovalid & ((!valid) | (od < d) | ((od == d) & (ou < u)));
-            d = take ? od : d;
-            u = take ? ou : u;
-        }
-        int p = __builtin_amdgcn_readfirstlane(u);
+        for (int s = 0; s < 4; ++s) d = fminf(d, row_xchg_f(d, s));
         d = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(d)));
+        const unsigned long long at_min = __ballot(cand && dg == d);
+        int p = (int)__builtin_ctzll(at_min ? at_min : __ballot(cand));
+        d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(dg), p));
         if (!sorted) {   // the next user in order, whatever its Schur diagonal
             p = step;
             d = __shfl(dg, step);
@@ -221,17 +218,19 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
                 dg = fmaf(-a.x, a.x, fmaf(-a.y, a.y, dg));   // S_tt -= |L_t|^2, as the update below forms it
             }
         }
+        // S_ij -= L_i conj(L_j) on every entry: an entry of a pivoted row or
+        // column becomes garbage, but such entries only ever feed others of
+        // their kind (column p is read at step p for the rows of the entries
+        // it updates), so no remaining entry, L column or pivot sees them
 #pragma unroll
-        for (int q = 0; q < kPer; ++q) {   // S_ij -= L_i conj(L_j)
+        for (int q = 0; q < kPer; ++q) {
             const int i = ei[q], j = ej[q];
             const float2 a = make_float2(si[q].x * inv, si[q].y * inv), b = make_float2(sj[q].x * inv, sj[q].y * inv);
             float2 v = sv[q];
             v.x = fmaf(-a.x, b.x, fmaf(-a.y, b.y, v.x));
             v.y = fmaf(-a.y, b.x, fmaf(a.x, b.y, v.y));
-            if (i < N && ((rem >> i) & 1u) && ((rem >> j) & 1u)) {
-                sv[q] = v;
-                S[i][j] = v;
-            }
+            sv[q] = v;
+            if (i < N) S[i][j] = v;
         }
         __syncthreads();
     }
@@ -278,16 +277,14 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
     }
     __syncthreads();
 
-    for (int idx = t; idx < NP; idx += kT) {   // packed column-major lower
-        int c = 0, rem_ = idx;
-        while (rem_ >= N - c) {
-            rem_ -= N - c;
-            ++c;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {   // this lane's entries (i, j) of W, i >= j, packed column-major lower
+        const int i = ei[q], j = ej[q];
+        if (i < N && i >= j) {
+            float2 v = Wl[i][j];
+            if (i == j) v.y = 0.f;
+            Wsc[j * N - (j * (j - 1)) / 2 + (i - j)] = v;
         }
-        const int r = c + rem_;
-        float2 v = Wl[r][c];
-        if (r == c) v.y = 0.f;
-        Wsc[idx] = v;
     }
     if (t < N) {
         const float dg = Wl[t][t].x;
@@ -295,8 +292,10 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
         permsc[t] = (uint8_t)sperm[t];
     }
     if (Gsc) {   // G[m][u] = sum_v conj(H_vm) Ainv_vu
+        // (m, u) of idx = t + kT it, stepped without a division per entry
+        const int dm = kT / N, du = kT % N;
+        int m = t / N, u = t % N;
         for (int idx = t; idx < NM; idx += kT) {
-            const int m = idx / N, u = idx % N;
             float re = 0.f, im = 0.f;
 #pragma unroll 8
             for (int v = 0; v < N; ++v) {
@@ -305,6 +304,12 @@ __device__ __forceinline__ void preprocess_one(const float2 *__restrict__ Hs, in
                 im = fmaf(h.x, a.y, fmaf(-h.y, a.x, im));
             }
             Gsc[idx] = make_float2(re, im);
+            m += dm;
+            u += du;
+            if (u >= N) {
+                u -= N;
+                ++m;
+            }
         }
     }
     if (t == 0) *status_sc = st;
