@@ -241,66 +241,129 @@ __global__ __launch_bounds__(64) void k_features(const float2 *__restrict__ W, c
 //   [48+i]  W_ii^2 (d1_i - d0_i) / mean W_jj^2, d0 / d1 the squared distances
 //           of c_i to its nearest and second-nearest box points (the PED cost,
 //           in units of tau^2, of taking rank 1 instead of rank 0 at level i)
+// Four lanes per vector (lane q: levels q, q + 4, q + 8, q + 12), sixteen
+// vectors per wave: every lane keeps its levels' residuals in registers, the
+// lane of level k decides b_k and hands it to the other lanes of its vector,
+// which update their residuals below k; each lane writes its levels' four
+// features.  The operations of each level (and the mean weights, summed in
+// level order) are exactly those of a one-thread-per-vector walk, with a chain
+// N steps long and four times the lanes in flight.
+constexpr int kFeatLPV = 4;                 // lanes per vector
+constexpr int kFeatVPB = 256 / kFeatLPV;    // vectors per 256-thread workgroup
+
 template <int N>
-__global__ __launch_bounds__(64) void k_features_walk(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
-                                                      const float2 *__restrict__ s, float tau, int n_sc, int n_sym,
-                                                      uint16_t *__restrict__ feat) {
+__global__ __launch_bounds__(256) void k_features_walk(const float2 *__restrict__ W, const uint8_t *__restrict__ perm,
+                                                       const float2 *__restrict__ s, float tau, int n_sc, int n_sym,
+                                                       uint16_t *__restrict__ feat) {
+    constexpr int T = (N + kFeatLPV - 1) / kFeatLPV;   // levels per lane
+    __shared__ float s_wd[kFeatVPB][16];
     constexpr int NP = VP_PACKED(N);
     const size_t n_vec = (size_t)n_sc * n_sym;
-    const size_t v = (size_t)blockIdx.x * 64 + threadIdx.x;
-    if (v >= n_vec) return;
+    const int vl = threadIdx.x / kFeatLPV, q = threadIdx.x % kFeatLPV;
+    const size_t v0 = (size_t)blockIdx.x * kFeatVPB + vl;
+    const bool live = v0 < n_vec;
+    const size_t v = live ? v0 : n_vec - 1;   // dead lanes shadow the last vector (no writes)
     const int sc = (int)(v / n_sym);
     const float2 *Wc = W + (size_t)sc * NP;
     const uint8_t *pm = perm + (size_t)sc * N;
-    uint16_t *f = feat + v * 64;
-    float wd[N], mean = 0.f, wmean = 0.f;
-    for (int i = 0; i < N; ++i) {
-        wd[i] = Wc[vp_pidx(N, i, i)].x;
-        mean += wd[i];
-        wmean += wd[i] * wd[i];
+    const int src0 = (threadIdx.x & 63) & ~(kFeatLPV - 1);   // lane of level 0 of this vector, within the wave
+    float wdv[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int i = q + kFeatLPV * t;
+        wdv[t] = i < N ? Wc[vp_pidx(N, i < N ? i : 0, i < N ? i : 0)].x : 0.f;
+    }
+#pragma unroll
+    for (int t = 0; t < 16 / kFeatLPV; ++t) s_wd[vl][q + kFeatLPV * t] = t < T ? wdv[t < T ? t : 0] : 0.f;
+    __syncthreads();
+    float mean = 0.f, wmean = 0.f;   // in level order, as a sequential loop forms them
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const float w = s_wd[vl][j];
+        mean += w;
+        wmean += w * w;
     }
     mean /= N;
     wmean /= N;
-    const bool ok = (wd[0] > 0.f) && isfinite(wd[0]) && (mean > 0.f) && isfinite(mean) && isfinite(wmean);
+    const float wd0 = s_wd[vl][0];
+    const bool ok = (wd0 > 0.f) && isfinite(wd0) && (mean > 0.f) && isfinite(mean) && isfinite(wmean);
+    uint16_t *f = feat + v * 64;
     if (!ok) {
-        for (int i = 0; i < 64; ++i) f[i] = 0;
-        return;
+        if (live)
+#pragma unroll
+            for (int t = 0; t < 16 / kFeatLPV; ++t) {
+                const int i = q + kFeatLPV * t;
+                f[i] = f[16 + i] = f[32 + i] = f[48 + i] = 0;
+            }
+        return;   // the same for all lanes of the vector
     }
     const float inv_tau = 1.0f / tau;
-    float2 r[N];
-    for (int i = 0; i < N; ++i) {
+    float2 r[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) {
+        const int i = q + kFeatLPV * t;
         float re = 0.f, im = 0.f;
-        for (int j = 0; j <= i; ++j) {
-            const float2 w = Wc[vp_pidx(N, i, j)];
-            const int u = pm[j] < N ? pm[j] : N - 1;
-            const float2 x = s[(size_t)u * n_vec + v];
-            re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
-            im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+        if (i < N) {
+#pragma unroll
+            for (int j = 0; j < N; ++j) {
+                if (j <= i) {
+                    const float2 w = Wc[vp_pidx(N, i, j)];
+                    const int u = pm[j] < N ? pm[j] : N - 1;
+                    const float2 x = s[(size_t)u * n_vec + v];
+                    re = fmaf(w.x, x.x, fmaf(-w.y, x.y, re));
+                    im = fmaf(w.x, x.y, fmaf(w.y, x.x, im));
+                }
+            }
         }
-        r[i] = make_float2(re * inv_tau, im * inv_tau);
+        r[t] = make_float2(re * inv_tau, im * inv_tau);
     }
-    for (int i = 0; i < N; ++i) {
-        // the centre as the search's walk forms it: cp = c - 1/2 in one fma
-        const float nlinv = -(1.0f / wd[i]);
-        const float cpx = fmaf(r[i].x, nlinv, -0.5f), cpy = fmaf(r[i].y, nlinv, -0.5f);
-        const float cx = r[i].x * nlinv, cy = r[i].y * nlinv;
-        float a, b, a1, b1;
-        vp_demap0(cpx, cpy, a, b);
-        vp_demap1(cpx, cpy, cx, cy, 1, a1, b1);
-        const float ex = cx - a, ey = cy - b;
-        const float fx = cx - a1, fy = cy - b1;
-        const float d0 = ex * ex + ey * ey, d1 = fx * fx + fy * fy;
-        f[i] = f2bf(wd[i] / mean);
-        f[16 + i] = f2bf(ex);
-        f[32 + i] = f2bf(ey);
-        f[48 + i] = f2bf(wd[i] * wd[i] * (d1 - d0) / wmean);
-        for (int m = i + 1; m < N; ++m) {
-            const float2 w = Wc[vp_pidx(N, m, i)];
-            r[m].x = fmaf(w.x, a, fmaf(-w.y, b, r[m].x));
-            r[m].y = fmaf(w.x, b, fmaf(w.y, a, r[m].y));
+    float fa[T], fx[T], fy[T], fd[T];
+#pragma unroll
+    for (int t = 0; t < T; ++t) fa[t] = fx[t] = fy[t] = fd[t] = 0.f;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        constexpr int L = kFeatLPV;
+        const int tk = k / L;
+        // level k's lane: the centre as the search's walk forms it
+        // (cp = c - 1/2 in one fma), its nearest and second-nearest box points
+        float a = 0.f, b = 0.f;
+        if (q == k % L) {
+            const float wdk = wdv[tk];
+            const float nlinv = -(1.0f / wdk);
+            const float cpx = fmaf(r[tk].x, nlinv, -0.5f), cpy = fmaf(r[tk].y, nlinv, -0.5f);
+            const float cx = r[tk].x * nlinv, cy = r[tk].y * nlinv;
+            float a1, b1;
+            vp_demap0(cpx, cpy, a, b);
+            vp_demap1(cpx, cpy, cx, cy, 1, a1, b1);
+            const float ex = cx - a, ey = cy - b;
+            const float gx = cx - a1, gy = cy - b1;
+            const float d0 = ex * ex + ey * ey, d1 = gx * gx + gy * gy;
+            fa[tk] = wdk / mean;
+            fx[tk] = ex;
+            fy[tk] = ey;
+            fd[tk] = wdk * wdk * (d1 - d0) / wmean;
+        }
+        a = __shfl(a, src0 + k % L);
+        b = __shfl(b, src0 + k % L);
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const int i = q + L * t;
+            if (i > k && i < N) {
+                const float2 w = Wc[vp_pidx(N, i, k)];
+                r[t].x = fmaf(w.x, a, fmaf(-w.y, b, r[t].x));
+                r[t].y = fmaf(w.x, b, fmaf(w.y, a, r[t].y));
+            }
         }
     }
-    for (int i = N; i < 16; ++i) f[i] = f[16 + i] = f[32 + i] = f[48 + i] = 0;
+    if (live)
+#pragma unroll
+        for (int t = 0; t < 16 / kFeatLPV; ++t) {
+            const int i = q + kFeatLPV * t;
+            f[i] = f2bf(t < T ? fa[t < T ? t : 0] : 0.f);
+            f[16 + i] = f2bf(t < T ? fx[t < T ? t : 0] : 0.f);
+            f[32 + i] = f2bf(t < T ? fy[t < T ? t : 0] : 0.f);
+            f[48 + i] = f2bf(t < T ? fd[t < T ? t : 0] : 0.f);
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -645,7 +708,8 @@ int launch_features(const float2 *W, const uint8_t *perm, const float2 *s, float
 #define VP_CASE(n)                                                                                           \
     case n:                                                                                                  \
         if (kind == VP_FEAT_RANK0_WALK)                                                                      \
-            hipLaunchKernelGGL(k_features_walk<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, feat); \
+            hipLaunchKernelGGL(k_features_walk<n>, dim3((unsigned)((n_vec + kFeatVPB - 1) / kFeatVPB)),        \
+                               dim3(kFeatLPV * kFeatVPB), 0, st, W, perm, s, tau, n_sc, n_sym, feat);      \
         else                                                                                                 \
             hipLaunchKernelGGL(k_features<n>, g, dim3(64), 0, st, W, perm, s, tau, n_sc, n_sym, feat);      \
         break;
