@@ -309,7 +309,8 @@ def bench_learned(vp, steps, warmup, wl, H, s, K_mop=64):
         if ev: ev[1].record()
         paths = vp.paths_mop(prep.w2, K_mop)
         if ev: ev[2].record()
-        table, mass = prop.propose(prep.W, prep.perm, s, wl.tau, n_sym, fixed_paths=paths, K_fixed=K_mop)
+        table, _ = prop.propose(prep.W, prep.perm, s, wl.tau, n_sym, fixed_paths=paths, K_fixed=K_mop,
+                                with_mass=False)
         if ev: ev[3].record()
         o = vp.search(prep.W, prep.perm, s, tau, table, n_sym, flags=vp.VP_INCLUDE_ZERO | vp.VP_PATHS_PER_VECTOR)
         if ev: ev[4].record()

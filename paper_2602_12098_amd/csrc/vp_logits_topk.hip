@@ -89,18 +89,23 @@ __device__ __forceinline__ void epi_one(PassState<MODE> &st, const f32x16 (&acc)
         // arithmetic is not moved away from the matrix-core instruction it
         // is meant to run beside
         asm volatile("" : "+v"(st.m1[u][r]), "+v"(st.m2[u][r]));
-    } else {
+    } else if (MODE == 1) {
         const float z = acc[u][r] + bb[r];
         st.esum[u] += __builtin_amdgcn_exp2f(fmaf(z, kLog2e, st.off[u]));
         cm[u] |= (!(z < st.T[u]) ? 1u : 0u) << r;
         asm volatile("" : "+v"(st.esum[u]), "+v"(cm[u]));
+    } else {   // pass 2 without the softmax mass: the candidates only
+        const float z = acc[u][r] + bb[r];
+        cm[u] |= (!(z < st.T[u]) ? 1u : 0u) << r;
+        asm volatile("" : "+v"(cm[u]));
     }
 }
 
 // Appends the marked logits of block m to the row's list for split q.  A lane
 // with candidates stages its 16 logits of the tile in LDS and loops over its
 // set bits only (candidates are about 2 % of the logits).
-__device__ __forceinline__ void epi_append(const PassState<1> &st, const f32x16 (&acc)[2], const float (&bb)[16],
+template <int MODE>
+__device__ __forceinline__ void epi_append(const PassState<MODE> &st, const f32x16 (&acc)[2], const float (&bb)[16],
                                            const uint32_t (&cm)[2], int m, int q, int h, int rbase, int j, int wv,
                                            int *s_cnt, float *zst, uint2 *__restrict__ cand) {
     const int c0 = 32 * (q + kNQ * m) + 4 * h;
@@ -211,7 +216,7 @@ __device__ __forceinline__ void pass_block(int m, int nb, int q, int t, int h, i
         epi_one<MODE>(st, acc_prev, bb_prev, cm, s >> 3, 2 * (s & 7) + 1);
         __builtin_amdgcn_sched_barrier(0);
     }
-    if constexpr (MODE == 1) {
+    if constexpr (MODE >= 1) {
         if (m > 0) epi_append(st, acc_prev, bb_prev, cm, m - 1, q, h, rbase, j, wv, L.cnt, L.zst[t], cand);
     }
     read_bias(L, nslot, h, bb_next);   // after the last use of bb_prev: the two may be one array
@@ -226,10 +231,11 @@ __device__ __forceinline__ void pass_last(PassState<MODE> &st, const f32x16 (&ac
     uint32_t cm[2] = {0u, 0u};
 #pragma unroll
     for (int i = 0; i < 32; ++i) epi_one<MODE>(st, acc, bb, cm, i >> 4, i & 15);
-    if constexpr (MODE == 1) epi_append(st, acc, bb, cm, m, q, h, rbase, j, wv, L.cnt, L.zst[t], cand);
+    if constexpr (MODE >= 1) epi_append(st, acc, bb, cm, m, q, h, rbase, j, wv, L.cnt, L.zst[t], cand);
 }
 
-// Pass 1 (MODE 0) and pass 2 (MODE 1).  One workgroup per (256 rows, split);
+// Pass 1 (MODE 0) and pass 2 (MODE 1, or 2 without the softmax mass's sums).
+// One workgroup per (256 rows, split);
 // a one-dimensional grid ordered so that the four splits of a row group are
 // consecutive workgroups of one XCD (workgroup i runs on XCD i % 8), which
 // then read its rows of X through one L2.
@@ -271,7 +277,7 @@ __global__ __launch_bounds__(kLT) void k_lt_pass(const uint16_t *__restrict__ X,
             st.esum[u] = 0.f;
         }
     }
-    if (MODE == 1) L.cnt[t] = 0;
+    if (MODE >= 1) L.cnt[t] = 0;
     BlockRegs pE, pO;
     load_block(pE, Wt, bias, q, 0, t);
     store_block(L, pE, 0, t);
@@ -304,7 +310,7 @@ __global__ __launch_bounds__(kLT) void k_lt_pass(const uint16_t *__restrict__ X,
     } else {
         pass_last<MODE>(st, accO, bbO, nb - 1, q, h, rbase, j, wv, L, t, cand);
     }
-    if (MODE == 1) __syncthreads();   // every append of the workgroup is counted
+    if (MODE >= 1) __syncthreads();   // every append of the workgroup is counted
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int row = rbase + 32 * u + j;
@@ -321,9 +327,9 @@ __global__ __launch_bounds__(kLT) void k_lt_pass(const uint16_t *__restrict__ X,
                 for (int i = 0; i < 4; ++i) dst[i] = make_uint4(w[4 * i], w[4 * i + 1], w[4 * i + 2], w[4 * i + 3]);
             }
         } else {
-            const float e = st.esum[u] + __shfl_xor(st.esum[u], 32);
+            const float e = MODE == 1 ? st.esum[u] + __shfl_xor(st.esum[u], 32) : 0.f;
             if (st.valid[u] && h == 0) {
-                qsum[(size_t)row * kNQ + q] = e;
+                if (MODE == 1) qsum[(size_t)row * kNQ + q] = e;
                 cnt[(size_t)row * kNQ + q] = L.cnt[wv * 64 + 32 * u + j];
             }
         }
@@ -537,7 +543,11 @@ int launch_logits_top64(const uint16_t *X, int rows, const uint16_t *Wt, const f
     hipLaunchKernelGGL(k_lt_pass<0>, grid, dim3(kLT), 0, st, X, rows, Wt, bias, V, stats, nullptr, nullptr, nullptr,
                        nullptr);
     hipLaunchKernelGGL(k_lt_bound, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, stats, rows, thr, n_exact);
-    hipLaunchKernelGGL(k_lt_pass<1>, grid, dim3(kLT), 0, st, X, rows, Wt, bias, V, nullptr, thr, cand, cnt, qsum);
+    if (mass)
+        hipLaunchKernelGGL(k_lt_pass<1>, grid, dim3(kLT), 0, st, X, rows, Wt, bias, V, nullptr, thr, cand, cnt, qsum);
+    else   // no softmax mass asked for: pass 2 leaves out the sums of exp
+        hipLaunchKernelGGL(k_lt_pass<2>, grid, dim3(kLT), 0, st, X, rows, Wt, bias, V, nullptr, thr, cand, cnt,
+                           nullptr);
     hipLaunchKernelGGL(k_lt_select, dim3((unsigned)rows), dim3(64), 0, st, rows, thr, cand, cnt, qsum, idx, mass,
                        n_exact, queue);
     hipLaunchKernelGGL(k_lt_exact, dim3(256), dim3(64), 0, st, X, Wt, bias, V, thr, n_exact, queue, idx, mass);

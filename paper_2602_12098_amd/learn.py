@@ -370,18 +370,21 @@ class Proposer:
         self.vocab = vocab.contiguous()   # uint8 [V][N]
 
     @torch.no_grad()
-    def propose(self, W, perm, s, tau, n_sym, fixed_paths=None, K_fixed=8, fused=True, work=None):
+    def propose(self, W, perm, s, tau, n_sym, fixed_paths=None, K_fixed=8, fused=True, work=None,
+                with_mass=True):
         """Features -> hidden layers -> top-64 of the logits -> table
         [n_vec][64 + K_fixed][N].  Returns (table, mass).  fused: the last layer
         and the top-64 in one pass that never writes the logits
-        (logits_top64); else the logits GEMM and topk64 (same result)."""
+        (logits_top64); else the logits GEMM and topk64 (same result).
+        with_mass=False (fused only): mass is None, and the fused kernels
+        leave out the softmax sums."""
         n_sc = perm.shape[0]
         x = mlp_features(W, perm, s, tau, n_sym, kind=self.kind)
         p = self.p
         if fused and self.vocab.shape[0] % 128 == 0 and self.vocab.shape[0] >= 256:
             h1 = gemm_bf16(x, p.W1, trans_b=True, bias=p.b1, relu=True, out_f32=False, out_bf16=True)
             h2 = gemm_bf16(h1, p.W2, trans_b=True, bias=p.b2, relu=True, out_f32=False, out_bf16=True)
-            top, mass = logits_top64(h2, p.W3, p.b3, work=work)
+            top, mass = logits_top64(h2, p.W3, p.b3, with_mass=with_mass, work=work)
         else:
             z = MLPFunction.forward(_NoCtx(), x, *p)
             top, mass = topk64(z)
