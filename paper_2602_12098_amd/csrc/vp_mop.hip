@@ -657,7 +657,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     // (3) bucket sort by M over [0, T], then exact (M, lexicographic r) inside buckets
     // bucket of M: kNB (M / T)^4, monotone in M.  The members of S(T) grow
     // steeply towards T (|S(x)| rises like a power of x), and the fourth power
-    // spreads them nearly evenly, which keeps every bucket's insertion sort short.
+    // spreads them nearly evenly, which keeps every bucket's ranking short.
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
     for (int b = t; b < kNB; b += kT) S.dp[0][b] = 0u;
     double m[PER];
@@ -701,27 +701,33 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             const uint32_t pos = atomicAdd(&S.dp[1][bk[q]], 1u);
             S.fm[pos] = m[q];
             S.fw[pos] = lex[q];
-            S.fe[pos] = (uint16_t)(t + q * kT);
         }
     __syncthreads();
-    for (int b = t; b < kNB; b += kT) {
-        const uint32_t lo = S.dp[0][b], hi = S.dp[1][b];
-        for (uint32_t a = lo + 1; a < hi; ++a) {   // insertion sort on (M, lex)
-            const double mm = S.fm[a];
-            const unsigned long long x = S.fw[a];
-            const uint16_t e = S.fe[a];
-            uint32_t c = a;
-            while (c > lo && (S.fm[c - 1] > mm || (S.fm[c - 1] == mm && S.fw[c - 1] > x))) {
-                S.fm[c] = S.fm[c - 1];
-                S.fw[c] = S.fw[c - 1];
-                S.fe[c] = S.fe[c - 1];
-                --c;
+    // inside its bucket, each member's place is the number of members with a
+    // smaller (M, lexicographic r) key (the keys are distinct: r is); every
+    // thread ranks its own members, then all write them to their places
+    uint32_t dst[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        dst[q] = 0xffffffffu;
+        if (bk[q] >= 0) {
+            const uint32_t lo = S.dp[0][bk[q]], hi = S.dp[1][bk[q]];
+            uint32_t below = 0;
+            for (uint32_t a = lo; a < hi; ++a) {
+                const double ma = S.fm[a];
+                below += (ma < m[q] || (ma == m[q] && S.fw[a] < lex[q])) ? 1u : 0u;
             }
-            S.fm[c] = mm;
-            S.fw[c] = x;
-            S.fe[c] = e;
+            dst[q] = lo + below;
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q)
+        if (bk[q] >= 0) {
+            S.fm[dst[q]] = m[q];
+            S.fw[dst[q]] = lex[q];
+            S.fe[dst[q]] = (uint16_t)(t + q * kT);
+        }
     __syncthreads();
     for (int k = t; k < K; k += kT) {   // one path per thread: its N rank bytes
         const unsigned long long w = nibble_reverse(S.fw[k], N);   // level i at bits 4i
