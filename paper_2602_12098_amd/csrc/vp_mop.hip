@@ -9,11 +9,13 @@
 // member of S(T) is itself a member padded with zeros.  So: (1) a counting
 // recursion over a discretised metric (each term rounded up to a grid of
 // step h, which can only under-count) picks the smallest grid threshold T
-// with at least K members, first on a coarse grid, then on a fine grid
-// below the coarse answer; (2) S(T) is enumerated level by level, keeping
-// every prefix whose partial metric is <= T (the frontier never exceeds
-// |S(T)|); (3) S(T) is bucket-sorted by M over [0, T] and each bucket sorted
-// by the exact key (M, lexicographic r); the first K are the result.  This
+// with at least K members, on a grid over [0, 0.625 U] for an upper bound U
+// of the K-th smallest M (over [0, 1.25 U] if that grid never reaches K);
+// (2) S(T) is enumerated level by level, keeping every prefix whose partial
+// metric is <= T (the frontier never exceeds |S(T)|); (3) S(T) is
+// bucket-sorted by M over [0, T] and each member placed inside its bucket by
+// its rank under the exact key (M, lexicographic r); the first K are the
+// result.  This
 // does one enumeration and one sort instead of a K-way selection per
 // level.  A subcarrier whose S(T) does not fit the buffer (clustered or
 // equal weights) is marked and handled by the K-best kernel below.
