@@ -108,6 +108,25 @@ def test_paths_mop_bit_exact(vp):
             assert np.array_equal(paths[sc], ref), (wl.name, sc)
 
 
+@pytest.mark.parametrize("N,K,kind", [(16, 512, "integer"), (12, 256, "integer"), (8, 1000, "integer"),
+                                      (16, 1024, "loguniform"), (16, 64, "loguniform"), (5, 300, "integer")])
+def test_paths_mop_exact_metric_ties_at_scale(vp, N, K, kind):
+    # weights with many exactly equal metrics (small integers: every tie is
+    # broken by the lexicographic order inside the metric buckets) or spread
+    # over three decades; both the one-step bound (K <= 2^N) and the greedy
+    # one (K > 2^N), K up to the 1024 limit; bit-exact to the oracle's K-best
+    rng = np.random.default_rng(N * 31 + K)
+    n_sc = 6
+    if kind == "integer":
+        w = rng.integers(1, 5, size=(n_sc, N)).astype(np.float32)
+    else:
+        w = (10.0 ** rng.uniform(-1.5, 1.5, size=(n_sc, N))).astype(np.float32)
+    p = host(vp.paths_mop(_to_dev(w), K))
+    for sc in range(n_sc):
+        ref = O.mop_paths_kbest(w[sc].astype(np.float64), K)
+        assert np.array_equal(p[sc], ref), (N, K, kind, sc)
+
+
 def test_paths_mop_ties_and_small_K(vp):
     # equal weights: every tie broken lexicographically; K = 1 and K = 9^N
     w = torch.full((3, 3), 0.25, dtype=torch.float32, device=DEV)
