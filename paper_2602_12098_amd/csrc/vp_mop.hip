@@ -48,12 +48,14 @@ struct MopSmem {
     uint32_t part[kT];
 };
 
-// In-LDS bitonic sort of n (a power of two) 64-bit keys with 16-bit payloads.
+// In-LDS bitonic sort of n (a power of two) 64-bit keys with 16-bit payloads
+// by a workgroup of TPB threads.
+template <int TPB = kT>
 __device__ void block_bitonic_sort(unsigned long long *key, uint16_t *val, int n) {
     const int t = threadIdx.x;
     for (int size = 2; size <= n; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int i = t; i < (n >> 1); i += kT) {
+            for (int i = t; i < (n >> 1); i += TPB) {
                 const int lo = 2 * i - (i & (stride - 1));
                 const int hi = lo + stride;
                 const bool up = (lo & size) == 0;
@@ -83,17 +85,17 @@ __device__ __forceinline__ void bitonic_keep(unsigned long long &k, uint32_t &v,
     v = take ? ov : v;
 }
 
-template <class WordFn>
+template <int TPB = kT, class WordFn>
 __device__ void write_suffix_order(WordFn word, int K, unsigned long long *key, uint16_t *val,
                                    uint16_t *__restrict__ out) {
     const int t = threadIdx.x;
     int n = 1;
     while (n < K) n <<= 1;
-    if (n <= 2 * kT) {
+    if (n <= 2 * TPB) {
         // Bitonic sort with elements 2t and 2t + 1 in thread t's registers:
         // partners at distance 1 are in the same thread, at 2..64 in lane
         // t ^ (stride / 2) of the same wave, further ones are exchanged
-        // through LDS.  Positions n..2 kT - 1 hold sentinels sorted among
+        // through LDS.  Positions n..2 TPB - 1 hold sentinels sorted among
         // themselves.
         const int e0 = 2 * t;
         unsigned long long k0 = e0 < K ? word(e0) : ~0ull, k1 = e0 + 1 < K ? word(e0 + 1) : ~0ull;
@@ -142,13 +144,13 @@ __device__ void write_suffix_order(WordFn word, int K, unsigned long long *key, 
         __syncthreads();
         return;
     }
-    for (int k = t; k < n; k += kT) {
+    for (int k = t; k < n; k += TPB) {
         key[k] = k < K ? word(k) : ~0ull;
         val[k] = (uint16_t)k;
     }
     __syncthreads();
-    block_bitonic_sort(key, val, n);
-    for (int k = t; k < K; k += kT) out[k] = val[k];
+    block_bitonic_sort<TPB>(key, val, n);
+    for (int k = t; k < K; k += TPB) out[k] = val[k];
     __syncthreads();
 }
 
@@ -348,7 +350,7 @@ __global__ __launch_bounds__(kT) void k_mop(const float *__restrict__ w2, int n_
 // With FENCE = false the closing barrier (which lets the next scan reuse
 // `scratch`) is left out: the caller then alternates two scratch buffers and
 // has a barrier of its own between two scans on the same one.
-template <bool FENCE = true>
+template <bool FENCE = true, int TPB = kT>
 __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratch, uint32_t *total) {
     const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
     const uint32_t incl = wave_scan_incl(v);
@@ -356,7 +358,7 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratc
     __syncthreads();
     uint32_t base = 0, tot = 0;
 #pragma unroll
-    for (int q = 0; q < kT / 64; ++q) {
+    for (int q = 0; q < TPB / 64; ++q) {
         const uint32_t x = scratch[q];
         if (q < wv) base += x;
         tot += x;
@@ -374,10 +376,10 @@ __device__ __forceinline__ uint32_t block_scan_excl(uint32_t v, uint32_t *scratc
 // zero bins on their left so that shifted reads need no bounds test; counts
 // saturate at 2^20 (>= K, all that is compared).  buf: 2 x 2 NB uint32 of
 // LDS; dtab: kMaxN x 9 ints of LDS.
-template <int NB>
+template <int NB, int TPB = kT>
 __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *buf, int *sbest, int (*dtab)[9]) {
-    constexpr int BPT = NB / kT;   // bins per thread
-    static_assert(BPT * kT == NB && (BPT == 1 || BPT == 2), "one or two bins per thread");
+    constexpr int BPT = NB / TPB;   // bins per thread
+    static_assert(BPT * TPB == NB && (BPT == 1 || BPT == 2), "one or two bins per thread");
     constexpr uint32_t kSat = 1u << 20;
     const int t = threadIdx.x;
     const double inv_h = (1.0 + 0x1p-40) / h;   // the tiny excess keeps every term rounded up
@@ -390,7 +392,7 @@ __device__ int dp_threshold(const double *w, int N, int K, double h, uint32_t *b
     }
     if (t == 0) *sbest = NB;
     // the shifts ceil(w_l r / h) depend only on the level: one thread each
-    for (int q = t; q < N * 9; q += kT) {
+    for (int q = t; q < N * 9; q += TPB) {
         const int l = q / 9, r = q % 9;
         const double x = ceil((w[l] * inv_h) * (double)r);
         dtab[l][r] = x < (double)NB ? (int)x : NB;
@@ -528,23 +530,23 @@ __device__ double smallest_weights_bound(const double *w, int N, int m) {
     return __shfl(x, 0);
 }
 
-template <int CAP>
+template <int CAP, int NBK = kNB, int TPB = kT>
 struct ThrSmem {
     // fm and fw, adjacent, first hold the counting recursion's two buffers
     double fm[CAP];               // S(T) members / frontier: metric
     unsigned long long fw[CAP];   // rank nibbles (level i at bits 4i), later the lexicographic key
     uint16_t fe[CAP];             // enumeration (= lexicographic) position, carried through the sort
     uint16_t rank_of[CAP];        // enumeration position -> MoP rank (or 0xffff beyond K)
-    uint32_t dp[2][kNB];          // bucket starts / cursors
+    uint32_t dp[2][NBK];          // bucket starts / cursors
     double w[kMaxN];
     int dtab[kMaxN][9];           // bin shifts of the counting recursion
-    uint32_t scan[kT / 64];
-    uint32_t lscan[2][kT / 64];   // the enumeration's scans, alternating by level
+    uint32_t scan[TPB / 64];
+    uint32_t lscan[2][TPB / 64];  // the enumeration's scans, alternating by level
     int best;
     double ubound;
 
     __device__ uint32_t *count_buffers() {
-        static_assert(2 * CAP * sizeof(double) >= 4 * kNB * sizeof(uint32_t), "fm and fw hold the counting buffers");
+        static_assert(2 * CAP * sizeof(double) >= 4 * kNBCount * sizeof(uint32_t), "fm and fw hold the counting buffers");
         return reinterpret_cast<uint32_t *>(fm);
     }
 };
@@ -555,12 +557,17 @@ struct ThrSmem {
 // the K-best kernel.  20 KiB of LDS, eight workgroups per CU.
 constexpr int kCap512 = 768;
 
+// The same for tables of up to 256 paths on 128-thread workgroups: 384
+// frontier entries and 256 metric buckets, 10 KiB of LDS, so that a CU holds
+// fifteen workgroups and a whole slot's subcarriers are resident at once.
+constexpr int kCap256 = 384, kNB256 = 256, kT256 = 128;
+
 // One subcarrier (pointers as for mop_kbest_one).  Marks the table for the
 // K-best kernel when the threshold enumeration does not fit.
-template <int CAP>
-__device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__restrict__ w2, int N, int K, uint8_t *__restrict__ out,
-                            uint16_t *__restrict__ order) {
-    constexpr int PER = CAP / kT;   // frontier entries held per thread
+template <int CAP, int NBK = kNB, int TPB = kT>
+__device__ __forceinline__ void mop_thr_one(ThrSmem<CAP, NBK, TPB> &S, const float *__restrict__ w2, int N, int K,
+                                            uint8_t *__restrict__ out, uint16_t *__restrict__ order) {
+    constexpr int PER = CAP / TPB;   // frontier entries held per thread
     const int t = threadIdx.x;
 
     if (t < N) S.w[t] = (double)w2[t];
@@ -570,9 +577,9 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         valid &= (S.w[i] > 0.0) && isfinite(S.w[i]);
     }
     if (!valid) {   // failed preprocessing: a deterministic all-zero table
-        for (int idx = t; idx < K * N; idx += kT) out[idx] = 0;
+        for (int idx = t; idx < K * N; idx += TPB) out[idx] = 0;
         if (order)
-            for (int k = t; k < 2 * K; k += kT) order[k] = (uint16_t)(k % K);
+            for (int k = t; k < 2 * K; k += TPB) order[k] = (uint16_t)(k % K);
         return;
     }
     // (1) threshold: the smallest grid point whose count reaches K.  U bounds
@@ -590,10 +597,10 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
     double T = 0.0;   // K = 1: the zero path alone
     if (U > 0.0) {
         double h = 0.625 * U / (double)(kNBCount - 1);
-        int b = dp_threshold<kNBCount>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
+        int b = dp_threshold<kNBCount, TPB>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
         if (b < 0) {
             h = 1.25 * U / (double)(kNBCount - 1);
-            b = dp_threshold<kNBCount>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
+            b = dp_threshold<kNBCount, TPB>(S.w, N, K, h, S.count_buffers(), &S.best, S.dtab);
         }
         T = (b < 0 ? (double)(kNBCount - 1) : (double)b) * h;
     }
@@ -611,7 +618,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         double wr[9];   // the level's metric steps w_l r, formed once
 #pragma unroll
         for (int r = 0; r < 9; ++r) wr[r] = wl * (double)r;
-        const uint32_t chunk = (n + kT - 1) / kT;
+        const uint32_t chunk = (n + TPB - 1) / TPB;
         const uint32_t j0 = t * chunk;
         double m[PER];
         unsigned long long wd[PER];
@@ -634,7 +641,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         // (its barrier also orders this level's frontier reads before the
         // children's writes; the barrier closing the level separates two
         // scans on one buffer)
-        uint32_t off = block_scan_excl<false>(cnt, S.lscan[l & 1], &total);
+        uint32_t off = block_scan_excl<false, TPB>(cnt, S.lscan[l & 1], &total);
         if (total > (uint32_t)CAP) {
             fail = true;
             break;
@@ -657,17 +664,17 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         return;
     }
     // (3) bucket sort by M over [0, T], then exact (M, lexicographic r) inside buckets
-    // bucket of M: kNB (M / T)^4, monotone in M.  The members of S(T) grow
+    // bucket of M: NBK (M / T)^4, monotone in M.  The members of S(T) grow
     // steeply towards T (|S(x)| rises like a power of x), and the fourth power
     // spreads them nearly evenly, which keeps every bucket's ranking short.
     const double invT = T > 0.0 ? 1.0 / T : 0.0;
-    for (int b = t; b < kNB; b += kT) S.dp[0][b] = 0u;
+    for (int b = t; b < NBK; b += TPB) S.dp[0][b] = 0u;
     double m[PER];
     unsigned long long lex[PER];
     int bk[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-        const uint32_t j = t + q * kT;
+        const uint32_t j = t + q * TPB;
         bk[q] = -1;
         if (j < n) {
             S.rank_of[j] = 0xffff;
@@ -675,7 +682,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             const unsigned long long wd = S.fw[j];
             lex[q] = nibble_reverse(wd, N);   // level 0 in the most significant nibble
             const double x = m[q] * invT, x2 = x * x;
-            bk[q] = min(kNB - 1, (int)(x2 * x2 * (double)kNB));
+            bk[q] = min(NBK - 1, (int)(x2 * x2 * (double)NBK));
         }
     }
     __syncthreads();
@@ -684,11 +691,11 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         if (bk[q] >= 0) atomicAdd(&S.dp[0][bk[q]], 1u);
     __syncthreads();
     {
-        constexpr int BPT = kNB / kT;
+        constexpr int BPT = NBK / TPB;
         uint32_t loc = 0;
         for (int q = 0; q < BPT; ++q) loc += S.dp[0][t * BPT + q];
         uint32_t tot;
-        uint32_t base = block_scan_excl(loc, S.scan, &tot);
+        uint32_t base = block_scan_excl<true, TPB>(loc, S.scan, &tot);
         for (int q = 0; q < BPT; ++q) {
             const uint32_t c = S.dp[0][t * BPT + q];
             S.dp[0][t * BPT + q] = base;   // bucket start
@@ -728,10 +735,10 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         if (bk[q] >= 0) {
             S.fm[dst[q]] = m[q];
             S.fw[dst[q]] = lex[q];
-            S.fe[dst[q]] = (uint16_t)(t + q * kT);
+            S.fe[dst[q]] = (uint16_t)(t + q * TPB);
         }
     __syncthreads();
-    for (int k = t; k < K; k += kT) {   // one path per thread: its N rank bytes
+    for (int k = t; k < K; k += TPB) {   // one path per thread: its N rank bytes
         const unsigned long long w = nibble_reverse(S.fw[k], N);   // level i at bits 4i
         uint8_t *o = out + (size_t)k * N;
         if (N == 16 && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
@@ -750,7 +757,7 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
         uint16_t *lexorder = order;
         // the enumeration visited S(T) in lexicographic order: the selected
         // paths, in enumeration order, are the path table in lexicographic order
-        for (int k = t; k < K; k += kT) S.rank_of[S.fe[k]] = (uint16_t)k;
+        for (int k = t; k < K; k += TPB) S.rank_of[S.fe[k]] = (uint16_t)k;
         __syncthreads();
         uint32_t sel[PER];
         uint32_t cnt = 0;
@@ -761,26 +768,26 @@ __device__ __forceinline__ void mop_thr_one(ThrSmem<CAP> &S, const float *__rest
             cnt += sel[q];
         }
         uint32_t tot;
-        uint32_t pos = block_scan_excl(cnt, S.scan, &tot);
+        uint32_t pos = block_scan_excl<true, TPB>(cnt, S.scan, &tot);
 #pragma unroll
         for (int q = 0; q < PER; ++q)
             if (sel[q]) lexorder[pos++] = S.rank_of[t * PER + q];
         // suffix-major order: the nibble reversal of the lexicographic key
         const int NN = N;
-        write_suffix_order(
+        write_suffix_order<TPB>(
             [&](int k) { return nibble_reverse(S.fw[k], NN); },
             K, reinterpret_cast<unsigned long long *>(S.fm), S.fe, lexorder + K);
     }
 }
 
-template <int CAP>
-__global__ __launch_bounds__(kT) void k_mop_thr(const float *__restrict__ w2, int N, int K,
-                                                uint8_t *__restrict__ paths, uint16_t *__restrict__ order) {
+template <int CAP, int NBK = kNB, int TPB = kT>
+__global__ __launch_bounds__(TPB) void k_mop_thr(const float *__restrict__ w2, int N, int K,
+                                                 uint8_t *__restrict__ paths, uint16_t *__restrict__ order) {
     extern __shared__ unsigned char smem_raw[];
-    ThrSmem<CAP> &S = *reinterpret_cast<ThrSmem<CAP> *>(smem_raw);
+    ThrSmem<CAP, NBK, TPB> &S = *reinterpret_cast<ThrSmem<CAP, NBK, TPB> *>(smem_raw);
     const int sc = blockIdx.x;
-    mop_thr_one<CAP>(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
-                     order ? order + (size_t)sc * 2 * K : nullptr);
+    mop_thr_one<CAP, NBK, TPB>(S, w2 + (size_t)sc * N, N, K, paths + (size_t)sc * K * N,
+                               order ? order + (size_t)sc * 2 * K : nullptr);
 }
 
 // Batched: one workgroup per subcarrier of any group (K <= 512), then the
@@ -844,7 +851,11 @@ int launch_mop(const float *w2, int n_sc, int N, int K, uint8_t *paths, uint16_t
                               (int)allow_dynamic_lds(k_mop_thr<kCap512>, sizeof(ThrSmem<kCap512>)) +
                               (int)allow_dynamic_lds(k_mop_thr<2048>, sizeof(ThrSmem<2048>));
     (void)lds_ok;
-    if (K <= 512)
+    using Small = ThrSmem<kCap256, kNB256, kT256>;
+    if (K <= 256)
+        hipLaunchKernelGGL((k_mop_thr<kCap256, kNB256, kT256>), dim3(n_sc), dim3(kT256), sizeof(Small), st, w2, N, K,
+                           paths, order);
+    else if (K <= 512)
         hipLaunchKernelGGL(k_mop_thr<kCap512>, dim3(n_sc), dim3(kT), sizeof(ThrSmem<kCap512>), st, w2, N, K, paths,
                            order);
     else
