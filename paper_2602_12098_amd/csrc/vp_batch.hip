@@ -362,7 +362,9 @@ int enqueue_slot(vp_batch *p, hipStream_t st) {
     int rc = launch_batch_preprocess(p->d_groups, p->d_sc_group, p->n_sc, p->M, p->H, p->W, p->w2, p->perm, p->G,
                                      p->status, st);
     if (rc != VP_OK) return rc;
-    rc = launch_batch_mop(p->d_groups, p->d_sc_group, p->n_sc, p->w2, p->paths, st);
+    int max_K = 0;
+    for (const auto &g : p->hg) max_K = g.K > max_K ? g.K : max_K;
+    rc = launch_batch_mop(p->d_groups, p->d_sc_group, p->n_sc, max_K, p->w2, p->paths, st);
     if (rc != VP_OK) return rc;
     hipLaunchKernelGGL(k_batch_search, dim3((unsigned)p->grid), dim3(kBW), 0, st, p->d_groups, p->tiles, p->ntiles,
                        p->counter, p->W, p->perm, p->s, p->paths, p->n_sym, p->flags, p->best);

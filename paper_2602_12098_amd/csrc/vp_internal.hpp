@@ -134,8 +134,8 @@ int launch_batch_preprocess(const BatchGroup *groups, const int32_t *sc_group, i
                             const float2 *H, float2 *W, float *w2, uint8_t *perm, float2 *G, int32_t *status,
                             hipStream_t st);
 void prepare_batch_kernels();   // kernel attributes, set once before a graph capture
-int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, const float *w2,
-                     uint8_t *paths, hipStream_t st);
+int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, int max_K, const float *w2,
+                     uint8_t *paths, hipStream_t st);   // max_K: the largest K of the groups
 
 // Learned path proposal (vp_learn.hip).
 int launch_gemm(int M, int N, int K, const uint16_t *A, long long lda, int transA, const uint16_t *B, long long ldb,

@@ -790,17 +790,19 @@ __global__ __launch_bounds__(TPB) void k_mop_thr(const float *__restrict__ w2, i
                                order ? order + (size_t)sc * 2 * K : nullptr);
 }
 
-// Batched: one workgroup per subcarrier of any group (K <= 512), then the
-// K-best kernel for the tables the threshold pass marked.
-__global__ __launch_bounds__(kT) void k_batch_mop_thr(const BatchGroup *__restrict__ groups,
-                                                      const int32_t *__restrict__ sc_group,
-                                                      const float *__restrict__ w2, uint8_t *__restrict__ paths) {
+// Batched: one workgroup per subcarrier of any group (K <= 512, or the
+// 128-thread form when every group has K <= 256), then the K-best kernel for
+// the tables the threshold pass marked.
+template <int CAP, int NBK = kNB, int TPB = kT>
+__global__ __launch_bounds__(TPB) void k_batch_mop_thr(const BatchGroup *__restrict__ groups,
+                                                       const int32_t *__restrict__ sc_group,
+                                                       const float *__restrict__ w2, uint8_t *__restrict__ paths) {
     extern __shared__ unsigned char smem_raw[];
-    ThrSmem<kCap512> &S = *reinterpret_cast<ThrSmem<kCap512> *>(smem_raw);
+    ThrSmem<CAP, NBK, TPB> &S = *reinterpret_cast<ThrSmem<CAP, NBK, TPB> *>(smem_raw);
     const int sc = blockIdx.x;
     const BatchGroup g = groups[sc_group[sc]];
     const long long j = sc - g.sc0;
-    mop_thr_one<kCap512>(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr);
+    mop_thr_one<CAP, NBK, TPB>(S, w2 + g.offN + j * g.U, g.U, g.K, paths + g.offP + j * g.K * g.U, nullptr);
 }
 
 __global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__restrict__ groups,
@@ -831,15 +833,20 @@ __global__ __launch_bounds__(kT) void k_batch_mop_kbest(const BatchGroup *__rest
 }  // namespace
 
 void prepare_batch_kernels() {
-    (void)allow_dynamic_lds(k_batch_mop_thr, sizeof(ThrSmem<kCap512>));
+    (void)allow_dynamic_lds(k_batch_mop_thr<kCap512>, sizeof(ThrSmem<kCap512>));
+    (void)allow_dynamic_lds(k_batch_mop_thr<kCap256, kNB256, kT256>, sizeof(ThrSmem<kCap256, kNB256, kT256>));
     (void)allow_dynamic_lds(k_batch_mop_kbest, sizeof(MopSmem));
 }
 
-int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, const float *w2,
+int launch_batch_mop(const BatchGroup *groups, const int32_t *sc_group, int n_sc_total, int max_K, const float *w2,
                      uint8_t *paths, hipStream_t st) {
     if (n_sc_total == 0) return VP_OK;
-    hipLaunchKernelGGL(k_batch_mop_thr, dim3(n_sc_total), dim3(kT), sizeof(ThrSmem<kCap512>), st, groups, sc_group, w2,
-                       paths);
+    if (max_K <= 256)
+        hipLaunchKernelGGL((k_batch_mop_thr<kCap256, kNB256, kT256>), dim3(n_sc_total), dim3(kT256),
+                           sizeof(ThrSmem<kCap256, kNB256, kT256>), st, groups, sc_group, w2, paths);
+    else
+        hipLaunchKernelGGL(k_batch_mop_thr<kCap512>, dim3(n_sc_total), dim3(kT), sizeof(ThrSmem<kCap512>), st, groups,
+                           sc_group, w2, paths);
     hipLaunchKernelGGL(k_batch_mop_kbest, dim3((unsigned)((n_sc_total + kT - 1) / kT)), dim3(kT), sizeof(MopSmem), st,
                        groups, sc_group, n_sc_total, w2, paths);
     return launch_status();
