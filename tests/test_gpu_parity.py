@@ -492,8 +492,10 @@ def test_deterministic_reruns(vp):
 
 def test_paths_mop_clustered_weights_use_fallback(vp):
     # 16 equal weights: with K = 1024 the threshold set holds C(20,4) = 4845
-    # vectors, more than the enumeration buffer -> the K-best kernel redoes it.
-    for K in (512, 1024):
+    # vectors, more than the enumeration buffer -> the K-best kernel redoes it
+    # (K = 200 and 256: the same through the 128-thread kernel of K <= 256,
+    # whose buffer holds 384: 969 vectors lie within three steps)
+    for K in (200, 256, 512, 1024):
         w = torch.full((2, 16), 0.3, dtype=torch.float32, device=DEV)
         p = host(vp.paths_mop(w, K))
         ref = O.mop_paths_kbest(np.full(16, np.float32(0.3)).astype(np.float64), K)
