@@ -30,9 +30,12 @@ sys.path.insert(0, ROOT)
 
 METRIC = "precoded vectors/s at 16×16 256-QAM, 512 paths; power gap to exact VP (dB)"
 
-# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 VALU lane-ops/s; an FP32
-# FMA is 2 flop -> 78.6 TFLOP/s without packed-FP32 instructions (not used here).
-PEAK_VALU_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+# MI355X's published fp32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flop per clock
+# per SIMD = 157.3 TFLOP/s, taken whole: a stream of independent plain v_fmac_f32
+# instructions (no packed FP32; paper_2602_12098_amd/valuref.py) sustains 2.95 SIMD
+# clocks per wave64 instruction, under the 4 a 16-lane SIMD would need, so code without
+# packed instructions is not held to half of it.
+PEAK_VALU_TFLOPS = 256 * 4 * 64 * 2.4e9 / 1e12
 FLOP_PER_CM = 6   # one complex multiplication: 4 real multiplies + 2 adds
 
 
@@ -77,15 +80,20 @@ COUNTERS_FILE = "profiles/search_16x16_256qam_K512.valu.json"
 def search_counters(K, path=None):
     """Measured clock and VALU issue of the search kernel from the committed
     counter profile (GRBM_GUI_ACTIVE against the kernel's duration gives the
-    shader clock; SQ_ACTIVE_INST_VALU x 4 cycles over all SIMDs gives the VALU
-    issue fraction), or {} when it is missing, K differs or the sources changed."""
+    shader clock; 1024 SIMDs x those clocks over SQ_INSTS_VALU the SIMD clocks
+    per VALU instruction, set against those of a plain FMA stream), or {} when
+    it is missing, K differs or the sources changed."""
     path = path or os.path.join(ROOT, COUNTERS_FILE)
     if K != 512 or not os.path.exists(path):
         return {}
     rec = json.load(open(path))
     if sources_sha256(rec.get("source_files", SEARCH_SOURCES)) != rec.get("source_sha256"):
         return {}
-    return {"sclk_ghz_measured": rec["sclk_ghz"], "valu_busy": rec["valu_busy"],
+    if "simd_clocks_per_valu_instr" not in rec:
+        return {}
+    return {"sclk_ghz_measured": rec["sclk_ghz"], "simd_clocks_per_valu_instr": rec["simd_clocks_per_valu_instr"],
+            "fma_stream_clocks_per_valu_instr": rec["fma_stream_clocks_per_valu_instr"],
+            "issue_vs_fma_stream": rec["issue_vs_fma_stream"],
             "valu_instr_per_vector": rec["valu_instr_per_vector"], "counters_source": os.path.relpath(path, ROOT)}
 
 

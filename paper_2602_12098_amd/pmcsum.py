@@ -29,13 +29,7 @@ def summarize(db_path: str) -> str:
     return "\n".join(out)
 
 
-def valu_record(db_path: str, regex: str, vectors: int, sources) -> dict:
-    """Clock and VALU issue of one kernel from a run with SQ_INSTS_VALU and
-    GRBM_GUI_ACTIVE: the shader clock is GRBM_GUI_ACTIVE (summed over the 8
-    XCDs) / 8 over the dispatch's duration; VALU busy is SQ_INSTS_VALU x 4
-    cycles (a wave64 VALU instruction occupies a SIMD16 for 4 cycles) over
-    1024 SIMDs x those cycles."""
-    import hashlib
+def _per_dispatch(db_path: str, regex: str):
     db = sqlite3.connect(db_path)
     rows = db.execute("select kernel_name, dispatch_id, counter_name, sum(value), avg(duration) "
                       "from counters_collection group by kernel_name, dispatch_id, counter_name").fetchall()
@@ -46,27 +40,49 @@ def valu_record(db_path: str, regex: str, vectors: int, sources) -> dict:
             per[did]["duration_ns"] = d
     if not per:
         raise SystemExit(f"no dispatch of /{regex}/ in {db_path}")
+    return per
+
+
+def clocks_per_valu(db_path: str, regex: str):
+    """(shader clock in GHz, SIMD clocks per VALU wave-instruction, VALU
+    instructions, dispatches, duration in s) of one kernel from a run with
+    SQ_INSTS_VALU and GRBM_GUI_ACTIVE: the clock is GRBM_GUI_ACTIVE (summed
+    over the 8 XCDs) / 8 over the dispatch's duration; the clocks per
+    instruction are 1024 SIMDs x those cycles over SQ_INSTS_VALU."""
+    per = _per_dispatch(db_path, regex)
     n = len(per)
     mean = lambda c: sum(v[c] for v in per.values()) / n
     dur = mean("duration_ns") * 1e-9
     cycles = mean("GRBM_GUI_ACTIVE") / 8.0
     valu = mean("SQ_INSTS_VALU")
+    return cycles / dur / 1e9, 1024.0 * cycles / valu, valu, n, dur
+
+
+def valu_record(db_path: str, regex: str, vectors: int, sources, ref_db: str) -> dict:
+    """Clock and VALU issue of one kernel, set against the reference stream of
+    independent fp32 FMAs (valuref.py, profiled the same way): issue_vs_fma_stream
+    is the stream's clocks per VALU instruction over the kernel's."""
+    import hashlib
+    ghz, cpi, valu, n, dur = clocks_per_valu(db_path, regex)
+    rghz, rcpi, _, _, _ = clocks_per_valu(ref_db, "fma_stream")
     h = hashlib.sha256()
     for f in sources:
         with open(f, "rb") as fh:
             h.update(fh.read())
-    return {"kernel_regex": regex, "dispatches": n, "duration_us": dur * 1e6, "sclk_ghz": cycles / dur / 1e9,
-            "valu_instr": valu, "valu_busy": valu * 4.0 / (1024.0 * cycles),
+    return {"kernel_regex": regex, "dispatches": n, "duration_us": dur * 1e6, "sclk_ghz": ghz,
+            "valu_instr": valu, "simd_clocks_per_valu_instr": cpi,
+            "fma_stream_clocks_per_valu_instr": rcpi, "fma_stream_sclk_ghz": rghz,
+            "issue_vs_fma_stream": rcpi / cpi,
             "valu_instr_per_vector": valu / vectors, "vectors": vectors, "source_files": list(sources),
             "source_sha256": h.hexdigest()}
 
 
 if __name__ == "__main__":
     if len(sys.argv) > 2 and sys.argv[1] == "--valu-json":
-        # --valu-json OUT DB REGEX VECTORS SOURCE...
+        # --valu-json OUT DB REF_DB REGEX VECTORS SOURCE...
         import json
-        out, db, regex, vec = sys.argv[2:6]
-        rec = valu_record(db, regex, int(vec), sys.argv[6:])
+        out, db, ref_db, regex, vec = sys.argv[2:7]
+        rec = valu_record(db, regex, int(vec), sys.argv[7:], ref_db)
         with open(out, "w") as f:
             json.dump(rec, f, indent=1)
         print(json.dumps(rec, indent=1))
