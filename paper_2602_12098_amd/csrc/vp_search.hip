@@ -161,7 +161,11 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     uint16_t *s_k = reinterpret_cast<uint16_t *>(s_therm + NB);     // [K] path index of lex position
     uint16_t *s_node = s_k + K;                                     // [K] stage-1 prefix of path k
     uint16_t *s_first = s_node + K;                                 // [K + 1] first lex position of a prefix
-    __shared__ float s_state[kVPB][kMaxPrefix * SW];
+    __shared__ __align__(16) float s_state[kVPB][kMaxPrefix * SW];
+    // the workgroup's symbol vectors in user order [kVPB][N], read once after
+    // the first barrier, in the stage-1 state area (first written after two
+    // more barriers)
+    float2 *s_x = reinterpret_cast<float2 *>(&s_state[0][0]);
     __shared__ float2 s_r0[kVPB][N];
     __shared__ float s_nlinv[N];
     __shared__ float s_wdiag[N];
@@ -201,10 +205,15 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     // barrier: the start residuals (W, perm and s), the table, and both orders
     // (the deepest-level-first positions t + kTB it are the ones the tier words
     // below take, kept in registers)
-    {   // start residuals: thread (h, i) for vector h, level i
-        const int h = t / kTT, i = t % kTT;
-        if (i < N && h < nlive)
-            s_r0[h][i] = stilde_over_tau<N>(Wc, perm + (size_t)sc * N, s, vbase + h, n_vec, i, 1.0f / tau);
+    // start residuals, thread (h, i) for vector h, level i: its W row and
+    // user i's symbol of vector h are read here, the sum over the permuted
+    // symbols is formed after the barrier from LDS (no read waits on perm)
+    const int h0 = t / kTT, i0 = t % kTT;
+    const bool r0_thread = i0 < N && h0 < nlive;
+    float2 wrow[N];
+    if (r0_thread) {
+        s_x[h0 * N + i0] = s[(size_t)i0 * n_vec + vbase + h0];
+        stilde_row<N>(Wc, i0, wrow);
     }
     if (t < N) {
         s_wdiag[t] = Wc[vp_pidx(N, t, t)].x;
@@ -228,6 +237,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
         }
     }
     __syncthreads();
+    if (r0_thread) s_r0[h0][i0] = stilde_staged<N>(wrow, s_perm, s_x + h0 * N, i0, 1.0f / tau);   // read in stage 1, two barriers on
     // stage-2 tier words: batch b holds the paths at positions [32 b, 32 b + 32)
     // of the deepest-level-first order; OR of their per-level rank thermometers
     static_assert(kBatch == 32 && kTB % kBatch == 0, "a batch is one half of a wave");

@@ -35,6 +35,32 @@ __device__ __forceinline__ float2 stilde_over_tau(const float2 *__restrict__ Wc,
     return make_float2(re * inv_tau, im * inv_tau);
 }
 
+// stilde_over_tau in two steps for kernels that stage the symbols in LDS:
+// the W row i (all N loads issued up front, as above), then the sum over the
+// permuted symbols x[pm[j]] with the same arithmetic in the same order, so
+// the result has the same bits.
+template <int N>
+__device__ __forceinline__ void stilde_row(const float2 *__restrict__ Wc, int i, float2 (&w)[N]) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) w[j] = Wc[vp_pidx(N, i, j)];
+}
+
+template <int N>
+__device__ __forceinline__ float2 stilde_staged(const float2 (&w)[N], const uint8_t *pm, const float2 *x_user, int i,
+                                                float inv_tau) {
+    float re = 0.f, im = 0.f;
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+        const int u = pm[j] < N ? pm[j] : N - 1;   // a corrupt permutation must not index out of bounds
+        const float2 x = x_user[u];
+        if (j <= i) {
+            re = fmaf(w[j].x, x.x, fmaf(-w[j].y, x.y, re));
+            im = fmaf(w[j].x, x.y, fmaf(w[j].y, x.x, im));
+        }
+    }
+    return make_float2(re * inv_tau, im * inv_tau);
+}
+
 // Hides a wave-uniform pointer from loop-invariant code motion, so that the W
 // column of each level is scalar-loaded where it is used instead of all 240
 // coefficients being hoisted (and spilled) at once.  Loads through the
