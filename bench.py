@@ -32,7 +32,7 @@ METRIC = "precoded vectors/s at 16×16 256-QAM, 512 paths; power gap to exact VP
 
 # MI355X's published fp32 vector peak: 256 CUs x 4 SIMDs x 2.4 GHz x 64 flop per clock
 # per SIMD = 157.3 TFLOP/s, taken whole: a stream of independent plain v_fmac_f32
-# instructions (no packed FP32; paper_2602_12098_amd/valuref.py) sustains 2.95 SIMD
+# instructions (no packed FP32; paper_2602_12098_amd/valuref.py) sustains 2.8-2.9 SIMD
 # clocks per wave64 instruction, under the 4 a 16-lane SIMD would need, so code without
 # packed instructions is not held to half of it.
 PEAK_VALU_TFLOPS = 256 * 4 * 64 * 2.4e9 / 1e12
