@@ -75,3 +75,50 @@ def test_rzf_powers_match_the_oracle():
     prep = Prep(torch.from_numpy(np.array(Ws)), torch.from_numpy(np.array(perms).astype(np.uint8)))
     got = bench.rzf_powers(prep, torch.from_numpy(wl.s), wl.n_sym).numpy()
     np.testing.assert_allclose(got, np.array(want), rtol=1e-12)
+
+
+def test_counters_are_reported_only_for_the_profiled_sources(tmp_path):
+    # the clock / VALU-issue record is reported while the search sources hash
+    # to the recorded value, and not at all for a stale hash or an old format
+    rec = json.load(open(os.path.join(ROOT, bench.COUNTERS_FILE)))
+    assert rec["source_files"] == bench.SEARCH_SOURCES
+    fresh = dict(rec, source_sha256=bench.sources_sha256(bench.SEARCH_SOURCES))
+    p = tmp_path / "fresh.json"
+    p.write_text(json.dumps(fresh))
+    got = bench.search_counters(512, str(p))
+    assert got["simd_clocks_per_valu_instr"] == rec["simd_clocks_per_valu_instr"]
+    assert got["issue_vs_fma_stream"] == rec["issue_vs_fma_stream"]
+    assert bench.search_counters(256, str(p)) == {}
+    p.write_text(json.dumps(dict(rec, source_sha256="0" * 64)))
+    assert bench.search_counters(512, str(p)) == {}
+    old = {k: v for k, v in fresh.items() if k != "simd_clocks_per_valu_instr"}
+    p.write_text(json.dumps(old))
+    assert bench.search_counters(512, str(p)) == {}
+
+
+def test_clocks_per_valu_instruction(tmp_path):
+    # pmcsum: shader clock = GRBM_GUI_ACTIVE / 8 XCDs over the dispatch time,
+    # SIMD clocks per VALU instruction = 1024 SIMDs x those clocks / SQ_INSTS_VALU,
+    # both averaged over the kernel's dispatches (counters summed per dispatch)
+    import sqlite3
+
+    from paper_2602_12098_amd import pmcsum
+    db = tmp_path / "run_results.db"
+    con = sqlite3.connect(db)
+    con.execute("create table counters_collection (kernel_name text, dispatch_id int, counter_name text, "
+                "value real, duration real)")
+    rows = []
+    for did, (cycles, valu) in enumerate([(2.0e6, 5.12e8), (2.4e6, 6.144e8)]):
+        dur_ns = 1.0e6   # 1 ms
+        for xcd in range(8):   # GRBM_GUI_ACTIVE is read per XCD and summed
+            rows.append(("k_x<16>", did, "GRBM_GUI_ACTIVE", cycles, dur_ns))
+        rows.append(("k_x<16>", did, "SQ_INSTS_VALU", valu, dur_ns))
+        rows.append(("k_other", did, "SQ_INSTS_VALU", 1.0, dur_ns))
+    con.executemany("insert into counters_collection values (?, ?, ?, ?, ?)", rows)
+    con.commit()
+    con.close()
+    ghz, cpi, valu, n, dur = pmcsum.clocks_per_valu(str(db), r"k_x")
+    assert n == 2 and abs(dur - 1e-3) < 1e-15
+    assert abs(ghz - 2.2) < 1e-12                       # mean cycles 2.2e6 over 1 ms
+    assert abs(valu - 5.632e8) < 1e-3
+    assert abs(cpi - 1024 * 2.2e6 / 5.632e8) < 1e-12    # = 4.0
