@@ -394,6 +394,7 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     __shared__ float s_nlinv[kWV][N];
     __shared__ float s_wdiag[kWV][N];
     __shared__ uint8_t s_perm[kWV][N];
+    __shared__ float2 s_x[kWV][N];   // each vector's symbols, user order
 
     constexpr int NP = VP_PACKED(N);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -406,13 +407,30 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
     const float w00 = Wc[0].x;
     const float tau = taus[sc];
     const bool ok = (w00 > 0.f) && isfinite(w00) && (tau > 0.f) && isfinite(tau);
+    const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride;
+    // every global read of the set-up is issued before any is waited for: the
+    // diagonal and level order, lane t's W row and symbol of user t (the start
+    // residuals are summed from LDS after the barrier, so no read waits on the
+    // level order), and lane t's first path
+    float2 wrow[N];
+    float2 xs = make_float2(0.f, 0.f);
+    float wdg = 1.f;
+    uint8_t pmv = 0;
     if (t < N) {
-        s_wdiag[wv][t] = Wc[vp_pidx(N, t, t)].x;
-        s_nlinv[wv][t] = -(1.0f / s_wdiag[wv][t]);
-        s_perm[wv][t] = perm[(size_t)sc * N + t];
+        wdg = Wc[vp_pidx(N, t, t)].x;
+        pmv = perm[(size_t)sc * N + t];
+        xs = s[(size_t)t * n_vec + v];
+        stilde_row<N>(Wc, t, wrow);
+    }
+    const unsigned long long wd0 = t < K ? load_word<N>(P, t) : 0ull;
+    if (t < N) {
+        s_wdiag[wv][t] = wdg;
+        s_nlinv[wv][t] = -(1.0f / wdg);
+        s_perm[wv][t] = pmv;
+        s_x[wv][t] = xs;
     }
     __syncthreads();
-    if (t < N) s_r0[wv][t] = stilde_over_tau<N>(Wc, s_perm[wv], s, v, n_vec, t, 1.0f / tau);
+    if (t < N) s_r0[wv][t] = stilde_staged<N>(wrow, s_perm[wv], s_x[wv], t, 1.0f / tau);
     __syncthreads();
     if (!live) return;
     if (!ok) {   // failed preprocessing: l = 0, cost = NaN
@@ -423,11 +441,10 @@ __global__ __launch_bounds__(64 * kWV) void k_search_wave(const float2 *__restri
         return;
     }
 
-    const uint8_t *P = paths + ((flags & VP_PATHS_PER_VECTOR) ? v : (size_t)sc) * pstride;
     const float tau2 = tau * tau;
     unsigned long long best = ~0ull;
     for (int k = t; k < K; k += 64) {
-        const unsigned long long wd = load_word<N>(P, k);
+        const unsigned long long wd = k == t ? wd0 : load_word<N>(P, k);
         float2 r[N];
 #pragma unroll
         for (int i = 0; i < N; ++i) r[i] = s_r0[wv][i];
