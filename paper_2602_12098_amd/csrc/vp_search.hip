@@ -202,12 +202,12 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const uint16_t *LX = order + (size_t)sc * 2 * K;        // lexicographic
     const uint16_t *SX = LX + K;                            // deepest level most significant
     // every global read of the set-up is issued here, before the first
-    // barrier: the start residuals (W, perm and s), the table, and both orders
-    // (the deepest-level-first positions t + kTB it are the ones the tier words
+    // barrier, and none waits on another: for the start residuals, thread
+    // (h, i) (vector h, level i) reads W row i and user i's symbol of vector h,
+    // and the sum over the permuted symbols is formed from LDS after the
+    // barrier; then the level order, the table and both orders (the
+    // deepest-level-first positions t + kTB it are the ones the tier words
     // below take, kept in registers)
-    // start residuals, thread (h, i) for vector h, level i: its W row and
-    // user i's symbol of vector h are read here, the sum over the permuted
-    // symbols is formed after the barrier from LDS (no read waits on perm)
     const int h0 = t / kTT, i0 = t % kTT;
     const bool r0_thread = i0 < N && h0 < nlive;
     float2 wrow[N];
