@@ -176,7 +176,10 @@ int vp_paths_mop(const float *w2, int n_sc, int n_r, int K, uint8_t *paths, uint
  *  order    [n_sc][2][K] or NULL: the tables' two orders as written by
  *           vp_paths_mop (requires paths_sc_stride == K*N).  With them, the
  *           work of each distinct prefix of the first N/4 levels is done once
- *           per vector instead of once per path; results are identical.
+ *           per vector instead of once per path; results are identical.  A
+ *           table whose prefix-sharing state (about 14 K bytes plus 24 KiB at
+ *           N = 16) exceeds the LDS one workgroup may hold is searched per
+ *           path instead, with the same results.
  *  l        [N][n_vec][2] output int8 (re, im) in {-1, 0, 1}, user order
  *  cost     [n_vec] output
  *  kidx     [n_vec] output, selected path (K = zero perturbation)

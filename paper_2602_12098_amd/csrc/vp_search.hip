@@ -561,17 +561,36 @@ __global__ __launch_bounds__(kT) void k_fallback_merge(const float2 *__restrict_
     kidx_io[v] = kidx_base + k;
 }
 
+// Static LDS of a kernel (0 if the runtime cannot tell).
+template <typename Kern>
+size_t static_lds_bytes(Kern *kernel) {
+    hipFuncAttributes a{};
+    return hipFuncGetAttributes(&a, (const void *)kernel) == hipSuccess ? a.sharedSizeBytes : 0;
+}
+
+// LDS one workgroup may hold on the current device (0 if unknown).
+inline size_t max_lds_per_block() {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return 0;
+    return (size_t)v;
+}
+
 // The search kernel for a table shape: prefix sharing with orders, one wave
-// per vector for short tables, else one workgroup per vector.
+// per vector for short tables, else one workgroup per vector.  A table too
+// large for the prefix-sharing kernel's LDS (static plus K-sized dynamic part
+// beyond what a workgroup may hold) takes the per-path kernels, which give
+// the same results.
 template <int N, bool MASKED, bool RLUT>
 void launch_search_kernel(const float2 *W, const uint8_t *perm, const float2 *s, const float *tau, const uint8_t *paths,
                           const uint16_t *order, int K, int64_t pstride, int n_sc, int n_sym, uint32_t flags,
                           VecMask mask, float *cost, int32_t *kidx, hipStream_t st) {
     const size_t n_vec = (size_t)n_sc * n_sym;
-    if (order) {
-        const size_t smem = trie_lds_bytes(K);
-        static const bool lds_ok = allow_dynamic_lds(k_search_trie<N, MASKED, RLUT>, 64 * 1024);
-        (void)lds_ok;
+    constexpr size_t kDynMax = 64 * 1024;
+    static const bool lds_ok = allow_dynamic_lds(k_search_trie<N, MASKED, RLUT>, kDynMax);
+    static const size_t trie_static = static_lds_bytes(k_search_trie<N, MASKED, RLUT>);
+    const size_t smem = trie_lds_bytes(K);
+    if (order && lds_ok && smem <= kDynMax && trie_static + smem <= max_lds_per_block()) {
         const unsigned blocks = (unsigned)n_sc * (unsigned)((n_sym + kVPB - 1) / kVPB);
         hipLaunchKernelGGL((k_search_trie<N, MASKED, RLUT>), dim3(blocks), dim3(kTB), smem, st, W, perm, s, tau, paths,
                            order, K, (long long)pstride, n_sym, n_vec, flags, cost, kidx, mask);

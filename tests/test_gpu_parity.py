@@ -576,13 +576,16 @@ def test_prefix_sharing_is_bit_identical(vp, N, K):
 
 
 @pytest.mark.parametrize("N,K,hi,n_sym", [(16, 512, 9, 5), (16, 300, 9, 5), (8, 512, 3, 5), (5, 200, 9, 5),
-                                           (16, 512, 2, 5), (16, 512, 9, 1), (16, 512, 2, 2), (7, 64, 9, 1)])
+                                           (16, 512, 2, 5), (16, 512, 9, 1), (16, 512, 2, 2), (7, 64, 9, 1),
+                                           (16, 2048, 9, 3), (16, 4096, 3, 3)])
 def test_trie_search_any_table_is_bit_identical(vp, N, K, hi, n_sym):
     # arbitrary per-subcarrier tables (random ranks, duplicates allowed) with
     # their two orders: the prefix-sharing search must equal the plain
     # per-path search bit for bit, also with many distinct prefixes (done in
     # chunks), with repeated paths, and with one or two symbols per subcarrier
-    # (a workgroup takes two vectors of a subcarrier)
+    # (a workgroup takes two vectors of a subcarrier); K up to the 4096 limit,
+    # where the prefix-sharing kernel's LDS may exceed a workgroup's and the
+    # per-path kernel serves the call
     rng = np.random.default_rng(N * 1000 + K + hi + 17 * n_sym)
     n_sc = 6
     H = vpgen.draw_rayleigh(rng, n_sc, N, N)
