@@ -179,22 +179,43 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const int sc = (int)(blk / slots);
     const int t = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
-    const size_t vbase = (size_t)sc * n_sym + (size_t)(blk % slots) * kVPB;   // the workgroup's first vector
-    const int nlive = min(kVPB, n_sym - (int)(blk % slots) * kVPB);          // live vectors of this workgroup
-    // masked search: the live vectors it serves (the same in every thread)
-    bool on0 = true, on1 = nlive > 1;
+    // the workgroup's vectors: symbols 2 j and 2 j + 1 of its subcarrier
+    // (j = blk mod slots); in a masked search of up to 64 symbols per
+    // subcarrier, the j-th pair of the subcarrier's served symbols instead, so
+    // that served vectors are not left paired with skipped ones (a workgroup
+    // left without a pair returns at once)
+    const int j_pair = (int)(blk % slots);
+    int sym0 = j_pair * kVPB, sym1 = sym0 + 1;
+    int nlive = min(kVPB, n_sym - sym0);   // live vectors of this workgroup
+    bool on0 = true, on1 = nlive > 1;      // the live vectors it serves (the same in every thread)
     if (MASKED) {
-        on0 = mask.on(vbase);
-        on1 = nlive > 1 && mask.on(vbase + 1);
-        if (!on0 && !on1) return;
+        if (n_sym <= 64) {
+            const int lane = t & 63;
+            const bool f = lane < n_sym && mask.on((size_t)sc * n_sym + lane);
+            unsigned long long bal = __ballot(f);   // every wave forms the same word
+            const int nf = __popcll(bal);
+            if (kVPB * j_pair >= nf) return;
+            nlive = min(kVPB, nf - kVPB * j_pair);
+            for (int q = 0; q < kVPB * j_pair; ++q) bal &= bal - 1ull;   // drop the pairs before this one
+            sym0 = __builtin_ctzll(bal);
+            bal &= bal - 1ull;
+            sym1 = nlive > 1 ? __builtin_ctzll(bal) : sym0;
+            on1 = nlive > 1;
+        } else {
+            on0 = mask.on((size_t)sc * n_sym + sym0);
+            on1 = nlive > 1 && mask.on((size_t)sc * n_sym + sym1);
+            if (!on0 && !on1) return;
+        }
     }
+    const size_t vsel0 = (size_t)sc * n_sym + sym0, vsel1 = (size_t)sc * n_sym + (nlive > 1 ? sym1 : sym0);
+    auto vsel = [&](int h) { return h == 0 ? vsel0 : vsel1; };   // a select, not an indexed array
     const float2 *__restrict__ Wc = W + (size_t)sc * NP;
     const float w00 = Wc[0].x;
     const float tau = taus[sc];
     if (!(w00 > 0.f) || !isfinite(w00) || !(tau > 0.f) || !isfinite(tau)) {   // failed subcarrier (all its vectors)
         if (t < nlive && (t == 0 ? on0 : on1)) {
-            cost_out[vbase + t] = __int_as_float(0x7fc00000);
-            kidx_out[vbase + t] = -1;
+            cost_out[vsel(t)] = __int_as_float(0x7fc00000);
+            kidx_out[vsel(t)] = -1;
         }
         return;
     }
@@ -212,7 +233,7 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     const bool r0_thread = i0 < N && h0 < nlive;
     float2 wrow[N];
     if (r0_thread) {
-        s_x[h0 * N + i0] = s[(size_t)i0 * n_vec + vbase + h0];
+        s_x[h0 * N + i0] = s[(size_t)i0 * n_vec + vsel(h0)];
         stilde_row<N>(Wc, i0, wrow);
     }
     if (t < N) {
@@ -370,8 +391,8 @@ __global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(kTrieWaves)
     if (t < kVPB && hv_on) {
         unsigned long long b = s_red[0][t];
         for (int w = 1; w < kTB / 64; ++w) b = umin64(b, s_red[w][t]);
-        cost_out[vbase + t] = __uint_as_float((unsigned)(b >> 32));
-        kidx_out[vbase + t] = (int32_t)(b & 0xffffffffull);
+        cost_out[vsel(t)] = __uint_as_float((unsigned)(b >> 32));
+        kidx_out[vsel(t)] = (int32_t)(b & 0xffffffffull);
     }
 }
 

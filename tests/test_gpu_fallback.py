@@ -38,14 +38,19 @@ def _proposal_tables(rng, n_vec, K, N):
     return t
 
 
-@pytest.mark.parametrize("K_fix,use_order,theta", [(128, True, 0.5), (128, False, 0.5), (300, False, 0.3),
-                                                   (512, True, 0.7), (512, True, float("inf"))])
-def test_fallback_matches_restricted_fixed_search(lib, K_fix, use_order, theta):
+@pytest.mark.parametrize("K_fix,use_order,theta,n_sc,n_sym", [(128, True, 0.5, 10, 5), (128, False, 0.5, 10, 5),
+                                                               (300, False, 0.3, 10, 5), (512, True, 0.7, 10, 5),
+                                                               (512, True, float("inf"), 10, 5),
+                                                               (512, True, 0.5, 10, 14), (512, True, 0.5, 2, 71)])
+def test_fallback_matches_restricted_fixed_search(lib, K_fix, use_order, theta, n_sc, n_sym):
+    # with orders, a workgroup of the prefix-sharing kernel takes the j-th pair
+    # of its subcarrier's flagged vectors (up to 64 symbols per subcarrier;
+    # beyond, the symbols 2 j and 2 j + 1 with those not flagged skipped)
     vp, learn = lib
-    wl = vpgen.make("16x16-rzf-256qam-rho0.5", 16, 16, 10, 5, 256, 0.16, K_fix, seed=41, rho=0.5)
+    wl = vpgen.make("16x16-rzf-256qam-rho0.5", 16, 16, n_sc, n_sym, 256, 0.16, K_fix, seed=41, rho=0.5)
     N, n_sym, n_vec = wl.N, wl.n_sym, wl.n_vec
     rng = np.random.default_rng(K_fix)
-    print(f"fallback case K={K_fix} order={use_order} theta={theta}", flush=True)
+    print(f"fallback case K={K_fix} order={use_order} theta={theta} n_sc={n_sc} n_sym={n_sym}", flush=True)
     H = torch.from_numpy(wl.H).to(DEV)
     s = torch.from_numpy(wl.s).to(DEV)
     prep = vp.preprocess(H, wl.alpha)
