@@ -122,3 +122,22 @@ def test_clocks_per_valu_instruction(tmp_path):
     assert abs(ghz - 2.2) < 1e-12                       # mean cycles 2.2e6 over 1 ms
     assert abs(valu - 5.632e8) < 1e-3
     assert abs(cpi - 1024 * 2.2e6 / 5.632e8) < 1e-12    # = 4.0
+
+
+def test_fma_stream_reference_builds(tmp_path):
+    # the issue-rate reference of the VALU counters compiles for gfx950 (hipcc
+    # cross-compiles without a GPU) and its loop is plain v_fmac_f32, no packed FP32
+    import shutil
+    import subprocess
+
+    if shutil.which("hipcc") is None and not os.path.exists("/opt/rocm/bin/hipcc"):
+        pytest.skip("no hipcc")
+    from paper_2602_12098_amd import valuref
+    exe = valuref.build(str(tmp_path))
+    assert os.path.exists(exe)
+    asm = tmp_path / "fma_stream.s"
+    subprocess.run(["hipcc", "-O3", "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang",
+                    "-packed-fp32-ops", "--offload-device-only", "-S", "-o", str(asm),
+                    str(tmp_path / "fma_stream.hip")], check=True, capture_output=True)
+    text = asm.read_text()
+    assert text.count("v_fmac_f32") >= 24 and "v_pk_fma_f32" not in text
