@@ -46,7 +46,7 @@ def search_cm_per_vector(n_t, K):
 
 SEARCH_SOURCES = ["paper_2602_12098_amd/csrc/vp_search.hip", "paper_2602_12098_amd/csrc/vp_walk.hpp",
                   "paper_2602_12098_amd/csrc/vp_device.hpp", "paper_2602_12098_amd/csrc/demap_lut.h",
-                  "paper_2602_12098_amd/csrc/region_lut.h"]
+                  "paper_2602_12098_amd/csrc/region_lut.h", "paper_2602_12098_amd/build.py"]   # build flags too
 TRAFFIC_FILE = "profiles/k_search_trie_16x16_256qam_K512.traffic.json"
 
 
